@@ -1,0 +1,162 @@
+"""ctypes wrapper of the C oracle (libcfx_oracle.so) plus numpy helpers.
+
+Test infrastructure only.  Matrices are row-major float64 numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+
+class _Counters(C.Structure):
+    _fields_ = [("divisions", C.c_int64), ("multiply_subtracts", C.c_int64)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = os.environ.get("CFX_ORACLE_LIB")  # a planted-mistake build, in tests
+        if path is None:
+            path = _build.LIB
+            if not os.path.exists(path):
+                _build.build()
+        L = C.CDLL(path)
+        dp = C.POINTER(C.c_double)
+        i64p = C.POINTER(C.c_int64)
+        i32p = C.POINTER(C.c_int32)
+        L.oracle_tslu.argtypes = [C.c_int64, C.c_int64, dp, C.c_int64, C.c_int64,
+                                  C.c_int64, i64p, dp]
+        L.oracle_tslu.restype = C.c_int
+        L.oracle_getrf.argtypes = [C.c_int64, dp, C.c_int64, C.c_int64, C.c_int64,
+                                   i32p, i32p, dp, C.c_int64, C.POINTER(_Counters)]
+        L.oracle_getrf.restype = C.c_int
+        L.oracle_getrs.argtypes = [C.c_int64, C.c_int64, dp, C.c_int64, i32p, dp, C.c_int64]
+        L.oracle_getrs.restype = C.c_int
+        L.oracle_eta.argtypes = [C.c_int64, dp, C.c_int64, dp, C.c_int64, dp, C.c_int64]
+        L.oracle_eta.restype = C.c_double
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _check(a, dtype):
+    if not (isinstance(a, np.ndarray) and a.dtype == dtype and a.flags.c_contiguous):
+        raise TypeError(f"expected C-contiguous {dtype} array")
+
+
+def tslu(W: np.ndarray, vb: int, L: int, row0: int = 0):
+    """Tournament pivots of one panel W (rows x >= vb): (piv int64[vb], margin)."""
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    rows = W.shape[0]
+    piv = np.zeros(vb, dtype=np.int64)
+    mar = C.c_double(0.0)
+    rc = lib().oracle_tslu(rows, vb, _dp(W), W.shape[1], row0, L,
+                           piv.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(mar))
+    if rc != 0:
+        raise ValueError(f"oracle_tslu rejected argument {-rc}")
+    return piv, mar.value
+
+
+class Factorization:
+    def __init__(self, LU, ipiv, info, margins, counters):
+        self.LU = LU
+        self.ipiv = ipiv
+        self.info = info
+        self.margins = margins
+        self.counters = counters
+
+
+def getrf(A: np.ndarray, v: int, L: int, npanels: int = 0, overwrite: bool = False):
+    """TP(v, L) LU of a square row-major matrix.  Returns a Factorization."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    if not overwrite:
+        A = A.copy()
+    n = A.shape[0]
+    assert A.shape == (n, n)
+    ipiv = np.zeros(max(n, 1), dtype=np.int32)
+    info = C.c_int32(0)
+    npan = (n + v - 1) // v if (n > 0 and v > 0) else 0
+    margins = np.ones(max(npan, 1), dtype=np.float64)
+    cnt = _Counters()
+    rc = lib().oracle_getrf(n, _dp(A), max(n, 1), v, L,
+                            ipiv.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(info),
+                            _dp(margins), npanels, C.byref(cnt))
+    if rc != 0:
+        raise ValueError(f"oracle_getrf rejected argument {-rc}")
+    return Factorization(A, ipiv[:n], info.value, margins[:npan],
+                         (cnt.divisions, cnt.multiply_subtracts))
+
+
+def getrs(LU: np.ndarray, ipiv: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """Solve with oracle factors; B is (n,) or (n, nrhs); returns X (new array)."""
+    LU = np.ascontiguousarray(LU, dtype=np.float64)
+    ipiv = np.ascontiguousarray(ipiv, dtype=np.int32)
+    vec = B.ndim == 1
+    X = np.array(B, dtype=np.float64, copy=True, order="C")
+    if vec:
+        X = X[:, None].copy()
+    n, nrhs = X.shape
+    rc = lib().oracle_getrs(n, nrhs, _dp(LU), max(n, 1),
+                            ipiv.ctypes.data_as(C.POINTER(C.c_int32)), _dp(X), max(nrhs, 1))
+    if rc != 0:
+        raise ValueError(f"oracle_getrs rejected argument {-rc}")
+    return X[:, 0] if vec else X
+
+
+def eta(A: np.ndarray, x: np.ndarray, b: np.ndarray) -> float:
+    """Normwise backward error max over columns of ||b-Ax||_inf/(||A|| ||x|| + ||b||)."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    X = np.ascontiguousarray(x, dtype=np.float64)
+    Bm = np.ascontiguousarray(b, dtype=np.float64)
+    if X.ndim == 1:
+        X = X[:, None]
+        Bm = Bm[:, None]
+    n, nrhs = X.shape
+    worst = 0.0
+    for c in range(nrhs):
+        xc = np.ascontiguousarray(X[:, c])
+        bc = np.ascontiguousarray(Bm[:, c])
+        e = lib().oracle_eta(n, _dp(A), A.shape[1], _dp(xc), 1, _dp(bc), 1)
+        worst = max(worst, e)
+    return worst
+
+
+# --------------------------------------------------------------------------
+# Permutation helpers (plain definitions used by tests)
+# --------------------------------------------------------------------------
+
+def ipiv_to_perm(ipiv: np.ndarray) -> np.ndarray:
+    """perm such that (P A)[i] = A[perm[i]] for the interchanges in ipiv."""
+    n = len(ipiv)
+    perm = np.arange(n)
+    for i in range(n):
+        r = int(ipiv[i])
+        perm[i], perm[r] = perm[r], perm[i]
+    return perm
+
+
+def unpack(LU: np.ndarray):
+    n = LU.shape[0]
+    L = np.tril(LU, -1) + np.eye(n)
+    U = np.triu(LU)
+    return L, U
+
+
+def lu_residual(A0: np.ndarray, LU: np.ndarray, ipiv: np.ndarray) -> float:
+    """||P A - L U||_F / ||A||_F (numpy matmul)."""
+    L, U = unpack(LU)
+    PA = A0[ipiv_to_perm(ipiv)]
+    return float(np.linalg.norm(PA - L @ U) / np.linalg.norm(A0))
+
+
+def ipiv_sign(ipiv: np.ndarray) -> int:
+    return -1 if int(np.sum(ipiv != np.arange(len(ipiv)))) % 2 else 1
