@@ -1,0 +1,130 @@
+/*
+ * cfx.h -- C ABI of an MI355X (gfx950) library for dense LU factorisation
+ * with tournament pivoting, after COnfLUX (Kwasniewski et al., "On the
+ * Parallel I/O Optimality of Linear Algebra Kernels: Near-Optimal LU
+ * Factorization", arXiv 2010.05975).
+ *
+ * The problem (Sec. 2.2, Fig. 1, and Sec. 6 statements S1/S2): overwrite a
+ * dense n x n matrix A in place with its factors, A = P L U, L unit lower
+ * triangular (stored strictly below the diagonal), U upper triangular.  The
+ * factorisation is blocked with panel width v (Alg. 1); each panel's v pivot
+ * rows are chosen by tournament pivoting (Sec. 7.3): every leaf of L leaves
+ * selects v candidate rows by Gaussian elimination with partial pivoting,
+ * and a binary reduction tree of "playoff" rounds keeps v winners per node
+ * (Sec. 7.4, Step 1).  FactorizeA10 and FactorizeA01 are the two triangular
+ * solves and FactorizeA11 the Schur-complement update (Sec. 7.2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Matrices are ROW-MAJOR FP64 with a row stride (lda >= number of
+ *    columns), 0-based indices.
+ *  - Pointers named A, B, X, ipiv, info, work are DEVICE pointers (memory
+ *    from hipMalloc or a PyTorch CUDA tensor) unless stated otherwise.  The
+ *    caller owns all of them; the library never frees or keeps them beyond
+ *    the call, and never allocates device memory outside the handle.
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *    Calls are asynchronous on it unless stated otherwise.
+ *  - Return value: CFX_OK (0), -i when argument i (1-based) is invalid,
+ *    or one of the named negative codes below.  Numerical singularity is
+ *    reported through `info`, never through the return value.  No call
+ *    throws across the ABI.
+ *  - A handle is not thread-safe: serialise calls on one handle.
+ */
+#ifndef CFX_H
+#define CFX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    CFX_OK = 0,
+    CFX_PENDING = 1,          /* serving: result not ready yet             */
+    CFX_ENOMEM = -1001,       /* workspace or arena too small              */
+    CFX_EHIP = -1002,         /* a HIP runtime call failed                 */
+    CFX_EBUSY = -1003,        /* serving: queue full                       */
+    CFX_ENOTSUP = -1004,      /* shape outside the supported range         */
+};
+
+enum {
+    CFX_PREC_FP64 = 0,        /* every step in FP64                        */
+    CFX_PREC_BF16 = 1,        /* Schur update with BF16 operands, FP32 acc */
+    CFX_PREC_FP16 = 2,        /* Schur update with FP16 operands, FP32 acc */
+};
+
+/* Options of the tournament-pivoted LU.
+ *   v         : panel width (Alg. 1 blocking parameter v), 1..256.
+ *   leaves    : leaf count L of the tournament; a panel with r rows left has
+ *               leaves of h = max(v, ceil(r / L)) rows (the last one may be
+ *               shorter).  h must not exceed 8192 rows.
+ *   precision : CFX_PREC_*; the pivot search, row interchanges and both
+ *               triangular solves are always FP64.
+ *   lookahead : 0 or 1; 1 overlaps the next panel's tournament with the
+ *               rest of the current Schur update on a second stream. */
+typedef struct {
+    int32_t v;
+    int32_t leaves;
+    int32_t precision;
+    int32_t lookahead;
+} cfx_lu_opts;
+
+typedef struct cfx_handle cfx_handle;
+
+/* Create / destroy a handle on the current HIP device.  The handle owns a
+ * second stream and a few events (for lookahead); nothing else. */
+int cfx_create(cfx_handle **h);
+int cfx_destroy(cfx_handle *h);
+
+/* Static description of the library build (host memory, NUL-terminated). */
+const char *cfx_version(void);
+
+/* Workspace bytes cfx_getrf needs for an n x n matrix with these options.
+ * `bytes` is a host pointer. */
+int cfx_getrf_buffer_size(cfx_handle *h, int64_t n, const cfx_lu_opts *opts,
+                          size_t *bytes);
+
+/* Blocked right-looking LU with tournament pivoting, A = P L U (Alg. 1,
+ * compute steps TournPivot, FactorizeA10, FactorizeA01, FactorizeA11; the
+ * pivot rows are interchanged explicitly rather than masked).
+ *   n     : order of A, n >= 0.
+ *   A     : device, n x n row-major, stride lda >= max(1, n); overwritten by
+ *           L (strictly below the diagonal, unit diagonal implicit) and U.
+ *   ipiv  : device int32[n]: row i was interchanged with row ipiv[i] >= i,
+ *           interchanges applied in order i = 0 .. n-1 (LAPACK style, 0-based).
+ *   info  : device int32: 0, or j+1 for the first exactly zero U[j][j]
+ *           (the factorisation continues; that column of L is left unscaled).
+ *   opts  : host pointer, see cfx_lu_opts.
+ *   work  : device workspace of at least cfx_getrf_buffer_size bytes,
+ *           256-byte aligned.
+ * Asynchronous on `stream`. */
+int cfx_getrf(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *ipiv,
+              int32_t *info, const cfx_lu_opts *opts, void *work,
+              size_t work_bytes, void *stream);
+
+/* Tournament pivot selection of one panel (Sec. 7.3; Sec. 7.4 Step 1): the
+ * panel is W = rows x vb at device pointer W with stride ldw; row i of W is
+ * global row row0 + i.  Writes the vb selected global rows, in selection
+ * order, to the device int32 array piv.  W is not modified.  `leaves` as in
+ * cfx_lu_opts.  work as for cfx_getrf with n = rows, v = vb.
+ * Asynchronous on `stream`. */
+int cfx_tslu(cfx_handle *h, int64_t rows, int64_t vb, const double *W,
+             int64_t ldw, int64_t row0, int32_t leaves, int32_t *piv,
+             void *work, size_t work_bytes, void *stream);
+
+/* Solve A X = B with the factors of cfx_getrf: apply the interchanges of
+ * ipiv to B in order, forward substitution with unit L, back substitution
+ * with U.
+ *   LU   : device, n x n factors, stride lda.
+ *   B    : device, n x nrhs row-major, stride ldb >= nrhs; overwritten by X.
+ * Asynchronous on `stream`. */
+int cfx_getrs(cfx_handle *h, int64_t n, int64_t nrhs, const double *LU,
+              int64_t lda, const int32_t *ipiv, double *B, int64_t ldb,
+              void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CFX_H */

@@ -1,0 +1,172 @@
+"""Thin ctypes binding of libcfx.so (include/cfx.h).
+
+Each function marshals PyTorch CUDA tensors (row-major, FP64) into the C ABI
+call of the same name and raises on a non-zero status.  No computation
+happens here; if libcfx.so is missing the call raises instead of falling
+back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcfx.so")
+
+PREC = {"fp64": 0, "bf16": 1, "fp16": 2}
+STATUS = {0: "CFX_OK", 1: "CFX_PENDING", -1001: "CFX_ENOMEM", -1002: "CFX_EHIP",
+          -1003: "CFX_EBUSY", -1004: "CFX_ENOTSUP"}
+
+_lib = None
+
+
+class LuOpts(C.Structure):
+    _fields_ = [("v", C.c_int32), ("leaves", C.c_int32), ("precision", C.c_int32),
+                ("lookahead", C.c_int32)]
+
+
+class CfxError(RuntimeError):
+    def __init__(self, fn, code):
+        self.code = code
+        what = STATUS.get(code, f"invalid argument {-code}" if code < 0 else str(code))
+        super().__init__(f"{fn} failed: {what} ({code})")
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                               "or python -m paper_2010_05975_amd.build")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
+        sz = C.c_size_t
+        L.cfx_version.restype = C.c_char_p
+        L.cfx_create.argtypes = [C.POINTER(vp)]
+        L.cfx_destroy.argtypes = [vp]
+        L.cfx_getrf_buffer_size.argtypes = [vp, i64, C.POINTER(LuOpts), C.POINTER(sz)]
+        L.cfx_getrf.argtypes = [vp, i64, vp, i64, vp, vp, C.POINTER(LuOpts), vp, sz, vp]
+        L.cfx_tslu.argtypes = [vp, i64, i64, vp, i64, i64, i32, vp, vp, sz, vp]
+        L.cfx_getrs.argtypes = [vp, i64, i64, vp, i64, vp, vp, i64, vp]
+        for f in ("cfx_create", "cfx_destroy", "cfx_getrf_buffer_size", "cfx_getrf",
+                  "cfx_tslu", "cfx_getrs"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(fn, rc):
+    if rc != 0:
+        raise CfxError(fn, rc)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else C.c_void_p(0)
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _mat(A, name):
+    if A.device.type != "cuda" or A.dtype != torch.float64 or A.dim() != 2:
+        raise TypeError(f"{name} must be a 2-D float64 CUDA tensor")
+    if A.stride(1) != 1:
+        raise TypeError(f"{name} must be row-major (unit column stride)")
+    return max(A.stride(0), A.shape[1], 1)
+
+
+class Handle:
+    """Owns a cfx_handle (create/destroy) on the current device."""
+
+    def __init__(self):
+        h = C.c_void_p()
+        _check("cfx_create", lib().cfx_create(C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            lib().cfx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default = {}
+
+
+def default_handle() -> Handle:
+    dev = torch.cuda.current_device()
+    if dev not in _default:
+        _default[dev] = Handle()
+    return _default[dev]
+
+
+def version() -> str:
+    return lib().cfx_version().decode()
+
+
+def getrf_buffer_size(n, v=256, leaves=64, precision="fp64", lookahead=0, handle=None):
+    h = handle or default_handle()
+    o = LuOpts(v, leaves, PREC[precision], lookahead)
+    b = C.c_size_t()
+    _check("cfx_getrf_buffer_size", lib().cfx_getrf_buffer_size(h.h, n, C.byref(o), C.byref(b)))
+    return b.value
+
+
+def workspace(n, v=256, leaves=64, precision="fp64", lookahead=0, device=None, handle=None):
+    nbytes = getrf_buffer_size(n, v, leaves, precision, lookahead, handle)
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device or "cuda")
+
+
+def getrf(A, v=256, leaves=64, precision="fp64", lookahead=0, work=None, ipiv=None, info=None,
+          stream=None, handle=None):
+    """cfx_getrf: factor A in place; returns (ipiv int32[n], info int32[1])."""
+    h = handle or default_handle()
+    lda = _mat(A, "A")
+    n = A.shape[0]
+    if A.shape[1] != n:
+        raise ValueError("A must be square")
+    if ipiv is None:
+        ipiv = torch.empty(max(n, 1), dtype=torch.int32, device=A.device)
+    if info is None:
+        info = torch.empty(1, dtype=torch.int32, device=A.device)
+    if work is None:
+        work = workspace(n, v, leaves, precision, lookahead, A.device, h)
+    o = LuOpts(v, leaves, PREC[precision], lookahead)
+    _check("cfx_getrf", lib().cfx_getrf(h.h, n, _ptr(A), lda, _ptr(ipiv), _ptr(info), C.byref(o),
+                                        _ptr(work), work.numel(), _stream(stream)))
+    return ipiv[:n], info
+
+
+def tslu(W, vb, leaves, row0=0, work=None, stream=None, handle=None):
+    """cfx_tslu: tournament pivots of the panel W[:, :vb]; returns int32[vb]."""
+    h = handle or default_handle()
+    ldw = _mat(W, "W")
+    rows = W.shape[0]
+    piv = torch.empty(vb, dtype=torch.int32, device=W.device)
+    if work is None:
+        work = workspace(rows, vb, leaves, "fp64", 0, W.device, h)
+    _check("cfx_tslu", lib().cfx_tslu(h.h, rows, vb, _ptr(W), ldw, row0, leaves, _ptr(piv),
+                                      _ptr(work), work.numel(), _stream(stream)))
+    return piv
+
+
+def getrs(LU, ipiv, B, stream=None, handle=None):
+    """cfx_getrs: solve in place in B (n x nrhs, or n) with the factors of getrf."""
+    h = handle or default_handle()
+    lda = _mat(LU, "LU")
+    vec = B.dim() == 1
+    Bm = B.view(-1, 1) if vec else B
+    ldb = _mat(Bm, "B")
+    n, nrhs = Bm.shape
+    _check("cfx_getrs", lib().cfx_getrs(h.h, n, nrhs, _ptr(LU), lda, _ptr(ipiv), _ptr(Bm), ldb,
+                                        _stream(stream)))
+    return B

@@ -1,0 +1,152 @@
+// Schur-complement update A22 -= L21 U12 (FactorizeA11 of Alg. 1, the
+// statement S2 of Sec. 6 that carries the leading 2N^3/3 flops) on the FP64
+// matrix cores of gfx950.
+//
+// A workgroup of 4 wavefronts owns a 128 x 128 tile of C; each wavefront a
+// 64 x 64 sub-tile held as 4 x 4 accumulators of v_mfma_f64_16x16x4f64.
+// The K = vb reduction is staged through LDS in chunks of 16, double
+// buffered: the next chunk is fetched into registers while the current one
+// feeds the matrix cores.  Both operand tiles are stored k-major in LDS so
+// that the 16 lanes of an MFMA operand row read 16 consecutive doubles.
+// C is read and written once, in the epilogue.
+//
+// Tiles are mapped XCD-aware: consecutive workgroup ids land on different
+// XCDs (each with its own L2), so ids are regrouped to give each XCD a
+// contiguous, row-grouped range of tiles that share L21 and U12 strips.
+#include "cfx_internal.h"
+
+namespace cfx {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 128, BN = 128, BK = 16;
+constexpr int LDA_S = BM + 16;   // padded k-major rows of the L tile
+constexpr int LDB_S = BN + 16;
+constexpr int GROUP_M = 8;
+constexpr int NXCD = 8;
+
+__device__ __forceinline__ void tile_of(int bid, int nb, int tm, int tn, int &ti, int &tj)
+{
+    // XCD regrouping: hardware sends id b to XCD b % 8.
+    const int per = nb / NXCD;
+    int t = bid;
+    if (bid < per * NXCD) t = (bid % NXCD) * per + bid / NXCD;
+    // grouped row-major order inside the range
+    const int group = t / (GROUP_M * tn);
+    const int first = group * GROUP_M;
+    const int gsz = (tm - first) < GROUP_M ? (tm - first) : GROUP_M;
+    const int r = t - group * GROUP_M * tn;
+    ti = first + r % gsz;
+    tj = r / gsz;
+}
+
+__global__ __launch_bounds__(256, 2) void schur_f64_kernel(const double *__restrict__ L, int64_t ldl,
+                                                           const double *__restrict__ U, int64_t ldu,
+                                                           double *__restrict__ C, int64_t ldc,
+                                                           int64_t mr, int64_t nc, int K, int tm, int tn)
+{
+    __shared__ double As[2][BK * LDA_S];
+    __shared__ double Bs[2][BK * LDB_S];
+
+    int ti, tj;
+    tile_of(blockIdx.x, gridDim.x, tm, tn, ti, tj);
+    const int64_t i0 = (int64_t)ti * BM, j0 = (int64_t)tj * BN;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
+    const int lr = lane & 15, lk = lane >> 4;
+
+    // global -> register staging assignment
+    const int a_row = tid >> 1, a_col = (tid & 1) * 8;     // L tile: 128 rows x 16
+    const int b_row = tid >> 4, b_col = (tid & 15) * 8;    // U tile: 16 rows x 128
+    double ra[8], rb[8];
+
+    auto fetch = [&](int kc) {
+        const int k0 = kc * BK;
+        const int64_t gi = i0 + a_row;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int kk = k0 + a_col + q;
+            ra[q] = (gi < mr && kk < K) ? L[gi * ldl + kk] : 0.0;
+        }
+        const int kb = k0 + b_row;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t gj = j0 + b_col + q;
+            rb[q] = (kb < K && gj < nc) ? U[(int64_t)kb * ldu + gj] : 0.0;
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) As[buf][(a_col + q) * LDA_S + a_row] = ra[q];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) Bs[buf][b_row * LDB_S + b_col + q] = rb[q];
+    };
+
+    d4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+
+    const int nk = (K + BK - 1) / BK;
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    for (int kc = 0; kc < nk; ++kc) {
+        const int buf = kc & 1;
+        if (kc + 1 < nk) fetch(kc + 1);
+        const double *as = As[buf];
+        const double *bs = Bs[buf];
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            double af[4], bf[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) af[a] = as[(kk + lk) * LDA_S + wm + a * 16 + lr];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) bf[b] = bs[(kk + lk) * LDB_S + wn + b * 16 + lr];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+        }
+        if (kc + 1 < nk) stash(buf ^ 1);
+        __syncthreads();
+    }
+
+    // epilogue: for v_mfma_f64_16x16x4f64 lane l holds rows l/16 + 4q
+    // (q = 0..3) of column l%16 of each 16 x 16 block
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int64_t gj = j0 + wn + b * 16 + lr;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t gi = i0 + wm + a * 16 + lk + 4 * q;
+                if (gi < mr && gj < nc) {
+                    double *c = C + gi * ldc + gj;
+                    *c = *c - acc[a][b][q];
+                }
+            }
+        }
+}
+
+}  // namespace
+
+int launch_schur_f64(const double *L, int64_t ldl, const double *U, int64_t ldu, double *C,
+                     int64_t ldc, int64_t mr, int64_t nc, int K, hipStream_t st)
+{
+    if (mr <= 0 || nc <= 0 || K <= 0) return CFX_OK;
+    const int tm = (int)((mr + BM - 1) / BM), tn = (int)((nc + BN - 1) / BN);
+    const int64_t nb = (int64_t)tm * tn;
+    hipLaunchKernelGGL(schur_f64_kernel, dim3((unsigned)nb), dim3(256), 0, st, L, ldl, U, ldu, C, ldc,
+                       mr, nc, K, tm, tn);
+    CFX_HIP(hipGetLastError());
+    return CFX_OK;
+}
+
+}  // namespace cfx

@@ -1,0 +1,152 @@
+"""GPU parity of the FP64 tournament-pivoted LU against the CPU oracle.
+
+Every call goes through the C ABI (libcfx.so via the ctypes binding)."""
+import numpy as np
+import pytest
+
+import cfx_inputs as G
+from oracle import oracle as O
+from tests.gpu_util import compare_panels, say, to_dev
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cfx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2010_05975_amd import cfx as m
+    m.lib()
+    return m
+
+
+# ---------------------------------------------------------------------------
+# tournament alone
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("rows,vb,L", [(64, 8, 4), (512, 32, 4), (300, 32, 3), (1000, 16, 7),
+                                       (2048, 64, 8), (4096, 256, 16), (1024, 256, 1),
+                                       (700, 128, 5), (33, 32, 64)])
+def test_tslu_matches_oracle(cfx, rows, vb, L):
+    say(f"tslu rows={rows} vb={vb} L={L}")
+    W = G.normal_matrix(rows, rows + vb)[:, :vb].copy()
+    ref, margin = O.tslu(W, vb, L, row0=5)
+    piv = cfx.tslu(to_dev(W), vb, L, row0=5).cpu().numpy()
+    torch.cuda.synchronize()
+    assert margin > 1e-10
+    assert np.array_equal(piv, ref)
+
+
+def test_tslu_ties_smallest_row(cfx):
+    say("tslu ties")
+    W = G.wilkinson_growth_matrix(96)[:, :32].copy()
+    ref, _ = O.tslu(W, 32, 3)
+    piv = cfx.tslu(to_dev(W), 32, 3).cpu().numpy()
+    assert np.array_equal(piv, ref)
+    assert np.array_equal(piv, np.arange(32))
+
+
+# ---------------------------------------------------------------------------
+# full factorisation
+# ---------------------------------------------------------------------------
+
+def run_getrf(cfx, A, v, L):
+    dA = to_dev(A)
+    ipiv, info = cfx.getrf(dA, v=v, leaves=L)
+    torch.cuda.synchronize()
+    return dA.cpu().numpy(), ipiv.cpu().numpy(), int(info.cpu()[0])
+
+
+def lu_tolerance(ref_LU, n):
+    # forward error of each factor entry: about n * eps * (|L||U|) with
+    # growth; 1e-9 relative to max|U| leaves room for pivot-order rounding.
+    return 1e-9 * max(1.0, float(np.abs(ref_LU).max()))
+
+
+@pytest.mark.parametrize("gen,n,v,L", [
+    ("uniform", 512, 32, 4),     # the small single-matrix case
+    ("normal", 300, 32, 3),      # ragged last panel
+    ("normal", 257, 16, 6),
+    ("uniform", 100, 128, 4),    # n < v
+    ("normal", 1, 32, 4),
+    ("normal", 1024, 64, 8),
+    ("normal", 2048, 256, 4),
+    ("normal", 777, 256, 2),
+])
+def test_getrf_matches_oracle(cfx, gen, n, v, L):
+    say(f"getrf {gen} n={n} v={v} L={L}")
+    A = getattr(G, f"{gen}_matrix")(n, 17)
+    ref = O.getrf(A, v, L)
+    LU, ipiv, info = run_getrf(cfx, A, v, L)
+    assert info == ref.info == 0
+    compared = compare_panels(ipiv, ref.ipiv, ref.margins, v)
+    say(f"  panels compared {compared}/{len(ref.margins)}")
+    assert O.lu_residual(A, LU, ipiv) <= 1e-12
+    if compared == len(ref.margins):
+        np.testing.assert_allclose(LU, ref.LU, rtol=0, atol=lu_tolerance(ref.LU, n))
+
+
+@pytest.mark.parametrize("n,v,L", [(64, 8, 4), (200, 32, 3), (96, 32, 1)])
+def test_getrf_wilkinson_exact(cfx, n, v, L):
+    say(f"wilkinson n={n}")
+    A = G.wilkinson_growth_matrix(n)
+    LU, ipiv, info = run_getrf(cfx, A, v, L)
+    ref = O.getrf(A, v, L)
+    assert np.array_equal(ipiv, np.arange(n))
+    assert np.array_equal(LU, ref.LU)
+
+
+@pytest.mark.parametrize("n,v,L", [(64, 8, 4), (64, 16, 3), (50, 7, 5)])
+def test_getrf_dd_exact(cfx, n, v, L):
+    say(f"dd n={n} v={v}")
+    L0, U0 = G.dyadic_dd_factors(n, 1)
+    A = L0 @ U0
+    LU, ipiv, info = run_getrf(cfx, A, v, L)
+    assert np.array_equal(ipiv, np.arange(n))
+    assert np.array_equal(np.tril(LU, -1) + np.eye(n), L0)
+    assert np.array_equal(np.triu(LU), U0)
+
+
+def test_getrf_zero_column_info(cfx):
+    say("zero column")
+    n = 80
+    A = G.normal_matrix(n, 4)
+    A[:, 37] = 0.0
+    LU, ipiv, info = run_getrf(cfx, A, 16, 3)
+    ref = O.getrf(A, 16, 3)
+    assert info == ref.info == 38
+    assert np.array_equal(ipiv, ref.ipiv)
+    np.testing.assert_allclose(LU, ref.LU, rtol=0, atol=1e-9 * np.abs(ref.LU).max())
+
+
+def test_getrf_empty(cfx):
+    say("empty")
+    A = torch.zeros((0, 0), dtype=torch.float64, device="cuda")
+    ipiv, info = cfx.getrf(A, v=32, leaves=4)
+    torch.cuda.synchronize()
+    assert int(info.cpu()[0]) == 0
+
+
+# ---------------------------------------------------------------------------
+# solve
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,nrhs,v,L", [(512, 1, 32, 4), (300, 5, 32, 3), (1000, 64, 64, 4),
+                                        (600, 1, 256, 2)])
+def test_getrs_matches_oracle(cfx, n, nrhs, v, L):
+    say(f"getrs n={n} nrhs={nrhs}")
+    A = G.normal_matrix(n, 3)
+    B = G.rhs(n, nrhs, 4)
+    ref = O.getrf(A, v, L)
+    Xref = O.getrs(ref.LU, ref.ipiv, B)
+    dA = to_dev(A)
+    ipiv, info = cfx.getrf(dA, v=v, leaves=L)
+    dB = to_dev(B)
+    cfx.getrs(dA, ipiv, dB)
+    X = dB.cpu().numpy()
+    # A direct FP64 solve's backward error is a small multiple of n*u (not the
+    # 5e-15 refinement target); it must stay within 4x of the oracle's own.
+    eta_ref = O.eta(A, Xref, B)
+    assert O.eta(A, X, B) <= max(4 * eta_ref, 1e-15)
+    np.testing.assert_allclose(X, Xref, rtol=1e-8, atol=1e-8 * np.abs(Xref).max())
