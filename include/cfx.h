@@ -124,6 +124,27 @@ int cfx_getrs(cfx_handle *h, int64_t n, int64_t nrhs, const double *LU,
               int64_t lda, const int32_t *ipiv, double *B, int64_t ldb,
               void *stream);
 
+/* Per-phase device time of the factorisation steps, for measurement.
+ * Between cfx_profile_begin and cfx_profile_end every cfx_getrf on the
+ * handle records HIP events around each phase on the stream that runs it.
+ * cfx_profile_end waits for those events (host-blocking), fills `out`
+ * (host pointer) with the summed durations and stops recording.
+ *   schur_flops : algorithmic flops of the Schur updates, 2 * rows * cols * K
+ *                 summed over launches (statement S2 of Sec. 6, twice for
+ *                 the multiply and the subtract). */
+typedef struct {
+    double tslu_ms;       /* TournPivot: leaves and playoff rounds        */
+    double laswp_ms;      /* row interchanges                             */
+    double trsm_ms;       /* FactorizeA10 + FactorizeA01                  */
+    double schur_ms;      /* FactorizeA11                                 */
+    double schur_flops;
+    int64_t schur_launches;
+    int64_t panels;
+} cfx_profile;
+
+int cfx_profile_begin(cfx_handle *h);
+int cfx_profile_end(cfx_handle *h, cfx_profile *out);
+
 #ifdef __cplusplus
 }
 #endif

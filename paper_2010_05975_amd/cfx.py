@@ -27,6 +27,15 @@ class LuOpts(C.Structure):
                 ("lookahead", C.c_int32)]
 
 
+class Profile(C.Structure):
+    _fields_ = [("tslu_ms", C.c_double), ("laswp_ms", C.c_double), ("trsm_ms", C.c_double),
+                ("schur_ms", C.c_double), ("schur_flops", C.c_double),
+                ("schur_launches", C.c_int64), ("panels", C.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class CfxError(RuntimeError):
     def __init__(self, fn, code):
         self.code = code
@@ -50,8 +59,10 @@ def lib():
         L.cfx_getrf.argtypes = [vp, i64, vp, i64, vp, vp, C.POINTER(LuOpts), vp, sz, vp]
         L.cfx_tslu.argtypes = [vp, i64, i64, vp, i64, i64, i32, vp, vp, sz, vp]
         L.cfx_getrs.argtypes = [vp, i64, i64, vp, i64, vp, vp, i64, vp]
+        L.cfx_profile_begin.argtypes = [vp]
+        L.cfx_profile_end.argtypes = [vp, C.POINTER(Profile)]
         for f in ("cfx_create", "cfx_destroy", "cfx_getrf_buffer_size", "cfx_getrf",
-                  "cfx_tslu", "cfx_getrs"):
+                  "cfx_tslu", "cfx_getrs", "cfx_profile_begin", "cfx_profile_end"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -170,3 +181,17 @@ def getrs(LU, ipiv, B, stream=None, handle=None):
     _check("cfx_getrs", lib().cfx_getrs(h.h, n, nrhs, _ptr(LU), lda, _ptr(ipiv), _ptr(Bm), ldb,
                                         _stream(stream)))
     return B
+
+
+def profile_begin(handle=None):
+    """cfx_profile_begin: record per-phase events on subsequent getrf calls."""
+    h = handle or default_handle()
+    _check("cfx_profile_begin", lib().cfx_profile_begin(h.h))
+
+
+def profile_end(handle=None) -> dict:
+    """cfx_profile_end: wait for the recorded events; per-phase milliseconds."""
+    h = handle or default_handle()
+    p = Profile()
+    _check("cfx_profile_end", lib().cfx_profile_end(h.h, C.byref(p)))
+    return p.as_dict()

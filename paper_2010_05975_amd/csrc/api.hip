@@ -2,8 +2,49 @@
 // the host loop over panels of Alg. 1 (TournPivot, interchanges,
 // FactorizeA10/A01, FactorizeA11 per panel).
 #include <new>
+#include <vector>
 
 #include "cfx_internal.h"
+
+namespace cfx {
+enum Phase { PH_TSLU = 0, PH_LASWP, PH_TRSM, PH_SCHUR, PH_COUNT };
+
+// Event-pair recorder behind cfx_profile_begin / cfx_profile_end.
+struct Profiler {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    struct Rec { int phase; hipEvent_t a, b; double flops; };
+    std::vector<Rec> recs;
+    int64_t panels = 0;
+
+    hipEvent_t next()
+    {
+        if (used == pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+    // Returns the begin event (or null when not recording).
+    hipEvent_t begin(hipStream_t st)
+    {
+        if (!on) return nullptr;
+        hipEvent_t e = next();
+        if (e) (void)hipEventRecord(e, st);
+        return e;
+    }
+    void end(int phase, hipEvent_t a, hipStream_t st, double flops = 0.0)
+    {
+        if (!on || !a) return;
+        hipEvent_t e = next();
+        if (!e) return;
+        (void)hipEventRecord(e, st);
+        recs.push_back({phase, a, e, flops});
+    }
+};
+}  // namespace cfx
 
 struct cfx_handle {
     int device = 0;
@@ -12,6 +53,7 @@ struct cfx_handle {
     hipEvent_t ev_tslu = nullptr;   // next panel's tournament done
     void *scratch = nullptr;        // getrs permutation + gather buffer
     size_t scratch_bytes = 0;
+    cfx::Profiler prof;
 };
 
 namespace cfx {
@@ -120,9 +162,49 @@ int cfx_create(cfx_handle **h)
     return CFX_OK;
 }
 
+int cfx_profile_begin(cfx_handle *h)
+{
+    if (!h) return -1;
+    h->prof.on = true;
+    h->prof.used = 0;
+    h->prof.recs.clear();
+    h->prof.panels = 0;
+    return CFX_OK;
+}
+
+int cfx_profile_end(cfx_handle *h, cfx_profile *out)
+{
+    if (!h) return -1;
+    if (!out) return -2;
+    Profiler &pf = h->prof;
+    cfx_profile r{};
+    double ms[PH_COUNT] = {0, 0, 0, 0};
+    for (const auto &rec : pf.recs) {
+        CFX_HIP(hipEventSynchronize(rec.b));
+        float t = 0.f;
+        CFX_HIP(hipEventElapsedTime(&t, rec.a, rec.b));
+        ms[rec.phase] += t;
+        if (rec.phase == PH_SCHUR) {
+            r.schur_flops += rec.flops;
+            ++r.schur_launches;
+        }
+    }
+    r.tslu_ms = ms[PH_TSLU];
+    r.laswp_ms = ms[PH_LASWP];
+    r.trsm_ms = ms[PH_TRSM];
+    r.schur_ms = ms[PH_SCHUR];
+    r.panels = pf.panels;
+    *out = r;
+    pf.on = false;
+    pf.recs.clear();
+    pf.used = 0;
+    return CFX_OK;
+}
+
 int cfx_destroy(cfx_handle *h)
 {
     if (!h) return -1;
+    for (hipEvent_t e : h->prof.pool) (void)hipEventDestroy(e);
     if (h->scratch) (void)hipFree(h->scratch);
     if (h->ev_panel) (void)hipEventDestroy(h->ev_panel);
     if (h->ev_tslu) (void)hipEventDestroy(h->ev_tslu);
@@ -166,18 +248,28 @@ int cfx_getrf(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *ipiv, i
     Workspace ws;
     if ((rc = carve_workspace(work, work_bytes, n, v, L, opts->precision, &ws))) return rc;
 
+    Profiler &pf = h->prof;
     for (int64_t k = 0; k < n; k += v) {
         const int vb = (int)((n - k) < v ? (n - k) : v);
         const int64_t m = n - k - vb;
         double *panel = A + k * lda + k;
+        hipEvent_t e = pf.begin(st);
         if ((rc = launch_tslu(panel, lda, k, n - k, vb, L, ws, nullptr, ipiv, info, st))) return rc;
+        pf.end(PH_TSLU, e, st);
+        e = pf.begin(st);
         if ((rc = launch_laswp(A, lda, n, k, vb, ws, st))) return rc;
+        pf.end(PH_LASWP, e, st);
         if (m > 0) {
+            e = pf.begin(st);
             if ((rc = launch_trsm(A, lda, k, vb, m, st))) return rc;
+            pf.end(PH_TRSM, e, st);
+            e = pf.begin(st);
             if ((rc = launch_schur_f64(panel + vb * lda, lda, panel + vb, lda, panel + vb * lda + vb,
                                        lda, m, m, vb, st)))
                 return rc;
+            pf.end(PH_SCHUR, e, st, 2.0 * (double)m * (double)m * vb);
         }
+        if (pf.on) ++pf.panels;
     }
     return CFX_OK;
 }
