@@ -64,7 +64,7 @@ def main():
     ap.add_argument("--n", type=int, default=32768)
     ap.add_argument("--v", type=int, default=256)
     ap.add_argument("--leaves", type=int, default=64)
-    ap.add_argument("--lookahead", type=int, default=0)
+    ap.add_argument("--lookahead", type=int, default=1)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-panels", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")

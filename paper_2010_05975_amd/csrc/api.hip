@@ -249,28 +249,84 @@ int cfx_getrf(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *ipiv, i
     if ((rc = carve_workspace(work, work_bytes, n, v, L, opts->precision, &ws))) return rc;
 
     Profiler &pf = h->prof;
+    if (!opts->lookahead) {
+        for (int64_t k = 0; k < n; k += v) {
+            const int vb = (int)((n - k) < v ? (n - k) : v);
+            const int64_t m = n - k - vb;
+            double *panel = A + k * lda + k;
+            hipEvent_t e = pf.begin(st);
+            if ((rc = launch_tslu(panel, lda, k, n - k, vb, L, ws, nullptr, ipiv, info, st))) return rc;
+            pf.end(PH_TSLU, e, st);
+            e = pf.begin(st);
+            if ((rc = launch_laswp(A, lda, n, k, vb, ws, st))) return rc;
+            pf.end(PH_LASWP, e, st);
+            if (m > 0) {
+                e = pf.begin(st);
+                if ((rc = launch_trsm(A, lda, k, vb, m, st))) return rc;
+                pf.end(PH_TRSM, e, st);
+                e = pf.begin(st);
+                if ((rc = launch_schur_f64(panel + vb * lda, lda, panel + vb, lda, panel + vb * lda + vb,
+                                           lda, m, m, vb, st)))
+                    return rc;
+                pf.end(PH_SCHUR, e, st, 2.0 * (double)m * (double)m * vb);
+            }
+            if (pf.on) ++pf.panels;
+        }
+        return CFX_OK;
+    }
+
+    // Lookahead (depth 1): the Schur update of panel k is split into the
+    // next panel's columns (A22[:, 0:vb']) and the rest.  The next panel's
+    // tournament only reads those columns, so it runs on the side stream
+    // while the main stream finishes the rest of the update; the next
+    // interchanges wait for both.
+    hipStream_t side = h->side;
+    {
+        const int vb0 = (int)(n < v ? n : v);
+        hipEvent_t e = pf.begin(st);
+        if ((rc = launch_tslu(A, lda, 0, n, vb0, L, ws, nullptr, ipiv, info, st))) return rc;
+        pf.end(PH_TSLU, e, st);
+    }
+    bool tslu_on_side = false;
     for (int64_t k = 0; k < n; k += v) {
         const int vb = (int)((n - k) < v ? (n - k) : v);
         const int64_t m = n - k - vb;
         double *panel = A + k * lda + k;
+        if (tslu_on_side) CFX_HIP(hipStreamWaitEvent(st, h->ev_tslu, 0));
+        tslu_on_side = false;
         hipEvent_t e = pf.begin(st);
-        if ((rc = launch_tslu(panel, lda, k, n - k, vb, L, ws, nullptr, ipiv, info, st))) return rc;
-        pf.end(PH_TSLU, e, st);
-        e = pf.begin(st);
         if ((rc = launch_laswp(A, lda, n, k, vb, ws, st))) return rc;
         pf.end(PH_LASWP, e, st);
         if (m > 0) {
             e = pf.begin(st);
             if ((rc = launch_trsm(A, lda, k, vb, m, st))) return rc;
             pf.end(PH_TRSM, e, st);
+            const int vbn = (int)(m < v ? m : v);          // next panel width
+            double *L21 = panel + vb * lda, *U12 = panel + vb, *C = panel + vb * lda + vb;
             e = pf.begin(st);
-            if ((rc = launch_schur_f64(panel + vb * lda, lda, panel + vb, lda, panel + vb * lda + vb,
-                                       lda, m, m, vb, st)))
+            if ((rc = launch_schur_f64(L21, lda, U12, lda, C, lda, m, vbn, vb, st))) return rc;
+            pf.end(PH_SCHUR, e, st, 2.0 * (double)m * vbn * vb);
+            // next panel's tournament on the side stream
+            CFX_HIP(hipEventRecord(h->ev_panel, st));
+            CFX_HIP(hipStreamWaitEvent(side, h->ev_panel, 0));
+            const int64_t kn = k + vb;
+            e = pf.begin(side);
+            if ((rc = launch_tslu(A + kn * lda + kn, lda, kn, n - kn, vbn, L, ws, nullptr, ipiv, info, side)))
                 return rc;
-            pf.end(PH_SCHUR, e, st, 2.0 * (double)m * (double)m * vb);
+            pf.end(PH_TSLU, e, side);
+            CFX_HIP(hipEventRecord(h->ev_tslu, side));
+            tslu_on_side = true;
+            // the rest of the update
+            if (m > vbn) {
+                e = pf.begin(st);
+                if ((rc = launch_schur_f64(L21, lda, U12 + vbn, lda, C + vbn, lda, m, m - vbn, vb, st)))
+                    return rc;
+                pf.end(PH_SCHUR, e, st, 2.0 * (double)m * (double)(m - vbn) * vb);
+            }
         }
         if (pf.on) ++pf.panels;
     }
+    if (tslu_on_side) CFX_HIP(hipStreamWaitEvent(st, h->ev_tslu, 0));
     return CFX_OK;
 }
 

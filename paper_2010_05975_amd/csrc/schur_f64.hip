@@ -8,7 +8,8 @@
 // buffered: the next chunk is fetched into registers while the current one
 // feeds the matrix cores.  Both operand tiles are stored k-major in LDS so
 // that the 16 lanes of an MFMA operand row read 16 consecutive doubles.
-// C is read and written once, in the epilogue.
+// C is read once into the accumulators before the reduction (the L tile is
+// staged negated, so the matrix cores accumulate C - L U) and written once.
 //
 // Tiles are mapped XCD-aware: consecutive workgroup ids land on different
 // XCDs (each with its own L2), so ids are regrouped to give each XCD a
@@ -19,6 +20,7 @@ namespace cfx {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
 
 constexpr int BM = 128, BN = 128, BK = 16;
 constexpr int LDA_S = BM + 16;   // padded k-major rows of the L tile
@@ -41,6 +43,10 @@ __device__ __forceinline__ void tile_of(int bid, int nb, int tm, int tn, int &ti
     tj = r / gsz;
 }
 
+// EDGE: the tile may cross the matrix edge or K is not a multiple of BK
+// (every access is guarded).  VEC: operands are 16-byte aligned with even
+// strides, so a thread fetches its 8 contiguous doubles as 4 x 16 bytes.
+template <bool EDGE, bool VEC>
 __global__ __launch_bounds__(256, 2) void schur_f64_kernel(const double *__restrict__ L, int64_t ldl,
                                                            const double *__restrict__ U, int64_t ldu,
                                                            double *__restrict__ C, int64_t ldc,
@@ -61,40 +67,70 @@ __global__ __launch_bounds__(256, 2) void schur_f64_kernel(const double *__restr
     // global -> register staging assignment
     const int a_row = tid >> 1, a_col = (tid & 1) * 8;     // L tile: 128 rows x 16
     const int b_row = tid >> 4, b_col = (tid & 15) * 8;    // U tile: 16 rows x 128
+    const double *Lp = L + (i0 + a_row) * ldl + a_col;
+    const double *Up = U + (int64_t)b_row * ldu + j0 + b_col;
     double ra[8], rb[8];
 
     auto fetch = [&](int kc) {
         const int k0 = kc * BK;
-        const int64_t gi = i0 + a_row;
+        if constexpr (!EDGE && VEC) {
+            const d2 *la = reinterpret_cast<const d2 *>(Lp + k0);
+            const d2 *ub = reinterpret_cast<const d2 *>(Up + (int64_t)k0 * ldu);
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int kk = k0 + a_col + q;
-            ra[q] = (gi < mr && kk < K) ? L[gi * ldl + kk] : 0.0;
-        }
-        const int kb = k0 + b_row;
+            for (int q = 0; q < 4; ++q) {
+                const d2 x = la[q], y = ub[q];
+                ra[2 * q] = x[0]; ra[2 * q + 1] = x[1];
+                rb[2 * q] = y[0]; rb[2 * q + 1] = y[1];
+            }
+        } else if constexpr (!EDGE) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int64_t gj = j0 + b_col + q;
-            rb[q] = (kb < K && gj < nc) ? U[(int64_t)kb * ldu + gj] : 0.0;
+            for (int q = 0; q < 8; ++q) {
+                ra[q] = Lp[k0 + q];
+                rb[q] = Up[(int64_t)k0 * ldu + q];
+            }
+        } else {
+            const int64_t gi = i0 + a_row;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int kk = k0 + a_col + q;
+                ra[q] = (gi < mr && kk < K) ? L[gi * ldl + kk] : 0.0;
+            }
+            const int kb = k0 + b_row;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int64_t gj = j0 + b_col + q;
+                rb[q] = (kb < K && gj < nc) ? U[(int64_t)kb * ldu + gj] : 0.0;
+            }
         }
     };
     auto stash = [&](int buf) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) As[buf][(a_col + q) * LDA_S + a_row] = ra[q];
+        for (int q = 0; q < 8; ++q) As[buf][(a_col + q) * LDA_S + a_row] = -ra[q];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) Bs[buf][b_row * LDB_S + b_col + q] = rb[q];
+        for (int q = 0; q < 8; q += 2)
+            *reinterpret_cast<d2 *>(&Bs[buf][b_row * LDB_S + b_col + q]) = d2{rb[q], rb[q + 1]};
     };
 
+    // The accumulators start from C and the L tile is staged negated, so the
+    // matrix cores produce C - L U directly and the epilogue only stores.
     d4 acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int b = 0; b < 4; ++b) {
+            const int64_t gj = j0 + wn + b * 16 + lr;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t gi = i0 + wm + a * 16 + lk + 4 * q;
+                acc[a][b][q] = (!EDGE || (gi < mr && gj < nc)) ? C[gi * ldc + gj] : 0.0;
+            }
+        }
 
     const int nk = (K + BK - 1) / BK;
     fetch(0);
     stash(0);
     __syncthreads();
+#pragma unroll 1
     for (int kc = 0; kc < nk; ++kc) {
         const int buf = kc & 1;
         if (kc + 1 < nk) fetch(kc + 1);
@@ -127,10 +163,7 @@ __global__ __launch_bounds__(256, 2) void schur_f64_kernel(const double *__restr
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int64_t gi = i0 + wm + a * 16 + lk + 4 * q;
-                if (gi < mr && gj < nc) {
-                    double *c = C + gi * ldc + gj;
-                    *c = *c - acc[a][b][q];
-                }
+                if (!EDGE || (gi < mr && gj < nc)) C[gi * ldc + gj] = acc[a][b][q];
             }
         }
 }
@@ -143,8 +176,18 @@ int launch_schur_f64(const double *L, int64_t ldl, const double *U, int64_t ldu,
     if (mr <= 0 || nc <= 0 || K <= 0) return CFX_OK;
     const int tm = (int)((mr + BM - 1) / BM), tn = (int)((nc + BN - 1) / BN);
     const int64_t nb = (int64_t)tm * tn;
-    hipLaunchKernelGGL(schur_f64_kernel, dim3((unsigned)nb), dim3(256), 0, st, L, ldl, U, ldu, C, ldc,
-                       mr, nc, K, tm, tn);
+    const bool full = (mr % BM == 0) && (nc % BN == 0) && (K % BK == 0);
+    const bool vec = ((reinterpret_cast<uintptr_t>(L) | reinterpret_cast<uintptr_t>(U)) & 15) == 0 &&
+                     (ldl % 2 == 0) && (ldu % 2 == 0);
+    if (full && vec)
+        hipLaunchKernelGGL((schur_f64_kernel<false, true>), dim3((unsigned)nb), dim3(256), 0, st, L, ldl, U,
+                           ldu, C, ldc, mr, nc, K, tm, tn);
+    else if (full)
+        hipLaunchKernelGGL((schur_f64_kernel<false, false>), dim3((unsigned)nb), dim3(256), 0, st, L, ldl,
+                           U, ldu, C, ldc, mr, nc, K, tm, tn);
+    else
+        hipLaunchKernelGGL((schur_f64_kernel<true, false>), dim3((unsigned)nb), dim3(256), 0, st, L, ldl, U,
+                           ldu, C, ldc, mr, nc, K, tm, tn);
     CFX_HIP(hipGetLastError());
     return CFX_OK;
 }

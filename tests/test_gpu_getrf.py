@@ -51,9 +51,9 @@ def test_tslu_ties_smallest_row(cfx):
 # full factorisation
 # ---------------------------------------------------------------------------
 
-def run_getrf(cfx, A, v, L):
+def run_getrf(cfx, A, v, L, lookahead=0):
     dA = to_dev(A)
-    ipiv, info = cfx.getrf(dA, v=v, leaves=L)
+    ipiv, info = cfx.getrf(dA, v=v, leaves=L, lookahead=lookahead)
     torch.cuda.synchronize()
     return dA.cpu().numpy(), ipiv.cpu().numpy(), int(info.cpu()[0])
 
@@ -74,11 +74,12 @@ def lu_tolerance(ref_LU, n):
     ("normal", 2048, 256, 4),
     ("normal", 777, 256, 2),
 ])
-def test_getrf_matches_oracle(cfx, gen, n, v, L):
-    say(f"getrf {gen} n={n} v={v} L={L}")
+@pytest.mark.parametrize("lookahead", [0, 1])
+def test_getrf_matches_oracle(cfx, gen, n, v, L, lookahead):
+    say(f"getrf {gen} n={n} v={v} L={L} lookahead={lookahead}")
     A = getattr(G, f"{gen}_matrix")(n, 17)
     ref = O.getrf(A, v, L)
-    LU, ipiv, info = run_getrf(cfx, A, v, L)
+    LU, ipiv, info = run_getrf(cfx, A, v, L, lookahead)
     assert info == ref.info == 0
     compared = compare_panels(ipiv, ref.ipiv, ref.margins, v)
     say(f"  panels compared {compared}/{len(ref.margins)}")
@@ -108,12 +109,13 @@ def test_getrf_dd_exact(cfx, n, v, L):
     assert np.array_equal(np.triu(LU), U0)
 
 
-def test_getrf_zero_column_info(cfx):
-    say("zero column")
+@pytest.mark.parametrize("lookahead", [0, 1])
+def test_getrf_zero_column_info(cfx, lookahead):
+    say(f"zero column lookahead={lookahead}")
     n = 80
     A = G.normal_matrix(n, 4)
     A[:, 37] = 0.0
-    LU, ipiv, info = run_getrf(cfx, A, 16, 3)
+    LU, ipiv, info = run_getrf(cfx, A, 16, 3, lookahead)
     ref = O.getrf(A, 16, 3)
     assert info == ref.info == 38
     assert np.array_equal(ipiv, ref.ipiv)
@@ -150,3 +152,14 @@ def test_getrs_matches_oracle(cfx, n, nrhs, v, L):
     eta_ref = O.eta(A, Xref, B)
     assert O.eta(A, X, B) <= max(4 * eta_ref, 1e-15)
     np.testing.assert_allclose(X, Xref, rtol=1e-8, atol=1e-8 * np.abs(Xref).max())
+
+
+def test_getrf_lookahead_bitwise_equal(cfx):
+    """Lookahead only reorders independent launches: the factors are
+    bitwise the same as without it."""
+    say("lookahead bitwise")
+    A = G.normal_matrix(1500, 8)
+    a = run_getrf(cfx, A, 128, 4, 0)
+    b = run_getrf(cfx, A, 128, 4, 1)
+    assert np.array_equal(a[1], b[1])
+    assert np.array_equal(a[0], b[0])
