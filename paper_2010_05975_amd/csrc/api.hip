@@ -62,7 +62,8 @@ static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
     int64_t max_nodes, node_rows;
-    size_t off_S, off_cand0, off_cand1, off_cnt0, off_cnt1, off_plan, off_lu00, off_mp, total;
+    size_t off_S, off_cand0, off_cand1, off_cnt0, off_cnt1, off_plan, off_lu00, off_selg, off_rsel,
+        off_utg, off_rtg, off_mp, total;
 };
 
 static Layout layout(int64_t n, int v, int leaves, int precision)
@@ -83,6 +84,10 @@ static Layout layout(int64_t n, int v, int leaves, int precision)
     L.off_cnt1 = o;  o = align_up(o + (size_t)L.max_nodes * sizeof(int32_t));
     L.off_plan = o;  o = align_up(o + (size_t)(1 + 4 * kMaxV) * sizeof(int32_t));
     L.off_lu00 = o;  o = align_up(o + (size_t)v * v * sizeof(double));
+    L.off_selg = o;  o = align_up(o + (size_t)L.max_nodes * 2 * kMaxV * sizeof(int32_t));
+    L.off_rsel = o;  o = align_up(o + (size_t)L.max_nodes * L.node_rows);
+    L.off_utg = o;   o = align_up(o + (size_t)L.max_nodes * 32 * kMaxV * sizeof(double));
+    L.off_rtg = o;   o = align_up(o + (size_t)L.max_nodes * 32 * 40 * sizeof(double));
     L.off_mp = o;
     (void)precision;
     L.total = o;
@@ -108,6 +113,11 @@ int carve_workspace(void *work, size_t bytes, int64_t n, int v, int leaves, int 
     ws->ccnt[1] = reinterpret_cast<int32_t *>(b + L.off_cnt1);
     ws->plan = reinterpret_cast<int32_t *>(b + L.off_plan);
     ws->lu00 = reinterpret_cast<double *>(b + L.off_lu00);
+    ws->selg = reinterpret_cast<int32_t *>(b + L.off_selg);
+    ws->rsel = reinterpret_cast<unsigned char *>(b + L.off_rsel);
+    ws->rs_node = L.node_rows;
+    ws->utg = reinterpret_cast<double *>(b + L.off_utg);
+    ws->rtg = reinterpret_cast<double *>(b + L.off_rtg);
     ws->scratch = reinterpret_cast<double *>(b + L.off_mp);
     ws->scratch_bytes = bytes - L.off_mp;
     ws->max_nodes = L.max_nodes;

@@ -27,6 +27,11 @@ struct Workspace {
     int32_t *ccnt[2];   // candidate counts: nodes
     int32_t *plan;      // row-move plan: [0] = count, then dst[2v], src[2v]
     double *lu00;       // factored diagonal block, v x v
+    int32_t *selg;      // tournament node state: selection [nodes x 2 x kMaxV]
+    unsigned char *rsel; // tournament node state: selected-row mask [nodes x rs_node]
+    int64_t rs_node;
+    double *utg;        // tournament node state: U rows of a block [nodes x 32 x kMaxV]
+    double *rtg;        // tournament node state: block triangle [nodes x 32 x 40]
     double *scratch;    // mixed precision: packed low-precision panels
     size_t scratch_bytes;
     int64_t max_nodes;

@@ -1,35 +1,33 @@
 // Tournament pivoting (TournPivot of Alg. 1; Sec. 7.3 "Pivoting in COnfLUX";
 // Sec. 7.4, Step 1) on gfx950.
 //
-// One workgroup of 256 threads runs one node of the tournament: a leaf (h
-// consecutive rows of the panel) or a merge of two children's candidate
-// rows, stacked left child first and taken with their current-step panel
-// values.  The node selects min(vb, rows) rows by Gaussian elimination with
-// partial pivoting, ties to the smallest global row.  A level of the tree is
-// one launch.
+// Each node of the tournament is a leaf (h consecutive rows of the panel)
+// or a merge of two children's candidate rows, stacked left child first and
+// taken with their current-step panel values.  A node selects min(vb, rows)
+// rows by Gaussian elimination with partial pivoting, ties to the smallest
+// global row.  The elimination of a node is blocked by BW = 32 columns; each
+// block of one tree level is two launches:
 //
-// Layout inside a node: thread t owns physical rows t, t+256, ... (RPT rows)
-// and keeps their values of the current inner block of BW <= 32 columns in
-// registers.  The node's panel block lives in a column-major scratch block
-// (element (c, p) at c*rc + p): a wavefront touching one column of 64
-// consecutive rows makes one coalesced access, and the matrix-core tiles of
-// the trailing update read and write 128-byte row runs.
+//  P (one workgroup of 256 threads per node): thread t owns physical rows
+//    t, t+256, ... and keeps their block columns in registers.  Pivot steps:
+//    each thread scores its unselected rows, a DPP/readlane reduction picks
+//    the wave's best, the winning lane publishes its row into a
+//    double-buffered LDS slot, one barrier, and every thread picks the
+//    overall winner and eliminates its rows against it.  Then the block's
+//    pivot rows are extended to the trailing columns (U rows, unit-lower
+//    substitution in registers).  The node's state (selection, row mask,
+//    negated U rows) is kept in the workspace between launches.
+//  E (many workgroups, all nodes of the level): the rank-BW update of the
+//    trailing columns on the FP64 matrix cores, C^T -= U^T L^T, in 64 x 64
+//    tiles; a node's update is spread over the whole GPU instead of being
+//    bound by one compute unit's memory bandwidth.
 //
-// Per inner block:
-//  B. pivot steps: each thread scores its unselected rows, a wavefront
-//     shuffle reduction picks the wave's best, the winning lane publishes
-//     its row into a double-buffered LDS slot, one barrier, and every thread
-//     picks the overall winner from the 4 slots and eliminates its rows
-//     against that row (registers only);
-//  D. the block's pivot rows are extended to the trailing columns: U rows by
-//     substitution with the block's unit-lower triangle, one column per
-//     thread, in registers;
-//  E. the rank-BW update of the trailing columns on the FP64 matrix cores,
-//     in transposed form C^T -= U^T L^T (selected rows get zero
-//     multipliers, so they are left unchanged).
-// Rows are never moved: selected rows are marked, and the selection order is
-// kept in LDS.  In exact arithmetic this is the unblocked elimination, so the
-// selection is the same.
+// The node's panel block lives in a column-major scratch block (element
+// (c, p) at c*rc + p): a wavefront touching one column of 64 consecutive
+// rows makes one coalesced access, and the matrix-core tiles read and write
+// 128-byte row runs.  Rows are never moved: selected rows are marked, and the
+// selection order is kept.  In exact arithmetic this is the unblocked
+// elimination, so the selection is the same.
 //
 // The root also turns its selection into LAPACK-style interchanges (ipiv)
 // and a row-move plan for the swap kernel, and copies its factored top
@@ -70,6 +68,12 @@ struct NodeArgs {
     int32_t *ipiv;          // root: interchanges, global indexing (may be null)
     int32_t *plan;          // root: row-move plan (may be null)
     int32_t *info;          // root: first zero pivot (may be null)
+    int32_t *selg;          // per node: selected global rows [kMaxV], physical rows [kMaxV]
+    unsigned char *rsel;    // per node: row already selected [rs_node]
+    int rs_node;
+    double *utg;            // per node: U rows of the previous block [32 x kMaxV]
+    double *rtg;            // per node: the block's unit-lower triangle [32 x 40]
+    int jb;                 // first column of the current block
 };
 
 // Compile-time loop: f(std::integral_constant<int, 0>) ... f(<N-1>), so that
@@ -129,17 +133,23 @@ __device__ __forceinline__ double score(double a)
     return s == s ? s : -0.5;
 }
 
+constexpr int UTLD = kMaxV;                 // row stride of the saved U rows
+
+template <int RPT>
+struct BlockW {
+    static constexpr int value = (64 / RPT) < 32 ? (64 / RPT) : 32;
+};
+
 template <int BW>
 struct Lds {
-    static constexpr int UTLD = ((kMaxV - BW) + 15) & ~15;  // trailing columns
     d2 cand[2][NW][BW / 2 > 0 ? BW / 2 : 1];   // published pivot-row candidates
     double slot_a[2][NW];
     int slot_g[2][NW];
     int slot_t[2][NW];
     int slot_s[2][NW];
     double RT[BW][BW + 8];      // RT[l][i] = multiplier of block pivot i on pivot l
+    double PR[8][BW + 2];       // the current sub-panel's pivot rows
     union {
-        double Ut[BW][UTLD];    // -U rows of the block at the trailing columns
         double tile[64 * 65];   // gather: transpose staging
         int plan_tmp[2 * kMaxV];
     };
@@ -148,10 +158,49 @@ struct Lds {
     unsigned char rowsel[kMaxLeafRows];   // physical row already selected
 };
 
-template <int RPT>
-__global__ __launch_bounds__(NT) void tslu_node_kernel(NodeArgs p)
+// Rows of node `node` at this level; 0 for a promoted (unpaired) node.
+struct NodeRows {
+    int r = 0;
+    int cl = 0;
+    int64_t leaf_first = 0;
+    const int32_t *cl_list = nullptr, *cr_list = nullptr;
+    bool promoted = false;
+};
+
+__device__ __forceinline__ NodeRows node_rows(const NodeArgs &p, int node)
 {
-    constexpr int BW = (64 / RPT) < 32 ? (64 / RPT) : 32;
+    NodeRows n;
+    if (p.leaf) {
+        n.leaf_first = (int64_t)node * p.h;
+        const int64_t last = n.leaf_first + p.h < p.rows ? n.leaf_first + p.h : p.rows;
+        n.r = (int)(last - n.leaf_first);
+    } else {
+        const int a = 2 * node;
+        if (a + 1 >= p.nn_in) {
+            n.promoted = true;
+            return n;
+        }
+        n.cl = p.ccnt_in[a];
+        n.r = n.cl + p.ccnt_in[a + 1];
+        n.cl_list = p.cand_in + (size_t)a * p.vb;
+        n.cr_list = p.cand_in + (size_t)(a + 1) * p.vb;
+    }
+    return n;
+}
+
+__device__ __forceinline__ int node_gid(const NodeArgs &p, const NodeRows &n, int pr)
+{
+    if (p.leaf) return (int)(p.row0 + n.leaf_first + pr);
+    return pr < n.cl ? n.cl_list[pr] : n.cr_list[pr - n.cl];
+}
+
+// ---------------------------------------------------------------------------
+// P: pivot steps and U rows of one block, one workgroup per node.
+// ---------------------------------------------------------------------------
+template <int RPT>
+__global__ __launch_bounds__(NT) void tslu_panel_kernel(NodeArgs p)
+{
+    constexpr int BW = BlockW<RPT>::value;
     using L = Lds<BW>;
     extern __shared__ double smem_raw[];
     L &s = *reinterpret_cast<L *>(smem_raw);
@@ -162,74 +211,48 @@ __global__ __launch_bounds__(NT) void tslu_node_kernel(NodeArgs p)
     const int node = blockIdx.x;
     const int vb = p.vb;
     const int rc = p.rc;
+    const int jb = p.jb;
 
-    // ---- node rows ---------------------------------------------------------
-    int r;
-    int64_t leaf_first = 0;
-    const int32_t *cl_list = nullptr, *cr_list = nullptr;
-    int cl = 0;
-    if (p.leaf) {
-        leaf_first = (int64_t)node * p.h;
-        const int64_t last = leaf_first + p.h < p.rows ? leaf_first + p.h : p.rows;
-        r = (int)(last - leaf_first);
-    } else {
-        const int a = 2 * node;
-        if (a + 1 >= p.nn_in) {                 // unpaired: promoted unchanged
+    const NodeRows nr = node_rows(p, node);
+    if (nr.promoted) {                        // unpaired: promoted unchanged
+        if (jb == 0) {
+            const int a = 2 * node;
             const int c = p.ccnt_in[a];
             for (int i = tid; i < c; i += NT) p.cand_out[(size_t)node * vb + i] = p.cand_in[(size_t)a * vb + i];
             if (tid == 0) p.ccnt_out[node] = c;
-            return;
         }
-        cl = p.ccnt_in[a];
-        r = cl + p.ccnt_in[a + 1];
-        cl_list = p.cand_in + (size_t)a * vb;
-        cr_list = p.cand_in + (size_t)(a + 1) * vb;
+        return;
     }
-    auto gid_of = [&](int pr) -> int {
-        if (p.leaf) return (int)(p.row0 + leaf_first + pr);
-        return pr < cl ? cl_list[pr] : cr_list[pr - cl];
-    };
+    const int r = nr.r;
+    const int nsel = r < vb ? r : vb;
+    if (jb >= nsel) return;
+    const int bwc = (nsel - jb) < BW ? (nsel - jb) : BW;
+    const int tc0 = jb + bwc;            // first trailing column
+    const int ncol = nsel - tc0;         // trailing columns that matter
 
     double *Sn = p.S + (size_t)node * p.s_node;
-    for (int i = tid; i < r; i += NT) s.rowsel[i] = 0;
+    int32_t *selg = p.selg + (size_t)node * 2 * kMaxV;
+    unsigned char *rselg = p.rsel + (size_t)node * p.rs_node;
+    double *utg = p.utg + (size_t)node * 32 * UTLD;
+    double *rtg = p.rtg + (size_t)node * 32 * 40;
 
-    // ---- gather the current-step panel values, transposed through LDS ------
-    // (a 64-row strip of all vb columns is loaded at once, then written out
-    //  column-major one 64 x 64 tile at a time)
-    {
-        double *tile = s.tile;                  // 64 x 65 staging tile
-        constexpr int PER = 64 * 64 / NT;       // 16 elements per thread per tile
-        constexpr int NTL = 2;                  // tiles loaded per batch
-        for (int r0 = 0; r0 < r; r0 += 64)
-        for (int t0 = 0; t0 < vb; t0 += 64 * NTL) {
-            double v[NTL][PER];
-#pragma unroll
-            for (int tl = 0; tl < NTL; ++tl)
-#pragma unroll
-                for (int k = 0; k < PER; ++k) {
-                    const int e = tid + k * NT, i = e >> 6, c = t0 + tl * 64 + (e & 63);
-                    v[tl][k] = (r0 + i < r && c < vb)
-                                   ? p.W[(int64_t)(gid_of(r0 + i) - p.row0) * p.ldw + c] : 0.0;
-                }
-#pragma unroll
-            for (int tl = 0; tl < NTL; ++tl) {
-                if (t0 + tl * 64 < vb) {
-#pragma unroll
-                    for (int k = 0; k < PER; ++k) {
-                        const int e = tid + k * NT, i = e >> 6, c = e & 63;
-                        tile[i * 65 + c] = v[tl][k];
-                    }
-                    __syncthreads();
-#pragma unroll
-                    for (int k = 0; k < PER; ++k) {
-                        const int e = tid + k * NT, c = e >> 6, i = e & 63;
-                        if (r0 + i < r && t0 + tl * 64 + c < vb)
-                            Sn[(size_t)(t0 + tl * 64 + c) * rc + r0 + i] = tile[i * 65 + c];
-                    }
-                    __syncthreads();
-                }
-            }
+    if (jb > 0) {
+        for (int i = tid; i < jb; i += NT) {
+            s.sel[i] = selg[i];
+            s.selp[i] = selg[kMaxV + i];
         }
+    }
+    for (int i = tid; i < r; i += NT) s.rowsel[i] = rselg[i];
+    __syncthreads();
+    if (jb > 0) {
+        // the previous block's U rows (computed by the update launch) go
+        // into their pivot rows of the scratch block
+        const int pj0 = jb - BW, ncp = nsel - jb;
+        for (int e = tid; e < BW * ncp; e += NT) {
+            const int i = e / ncp, c = e - i * ncp;
+            Sn[(size_t)(jb + c) * rc + s.selp[pj0 + i]] = utg[(size_t)i * UTLD + c];
+        }
+        __syncthreads();    // the copies above land before any row is loaded
     }
 
     int gid[RPT];
@@ -237,18 +260,15 @@ __global__ __launch_bounds__(NT) void tslu_node_kernel(NodeArgs p)
     static_for<RPT>([&](auto QC) {
         constexpr int q = decltype(QC)::value;
         const int pr = tid + q * NT;
-        live[q] = pr < r;
-        gid[q] = live[q] ? gid_of(pr) : INT_MAX;
+        live[q] = pr < r && !s.rowsel[pr];
+        gid[q] = pr < r ? node_gid(p, nr, pr) : INT_MAX;
     });
 
-    const int nsel = r < vb ? r : vb;
-
-    for (int jb = 0; jb < nsel; jb += BW) {
-        const int bwc = (nsel - jb) < BW ? (nsel - jb) : BW;
-        const int tc0 = jb + bwc;            // first trailing column
-        const int ncol = nsel - tc0;         // trailing columns that matter
-
-        {   // x: the block columns of this thread's rows, live only here
+    {   // x: the block columns of this thread's rows.  The block is
+        // eliminated in sub-panels of SP columns: x[q][0..SP) always holds
+        // the current sub-panel (the register window shifts left by SP
+        // after each one), so only SP pivot steps are unrolled.
+        constexpr int SP = BW < 8 ? BW : 8;
         double x[RPT][BW];
         static_for<RPT>([&](auto QC) {
             constexpr int q = decltype(QC)::value;
@@ -258,186 +278,156 @@ __global__ __launch_bounds__(NT) void tslu_node_kernel(NodeArgs p)
                 x[q][c] = (pr < r && c < bwc) ? Sn[(size_t)(jb + c) * rc + pr] : 0.0;
         });
 
-        // ---- B: pivot steps of the block --------------------------------
-        static_for<BW>([&](auto JC) {
-            constexpr int j = decltype(JC)::value;
-            if (j < bwc) {
-                const int par = j & 1;
-                double ba = -1.0;
-                int bg = INT_MAX, bq = -1;
-                static_for<RPT>([&](auto QC) {
-                    constexpr int q = decltype(QC)::value;
-                    if (live[q]) {
-                        const double a = score(x[q][j]);
-                        if (beats(a, gid[q], ba, bg)) { ba = a; bg = gid[q]; bq = q; }
-                    }
-                });
-                double wa = ba;
-                int wg = bg;
-                wave_argmax(wa, wg);
-                // gids are unique, so exactly one lane owns the wave's best
-                if (bq >= 0 && bg == wg) {
-                    static_for<RPT>([&](auto QC) {
-                        constexpr int q = decltype(QC)::value;
-                        if (q == bq) {
-#pragma unroll
-                            for (int c = 0; c + 1 < BW; c += 2) s.cand[par][wave][c / 2] = d2{x[q][c], x[q][c + 1]};
-                            if (BW & 1) s.cand[par][wave][BW / 2][0] = x[q][BW - 1];
-                        }
-                    });
-                    s.slot_t[par][wave] = tid;
-                    s.slot_s[par][wave] = bq;
-                }
-                if (lane == 0) {
-                    s.slot_a[par][wave] = wa;
-                    s.slot_g[par][wave] = wg;
-                }
-                __syncthreads();
-                double ma = s.slot_a[par][0];
-                int mg = s.slot_g[par][0], mw = 0;
-#pragma unroll
-                for (int w = 1; w < NW; ++w) {
-                    const double aw = s.slot_a[par][w];
-                    const int gw = s.slot_g[par][w];
-                    if (beats(aw, gw, ma, mg)) { ma = aw; mg = gw; mw = w; }
-                }
-                const int ot = s.slot_t[par][mw], oq = s.slot_s[par][mw];
-                const double *prow = reinterpret_cast<const double *>(&s.cand[par][mw][0]);
-                if (tid == 0) {
-                    s.sel[jb + j] = mg;
-                    s.selp[jb + j] = ot + oq * NT;
-                    s.rowsel[ot + oq * NT] = 1;
-                }
-                if (tid < j) s.RT[tid][j] = prow[tid];
-                static_for<RPT>([&](auto QC) {
-                    constexpr int q = decltype(QC)::value;
-                    if (tid == ot && q == oq) live[q] = false;
-                });
-                const double piv = prow[j];
-                if (piv != 0.0) {
-                    d2 pv[BW / 2 > 0 ? BW / 2 : 1];
-#pragma unroll
-                    for (int c = 2 * ((j + 1) / 2); c + 1 < BW; c += 2) pv[c / 2] = s.cand[par][mw][c / 2];
+        for (int sp0 = 0; sp0 < bwc; sp0 += SP) {
+            const int spc = (bwc - sp0) < SP ? (bwc - sp0) : SP;   // steps in this sub-panel
+            const int rem = bwc - sp0 - SP;                        // block columns right of it
+            bool open[RPT];     // live when the sub-panel starts: writes its columns back
+            static_for<RPT>([&](auto QC) {
+                constexpr int q = decltype(QC)::value;
+                open[q] = live[q];
+            });
+            static_for<SP>([&](auto JC) {
+                constexpr int j = decltype(JC)::value;
+                if (j < spc) {
+                    const int par = j & 1;
+                    double ba = -1.0;
+                    int bg = INT_MAX, bq = -1;
                     static_for<RPT>([&](auto QC) {
                         constexpr int q = decltype(QC)::value;
                         if (live[q]) {
-                            const double l = x[q][j] / piv;
-                            x[q][j] = l;
-#pragma unroll
-                            for (int c = j + 1; c < BW; ++c)
-                                x[q][c] -= l * ((c + 1 < BW || !(BW & 1)) ? pv[c / 2][c & 1] : prow[c]);
+                            const double a = score(x[q][j]);
+                            if (beats(a, gid[q], ba, bg)) { ba = a; bg = gid[q]; bq = q; }
                         }
                     });
-                }
-            }
-        });
-
-        // block columns back to the scratch block (final for this block)
-        static_for<RPT>([&](auto QC) {
-            constexpr int q = decltype(QC)::value;
-            const int pr = tid + q * NT;
-            if (pr < r) {
+                    double wa = ba;
+                    int wg = bg;
+                    wave_argmax(wa, wg);
+                    // gids are unique, so exactly one lane owns the wave's best
+                    if (bq >= 0 && bg == wg) {
+                        static_for<RPT>([&](auto QC) {
+                            constexpr int q = decltype(QC)::value;
+                            if (q == bq) {
 #pragma unroll
-                for (int c = 0; c < BW; ++c)
-                    if (c < bwc) Sn[(size_t)(jb + c) * rc + pr] = x[q][c];
+                                for (int c = 0; c + 1 < BW; c += 2) s.cand[par][wave][c / 2] = d2{x[q][c], x[q][c + 1]};
+                                if (BW & 1) s.cand[par][wave][BW / 2][0] = x[q][BW - 1];
+                            }
+                        });
+                        s.slot_t[par][wave] = tid;
+                        s.slot_s[par][wave] = bq;
+                    }
+                    if (lane == 0) {
+                        s.slot_a[par][wave] = wa;
+                        s.slot_g[par][wave] = wg;
+                    }
+                    __syncthreads();
+                    double ma = s.slot_a[par][0];
+                    int mg = s.slot_g[par][0], mw = 0;
+#pragma unroll
+                    for (int w = 1; w < NW; ++w) {
+                        const double aw = s.slot_a[par][w];
+                        const int gw = s.slot_g[par][w];
+                        if (beats(aw, gw, ma, mg)) { ma = aw; mg = gw; mw = w; }
+                    }
+                    const int ot = s.slot_t[par][mw], oq = s.slot_s[par][mw];
+                    const double *prow = reinterpret_cast<const double *>(&s.cand[par][mw][0]);
+                    if (tid == 0) {
+                        s.sel[jb + sp0 + j] = mg;
+                        s.selp[jb + sp0 + j] = ot + oq * NT;
+                        s.rowsel[ot + oq * NT] = 1;
+                    }
+                    if (tid < BW) s.PR[j][tid] = prow[tid];
+                    static_for<RPT>([&](auto QC) {
+                        constexpr int q = decltype(QC)::value;
+                        if (tid == ot && q == oq) live[q] = false;
+                    });
+                    const double piv = prow[j];
+                    if (piv != 0.0) {
+                        double pv[SP];
+#pragma unroll
+                        for (int c = j + 1; c < SP; ++c) pv[c] = prow[c];
+                        static_for<RPT>([&](auto QC) {
+                            constexpr int q = decltype(QC)::value;
+                            if (live[q]) {
+                                const double l = x[q][j] / piv;
+                                x[q][j] = l;
+#pragma unroll
+                                for (int c = j + 1; c < SP; ++c) x[q][c] -= l * pv[c];
+                            }
+                        });
+                    }
+                }
+            });
+
+            // the sub-panel's columns are final for this block
+            static_for<RPT>([&](auto QC) {
+                constexpr int q = decltype(QC)::value;
+                const int pr = tid + q * NT;
+                if (open[q]) {
+#pragma unroll
+                    for (int c = 0; c < SP; ++c)
+                        if (c < spc) Sn[(size_t)(jb + sp0 + c) * rc + pr] = x[q][c];
+                }
+            });
+            if (rem > 0) {
+                __syncthreads();
+                // U rows of the sub-panel's pivots at the rest of the block:
+                // PR[i][SP + c] -= sum_{l<i} PR[i][l] * U[l][SP + c]
+                if (tid < rem) {
+                    const int c = SP + tid;
+#pragma unroll
+                    for (int i = 1; i < SP; ++i) {
+                        double u = s.PR[i][c];
+#pragma unroll
+                        for (int l = 0; l < SP; ++l)
+                            if (l < i) u -= s.PR[i][l] * s.PR[l][c];
+                        s.PR[i][c] = u;
+                    }
+                    // the sub-panel's pivot rows hold U rows in the rest of the block
+#pragma unroll
+                    for (int i = 0; i < SP; ++i)
+                        Sn[(size_t)(jb + sp0 + c) * rc + s.selp[jb + sp0 + i]] = s.PR[i][c];
+                }
+                __syncthreads();
+                // rank-SP update of the rest of the block, then shift the window
+                static_for<RPT>([&](auto QC) {
+                    constexpr int q = decltype(QC)::value;
+                    if (live[q]) {
+#pragma unroll
+                        for (int c = SP; c < BW; ++c) {
+                            double acc = x[q][c];
+#pragma unroll
+                            for (int l = 0; l < SP; ++l) acc -= x[q][l] * s.PR[l][c];
+                            x[q][c] = acc;
+                        }
+                    }
+#pragma unroll
+                    for (int c = 0; c + SP < BW; ++c) x[q][c] = x[q][c + SP];
+                });
             }
-        });
         }
-        __syncthreads();
+    }
+    __syncthreads();
+    // the block's unit-lower triangle for the update launch:
+    // RT[l][i] = multiplier of pivot i on pivot l (l < i)
+    for (int e = tid; e < bwc * bwc; e += NT) {
+        const int i = e / bwc, l = e - i * bwc;
+        if (l < i) s.RT[l][i] = Sn[(size_t)(jb + l) * rc + s.selp[jb + i]];
+    }
+    __syncthreads();
 
-        if (ncol > 0) {
-            // ---- D: U rows of the block at the trailing columns ---------
-            // (unit-lower substitution, one column per thread, in chunks of
-            //  8 rows held in registers; finished rows are kept in LDS)
-            for (int c = tid; c < ncol; c += NT) {
-                const size_t col = (size_t)(tc0 + c) * rc;
-                for (int h = 0; h < bwc; h += 8) {
-                    double u[8];
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) u[i] = (h + i < bwc) ? Sn[col + s.selp[jb + h + i]] : 0.0;
-                    for (int l = 0; l < h; ++l) {
-                        const double ul = -s.Ut[l][c];
-#pragma unroll
-                        for (int i = 0; i < 8; ++i) u[i] -= s.RT[l][h + i] * ul;
-                    }
-#pragma unroll
-                    for (int l = 0; l < 8; ++l)
-#pragma unroll
-                        for (int i = l + 1; i < 8; ++i) u[i] -= s.RT[h + l][h + i] * u[l];
-#pragma unroll
-                    for (int i = 0; i < 8; ++i)
-                        if (h + i < bwc) {
-                            s.Ut[h + i][c] = -u[i];
-                            Sn[col + s.selp[jb + h + i]] = u[i];
-                        }
-                }
-            }
-            __syncthreads();
-
-            // ---- E: C^T -= U^T L^T on the matrix cores ---------------------
-            // A = -U^T (16 trailing columns x 4 pivots), B = L^T (4 pivots x
-            // 16 rows, zero for selected rows), D = C^T tile (16 x 16).  A
-            // wave walks (row block, 64-column chunk) pairs and keeps the
-            // next chunk's loads in flight while the current one computes.
-            const int lr = lane & 15, lk = lane >> 4;
-            const int nrb = (r + 15) >> 4;
-            const int nch = (ncol + 63) >> 6;
-            const int my_nrb = nrb > wave ? (nrb - wave + NW - 1) / NW : 0;
-            const int total = my_nrb * nch;
-            constexpr int KS = (BW + 3) / 4;
-            auto load = [&](int it, d4 (&acc)[4], double (&bo)[KS]) {
-                const int rb = wave + NW * (it / nch);
-                const int c0 = (it % nch) * 64;
-                const int pr = rb * 16 + lr;
-                const bool rowok = pr < r && !s.rowsel[pr];
-#pragma unroll
-                for (int ks = 0; ks < KS; ++ks) {
-                    const int l = 4 * ks + lk;
-                    bo[ks] = (rowok && l < bwc) ? Sn[(size_t)(jb + l) * rc + pr] : 0.0;
-                }
-#pragma unroll
-                for (int t = 0; t < 4; ++t)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int cc = c0 + 16 * t + lk + 4 * q;
-                        acc[t][q] = (cc < ncol && pr < r) ? Sn[(size_t)(tc0 + cc) * rc + pr] : 0.0;
-                    }
-            };
-            d4 cur[4], nxt[4];
-            double bc[KS], bn[KS];
-            if (total > 0) load(0, cur, bc);
-            for (int it = 0; it < total; ++it) {
-                if (it + 1 < total) load(it + 1, nxt, bn);
-                const int rb = wave + NW * (it / nch);
-                const int c0 = (it % nch) * 64;
-                const int pr = rb * 16 + lr;
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    if (c0 + 16 * t < ncol) {
-#pragma unroll
-                        for (int ks = 0; ks < KS; ++ks) {
-                            const int l = 4 * ks + lk;
-                            const int cc = c0 + 16 * t + lr;
-                            const double aop = (l < bwc && cc < ncol) ? s.Ut[l][cc] : 0.0;
-                            cur[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, bc[ks], cur[t], 0, 0, 0);
-                        }
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const int cc = c0 + 16 * t + lk + 4 * q;
-                            if (cc < ncol && pr < r) Sn[(size_t)(tc0 + cc) * rc + pr] = cur[t][q];
-                        }
-                    }
-                }
-#pragma unroll
-                for (int t = 0; t < 4; ++t) cur[t] = nxt[t];
-#pragma unroll
-                for (int ks = 0; ks < KS; ++ks) bc[ks] = bn[ks];
-            }
-        }
-        __syncthreads();
+    // save the node state for the next launches
+    for (int i = tid; i < r; i += NT) rselg[i] = s.rowsel[i];
+    for (int i = tid; i < bwc; i += NT) {
+        selg[jb + i] = s.sel[jb + i];
+        selg[kMaxV + jb + i] = s.selp[jb + i];
     }
 
-    // ---- outputs -----------------------------------------------------------
+    for (int e = tid; e < BW * (BW + 8); e += NT) rtg[e] = (&s.RT[0][0])[e];
+
+    if (jb + bwc < nsel) return;
+
+    // ---- last block: outputs --------------------------------------------
+    __syncthreads();
     for (int j = tid; j < nsel; j += NT) p.cand_out[(size_t)node * vb + j] = s.sel[j];
     if (tid == 0) p.ccnt_out[node] = nsel;
     if (!p.root) return;
@@ -485,30 +475,200 @@ __global__ __launch_bounds__(NT) void tslu_node_kernel(NodeArgs p)
     }
 }
 
-template <int RPT>
-int launch_level(const NodeArgs &a, int grid, hipStream_t st)
+// ---------------------------------------------------------------------------
+// E: rank-BW update of the trailing columns of every node of the level.
+// Workgroup = one 64-row x 64-column tile of one node; wave w owns rows
+// 16w .. 16w+15 of the tile.  A = -U^T (16 columns x 4 pivots), B = L^T
+// (4 pivots x 16 rows, zero for selected rows), D = C^T (16 x 16).
+// ---------------------------------------------------------------------------
+template <int BW>
+__global__ __launch_bounds__(256) void tslu_update_kernel(NodeArgs p, int tiles_r, int tiles_c)
 {
-    constexpr int BW = (64 / RPT) < 32 ? (64 / RPT) : 32;
+    __shared__ double Ut[BW][64 + 1];   // -U rows of the block at the tile's columns
+    __shared__ double Rt[BW][BW + 8];
+    __shared__ int sp[BW];
+
+    const int tile = blockIdx.x;
+    const int per_node = tiles_r * tiles_c;
+    const int node = tile / per_node;
+    const int t = tile - node * per_node;
+    const int trow = t / tiles_c, tcol = t - trow * tiles_c;
+
+    const NodeRows nr = node_rows(p, node);
+    if (nr.promoted) return;
+    const int r = nr.r;
+    const int nsel = r < p.vb ? r : p.vb;
+    const int jb = p.jb;
+    if (jb >= nsel) return;
+    const int bwc = (nsel - jb) < BW ? (nsel - jb) : BW;
+    const int tc0 = jb + bwc, ncol = nsel - tc0;
+    const int c00 = tcol * 64, r00 = trow * 64;
+    if (c00 >= ncol || r00 >= r) return;
+
+    const int rc = p.rc;
+    const int tid = threadIdx.x;
+    double *Sn = p.S + (size_t)node * p.s_node;
+    const unsigned char *rselg = p.rsel + (size_t)node * p.rs_node;
+    const int32_t *selg = p.selg + (size_t)node * 2 * kMaxV;
+    double *utg = p.utg + (size_t)node * 32 * UTLD;
+    const double *rtg = p.rtg + (size_t)node * 32 * 40;
+
+    for (int e = tid; e < BW * (BW + 8); e += 256) (&Rt[0][0])[e] = rtg[e];
+    if (tid < BW) sp[tid] = selg[kMaxV + jb + tid];
+    __syncthreads();
+
+    // U rows of the block's pivots at this tile's columns: unit-lower
+    // substitution, one column per thread
+    if (tid < 64) {
+        const int cc = c00 + tid;
+        if (cc < ncol) {
+            const size_t col = (size_t)(tc0 + cc) * rc;
+            for (int h = 0; h < BW; h += 8) {
+                double u[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) u[i] = (h + i < bwc) ? Sn[col + sp[h + i]] : 0.0;
+                for (int l = 0; l < h; ++l) {
+                    const double ul = -Ut[l][tid];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) u[i] -= Rt[l][h + i] * ul;
+                }
+#pragma unroll
+                for (int l = 0; l < 8; ++l)
+#pragma unroll
+                    for (int i = l + 1; i < 8; ++i) u[i] -= Rt[h + l][h + i] * u[l];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    Ut[h + i][tid] = (h + i < bwc) ? -u[i] : 0.0;
+                    if (trow == 0 && h + i < bwc) utg[(size_t)(h + i) * UTLD + cc] = u[i];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < BW; ++i) Ut[i][tid] = 0.0;
+        }
+    }
+    __syncthreads();
+
+    // rank-BW update: A = -U^T (16 columns x 4 pivots), B = L^T (4 pivots x
+    // 16 rows, zero for selected rows), D = C^T (16 x 16)
+    const int lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int pr = r00 + wave * 16 + lr;
+    const bool rowin = pr < r;
+    const bool rowok = rowin && !rselg[pr];
+    constexpr int KS = (BW + 3) / 4;
+    double bop[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        const int l = 4 * ks + lk;
+        bop[ks] = (rowok && l < bwc) ? Sn[(size_t)(jb + l) * rc + pr] : 0.0;
+    }
+    d4 acc[4];
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int cc = c00 + 16 * tt + lk + 4 * q;
+            acc[tt][q] = (cc < ncol && rowin) ? Sn[(size_t)(tc0 + cc) * rc + pr] : 0.0;
+        }
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt) {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const int l = 4 * ks + lk;
+            const double aop = (l < bwc) ? Ut[l][16 * tt + lr] : 0.0;
+            acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, bop[ks], acc[tt], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int cc = c00 + 16 * tt + lk + 4 * q;
+            if (cc < ncol && rowin) Sn[(size_t)(tc0 + cc) * rc + pr] = acc[tt][q];
+        }
+}
+
+// Gather of a level: the current-step panel values of every node's rows into
+// its column-major scratch block, one 64 x 64 tile per workgroup (transposed
+// through LDS); also clears the node's selected-row mask.
+__global__ __launch_bounds__(256) void tslu_gather_kernel(NodeArgs p, int tiles_r, int tiles_c)
+{
+    __shared__ double tile[64][65];
+    const int per_node = tiles_r * tiles_c;
+    const int node = blockIdx.x / per_node;
+    const int t = blockIdx.x - node * per_node;
+    const int trow = t / tiles_c, tcol = t - trow * tiles_c;
+    const NodeRows nr = node_rows(p, node);
+    if (nr.promoted) return;
+    const int r = nr.r, r0 = trow * 64, c0 = tcol * 64;
+    if (r0 >= r || c0 >= p.vb) return;
+    const int tid = threadIdx.x;
+    double *Sn = p.S + (size_t)node * p.s_node;
+    constexpr int PER = 64 * 64 / 256;
+    double v[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = tid + k * 256, i = e >> 6, c = e & 63;
+        v[k] = (r0 + i < r && c0 + c < p.vb)
+                   ? p.W[(int64_t)(node_gid(p, nr, r0 + i) - p.row0) * p.ldw + c0 + c] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = tid + k * 256, i = e >> 6, c = e & 63;
+        tile[i][c] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = tid + k * 256, c = e >> 6, i = e & 63;
+        if (r0 + i < r && c0 + c < p.vb) Sn[(size_t)(c0 + c) * p.rc + r0 + i] = tile[i][c];
+    }
+    if (tcol == 0 && tid < 64 && r0 + tid < r) p.rsel[(size_t)node * p.rs_node + r0 + tid] = 0;
+}
+
+template <int RPT>
+int launch_level(NodeArgs a, int grid, int rows_cap, hipStream_t st)
+{
+    constexpr int BW = BlockW<RPT>::value;
     static bool attr_set = false;
     const size_t lds = sizeof(Lds<BW>);
     if (!attr_set) {
-        CFX_HIP(hipFuncSetAttribute((const void *)tslu_node_kernel<RPT>,
+        CFX_HIP(hipFuncSetAttribute((const void *)tslu_panel_kernel<RPT>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         attr_set = true;
     }
-    hipLaunchKernelGGL(tslu_node_kernel<RPT>, dim3(grid), dim3(NT), lds, st, a);
-    CFX_HIP(hipGetLastError());
+    const int nsel_max = rows_cap < a.vb ? rows_cap : a.vb;
+    const int tiles_r = (rows_cap + 63) / 64;
+    {
+        const int tiles_v = (a.vb + 63) / 64;
+        hipLaunchKernelGGL(tslu_gather_kernel, dim3(grid * tiles_r * tiles_v), dim3(256), 0, st, a, tiles_r,
+                           tiles_v);
+        CFX_HIP(hipGetLastError());
+    }
+    for (int jb = 0; jb < nsel_max; jb += BW) {
+        a.jb = jb;
+        hipLaunchKernelGGL(tslu_panel_kernel<RPT>, dim3(grid), dim3(NT), lds, st, a);
+        CFX_HIP(hipGetLastError());
+        const int ncol_max = nsel_max - (jb + BW);
+        if (ncol_max > 0) {
+            const int tiles_c = (ncol_max + 63) / 64;
+            hipLaunchKernelGGL(tslu_update_kernel<BW>, dim3(grid * tiles_r * tiles_c), dim3(256), 0, st, a,
+                               tiles_r, tiles_c);
+            CFX_HIP(hipGetLastError());
+        }
+    }
     return CFX_OK;
 }
 
 int launch_node_level(const NodeArgs &a, int grid, int rows_cap, hipStream_t st)
 {
-    if (rows_cap <= 256) return launch_level<1>(a, grid, st);
-    if (rows_cap <= 512) return launch_level<2>(a, grid, st);
-    if (rows_cap <= 1024) return launch_level<4>(a, grid, st);
-    if (rows_cap <= 2048) return launch_level<8>(a, grid, st);
-    if (rows_cap <= 4096) return launch_level<16>(a, grid, st);
-    if (rows_cap <= 8192) return launch_level<32>(a, grid, st);
+    if (rows_cap <= 256) return launch_level<1>(a, grid, rows_cap, st);
+    if (rows_cap <= 512) return launch_level<2>(a, grid, rows_cap, st);
+    if (rows_cap <= 1024) return launch_level<4>(a, grid, rows_cap, st);
+    if (rows_cap <= 2048) return launch_level<8>(a, grid, rows_cap, st);
+    if (rows_cap <= 4096) return launch_level<16>(a, grid, rows_cap, st);
+    if (rows_cap <= 8192) return launch_level<32>(a, grid, rows_cap, st);
     return CFX_ENOTSUP;
 }
 
@@ -536,6 +696,11 @@ int launch_tslu(const double *W, int64_t ldw, int64_t row0, int64_t rows, int vb
     a.ipiv = ipiv;
     a.plan = ipiv ? ws.plan : nullptr;
     a.info = info;
+    a.selg = ws.selg;
+    a.rsel = ws.rsel;
+    a.rs_node = (int)ws.rs_node;
+    a.utg = ws.utg;
+    a.rtg = ws.rtg;
 
     // leaves
     a.leaf = 1;
