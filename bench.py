@@ -56,6 +56,137 @@ def cpu_baseline(A_host, n, v, L, panels):
                       f"solves, Schur update); flops = LU flops of those columns"}
 
 
+def ir_leg(cfx, G, torch, n, v, L, conds, precs, seed, check_oracle):
+    """Time-to-solution on A = H1 diag(s) H2 (8 seeded reflectors each side,
+    s log-spaced to cond), 1 RHS: plain FP64 getrf + getrs, FP64 factors +
+    GMRES-IR, and BF16 / FP16 Schur updates + GMRES-IR, all to eta <= 5e-15
+    (the refinement stops there; the plain solve's eta is reported)."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    out = {"n": n, "v": v, "leaves": L, "tol": 5e-15, "gmres_restart": 30, "gmres_tol": 1e-6,
+           "max_outer": 20, "cases": []}
+    work_lu = cfx.workspace(n, v, L, "fp64", 1, dev)
+    for cond in conds:
+        spec = G.householder_spec(n, cond, seed)
+        A = G.householder_matrix(spec, device="cuda:0")
+        b_host = G.rhs(n, 1, seed + 1)[:, 0]
+        xs = G.householder_solution(spec, b_host)[:, 0]
+        b = torch.from_numpy(b_host).to(dev)
+        case = {"cond": cond}
+        # plain FP64 solve
+        F = A.clone()
+        x = b.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ipiv, info = cfx.getrf(F, v=v, leaves=L, lookahead=1, work=work_lu, stream=stream)
+        cfx.getrs(F, ipiv, x, stream=stream)
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+        r = b - A @ x
+        eta_plain = float(r.abs().max() / (A.abs().sum(dim=1).max() * x.abs().max() + b.abs().max()))
+        case["fp64_solve"] = {"seconds": round(t_plain, 4), "eta_fp64_residual": eta_plain,
+                              "forward_error": float(np.abs(x.cpu().numpy() - xs).max() / np.abs(xs).max())}
+        del F
+        torch.cuda.empty_cache()
+        for prec in ["fp64"] + list(precs):
+            nbytes = cfx.gesv_ir_buffer_size(n, 1, precision=prec, v=v, leaves=L, lookahead=1)
+            work = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+            X = torch.empty_like(b)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            X, rep = cfx.gesv_ir(A, b, X=X, work=work, stream=stream, precision=prec, v=v, leaves=L,
+                                 lookahead=1, tol=5e-15, max_outer=out["max_outer"],
+                                 gmres_restart=out["gmres_restart"], gmres_tol=out["gmres_tol"])
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            xh = X.cpu().numpy()
+            res = {"seconds": round(t, 4), "eta": rep["eta"], "eta_first": rep["eta_first"],
+                   "outer": rep["outer"], "gmres_iterations": rep["inner"],
+                   "converged": bool(rep["converged"]),
+                   "forward_error": float(np.abs(xh - xs).max() / np.abs(xs).max()),
+                   "speedup_vs_fp64_solve": round(t_plain / t, 3)}
+            if check_oracle and prec != "fp64":
+                from oracle import oracle as O
+                res["eta_oracle"] = O.eta(A.cpu().numpy(), xh, b_host)
+            case[f"{prec}_ir"] = res
+            log(f"ir cond {cond:g} {prec}: {res}")
+            del work
+            torch.cuda.empty_cache()
+        fp64_ir = case["fp64_ir"]["seconds"]
+        for prec in precs:
+            case[f"{prec}_ir"]["speedup_vs_fp64_ir"] = round(fp64_ir / case[f"{prec}_ir"]["seconds"], 3)
+        out["cases"].append(case)
+        del A
+        torch.cuda.empty_cache()
+    return out
+
+
+def batched_leg(cfx, G, torch, count, seed, steps):
+    """cfx_gesv_batched on `count` systems shaped like the batched workload:
+    n ~ U{16..512}, nrhs ~ U{1..8}, A ~ N(0,1) + shift I with shift 0 or
+    2 sqrt(n) (equal odds).  Entries come from a seeded device generator
+    into two pooled buffers (one view per system, lda = n); a pristine copy
+    restores them before every timed launch."""
+    dev = torch.device("cuda:0")
+    spec = G.batched_spec(count, seed)
+    n = spec.sizes.astype(np.int64)
+    r = spec.nrhs.astype(np.int64)
+    offA = np.concatenate([[0], np.cumsum(n * n)])
+    offB = np.concatenate([[0], np.cumsum(n * r)])
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    poolA0 = torch.randn(int(offA[-1]), dtype=torch.float64, device=dev, generator=gen)
+    poolB0 = torch.randn(int(offB[-1]), dtype=torch.float64, device=dev, generator=gen)
+    for i in range(count):   # diagonal shifts
+        if spec.shift[i]:
+            k = int(n[i])
+            poolA0[int(offA[i]):int(offA[i + 1])].view(k, k).diagonal().add_(float(spec.shift[i]))
+    poolA = poolA0.clone()
+    poolB = poolB0.clone()
+    As = [poolA[int(offA[i]):int(offA[i + 1])].view(int(n[i]), int(n[i])) for i in range(count)]
+    Bs = [poolB[int(offB[i]):int(offB[i + 1])].view(int(n[i]), int(r[i])) for i in range(count)]
+    batch = cfx.Batch(As, Bs)
+    tuned = cfx.batched_tune()
+    log(f"batched: tuned panel widths {tuned}")
+    stream = torch.cuda.current_stream()
+    times = []
+    for it in range(steps + 1):
+        poolA.copy_(poolA0)
+        poolB.copy_(poolB0)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        info = cfx.gesv_batched(batch, graph=True, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if it:   # the first call captures the graph: not timed
+            times.append(e0.elapsed_time(e1))
+    info_h = info.cpu().numpy()
+    ms = float(np.median(times))
+    lu_flops = float(np.sum(2.0 * n.astype(np.float64) ** 3 / 3.0))
+    solve_flops = float(np.sum(2.0 * n.astype(np.float64) ** 2 * r))
+    out = {"count": count, "seed": seed, "launch_ms": round(ms, 3), "launch_ms_all": [round(t, 3) for t in times],
+           "lu_tflops": round(lu_flops / (ms / 1e3) / 1e12, 3),
+           "lu_plus_solve_tflops": round((lu_flops + solve_flops) / (ms / 1e3) / 1e12, 3),
+           "systems_per_s": round(count / (ms / 1e3), 1), "tuned_vb": tuned,
+           "info_nonzero": int(np.count_nonzero(info_h)),
+           "compulsory_bytes": float(np.sum(16.0 * n.astype(np.float64) ** 2 + 16.0 * n * r))}
+    # spot check a few systems against the oracle (A restored from pristine)
+    from oracle import oracle as O
+    worst = 0.0
+    for i in np.linspace(0, count - 1, 6).astype(int):
+        k = int(n[i])
+        A0 = poolA0[int(offA[i]):int(offA[i + 1])].view(k, k).cpu().numpy()
+        B0 = poolB0[int(offB[i]):int(offB[i + 1])].view(k, int(r[i])).cpu().numpy()
+        X = Bs[i].cpu().numpy()
+        worst = max(worst, O.eta(A0, X, B0))
+    out["spot_check_max_eta"] = worst
+    log(f"batched: {out}")
+    del poolA, poolB, poolA0, poolB0, As, Bs, batch
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,6 +199,13 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-panels", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ir", action="store_true", help="skip the mixed-precision IR leg")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched leg")
+    ap.add_argument("--batched-count", type=int, default=20000)
+    ap.add_argument("--ir-conds", default="1e2,1e6,1e10")
+    ap.add_argument("--ir-precs", default="bf16,fp16")
+    ap.add_argument("--ir-oracle-check", action="store_true",
+                    help="also evaluate eta of each IR result with the CPU oracle")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -178,9 +316,15 @@ def main():
                      "avg_launch_flops": schur_avg_flops},
         "checks": {"eta": eta, "projected_residual": proj, "info": info_v},
     }
+    del pristine, A, work
+    torch.cuda.empty_cache()
+    if not args.no_ir:
+        conds = [float(c) for c in args.ir_conds.split(",") if c]
+        precs = [p for p in args.ir_precs.split(",") if p]
+        out["ir"] = ir_leg(cfx, G, torch, n, v, L, conds, precs, args.seed + 7, args.ir_oracle_check)
+    if not args.no_batched:
+        out["batched"] = batched_leg(cfx, G, torch, args.batched_count, args.seed + 11, max(args.steps, 1))
     if not args.no_cpu_baseline:
-        del pristine, A, work
-        torch.cuda.empty_cache()
         out["cpu_baseline"] = cpu_baseline(A_host, n, v, L, args.cpu_panels)
     print(json.dumps(out), flush=True)
 

@@ -61,7 +61,10 @@ enum {
  *               leaves of h = max(v, ceil(r / L)) rows (the last one may be
  *               shorter).  h must not exceed 8192 rows.
  *   precision : CFX_PREC_*; the pivot search, row interchanges and both
- *               triangular solves are always FP64.
+ *               triangular solves are always FP64.  With BF16/FP16 each
+ *               Schur update rounds L21 and U12 to that format, multiplies
+ *               on the matrix cores with FP32 accumulation and subtracts
+ *               the FP32 sum from the FP64 trailing matrix.
  *   lookahead : 0 or 1; 1 overlaps the next panel's tournament with the
  *               rest of the current Schur update on a second stream. */
 typedef struct {
@@ -123,6 +126,104 @@ int cfx_tslu(cfx_handle *h, int64_t rows, int64_t vb, const double *W,
 int cfx_getrs(cfx_handle *h, int64_t n, int64_t nrhs, const double *LU,
               int64_t lda, const int32_t *ipiv, double *B, int64_t ldb,
               void *stream);
+
+/* Mixed-precision solve with iterative refinement.  The paper computes the
+ * factorisation only; refinement is the standard GMRES-IR of Carson and
+ * Higham (SIAM J. Sci. Comput. 40(2), 2018): the tournament-pivoted LU of
+ * Alg. 1, with its Schur updates (FactorizeA11) in lu.precision, is the
+ * left preconditioner M = U^{-1} L^{-1} P of GMRES on M A d = M r; the
+ * residual r = b - A x (compensated FP64 row sums), the GMRES iteration and
+ * the update x += d are FP64.  Refinement of a right-hand side stops when
+ * its normwise backward error
+ *     eta = |b - A x|_inf / (|A|_inf |x|_inf + |b|_inf)
+ * is <= tol, or after max_outer refinement steps.
+ *   lu            : factorisation options (precision CFX_PREC_BF16/FP16 for
+ *                   the mixed-precision factorisation; FP64 also allowed).
+ *   tol           : target eta (>= 0), e.g. 5e-15.
+ *   max_outer     : maximum refinement steps (0 .. 10000).
+ *   gmres_restart : Krylov dimension of one GMRES solve (1 .. 64).
+ *   gmres_tol     : relative reduction of the preconditioned residual that
+ *                   ends one GMRES solve, in (0, 1). */
+typedef struct {
+    cfx_lu_opts lu;
+    double tol;
+    int32_t max_outer;
+    int32_t gmres_restart;
+    double gmres_tol;
+} cfx_ir_opts;
+
+typedef struct {
+    double eta;          /* final eta, maximum over the right-hand sides     */
+    double eta_first;    /* eta of the plain solve with the factors (max)    */
+    int32_t outer;       /* refinement steps, maximum over right-hand sides  */
+    int32_t inner;       /* GMRES iterations, summed over right-hand sides   */
+    int32_t converged;   /* 1 if every right-hand side reached tol           */
+    int32_t info;        /* info of the factorisation (see cfx_getrf)        */
+} cfx_ir_report;
+
+/* Workspace bytes of cfx_gesv_ir (host pointer `bytes`): an n x n factor
+ * copy, pivots, the getrf workspace and (gmres_restart + 8) n-vectors. */
+int cfx_gesv_ir_buffer_size(cfx_handle *h, int64_t n, int64_t nrhs,
+                            const cfx_ir_opts *opts, size_t *bytes);
+
+/* Solve A X = B by factorisation + GMRES-IR.
+ *   A    : device, n x n row-major, stride lda; NOT modified (the library
+ *          factors a copy inside work).
+ *   B    : device, n x nrhs row-major, stride ldb; not modified.
+ *   X    : device, n x nrhs row-major, stride ldx; receives the solution.
+ *   rep  : host pointer, filled before return.
+ *   work : device, >= cfx_gesv_ir_buffer_size bytes, 256-byte aligned.
+ * Host-blocking: returns when X and rep are final (it synchronises
+ * `stream`, on which all of its work runs).  A singular factorisation is
+ * reported through rep->info (and a non-finite eta), not the return value. */
+int cfx_gesv_ir(cfx_handle *h, int64_t n, int64_t nrhs, const double *A,
+                int64_t lda, const double *B, int64_t ldb, double *X,
+                int64_t ldx, const cfx_ir_opts *opts, cfx_ir_report *rep,
+                void *work, size_t work_bytes, void *stream);
+
+/* Batched LU + solve of `count` independent systems A_i X_i = B_i in one
+ * persistent launch (preceded by a one-workgroup sort of the systems by
+ * size).  Each system is factored as cfx_getrf with leaves = 1 (TP(v, 1):
+ * every panel's pivots come from GEPP of the whole panel, ties to the
+ * smaller row, Sec. 7.3), with the panel width v taken per size class from
+ * the handle's tuning table, then solved like cfx_getrs.
+ * All array arguments are DEVICE arrays of `count` entries:
+ *   n[i]     : order, 0 <= n[i] <= 512.
+ *   nrhs[i]  : right-hand sides, 0 <= nrhs[i] <= 16.
+ *   A[i]     : device pointer, n x n row-major, stride lda[i] >= max(1, n);
+ *              overwritten by L and U (as cfx_getrf).
+ *   B[i]     : device pointer, n x nrhs row-major, stride ldb[i] >=
+ *              max(1, nrhs); overwritten by X.
+ *   ipiv[i]  : device pointer to int32[n[i]] (as cfx_getrf).
+ *   info[i]  : 0, j+1 for the first exactly zero U[j][j] (that system's X
+ *              is then not finite), or -k when that system's k-th
+ *              descriptor is invalid (1 n, 2 A/ipiv null, 3 lda, 4 nrhs,
+ *              5 B null, 6 ldb); an invalid system is skipped.
+ *   work     : device, cfx_gesv_batched_buffer_size bytes, 256-byte aligned.
+ *   flags    : 0, or CFX_BATCHED_NO_GRAPH.  By default the launches are
+ *              captured into a HIP graph on the first call and the graph is
+ *              replayed by later calls with identical arguments (same
+ *              count, array pointers and work); the array CONTENTS are read
+ *              at run time, so new systems in the same buffers reuse it.
+ * Asynchronous on `stream`. */
+enum { CFX_BATCHED_NO_GRAPH = 1 };
+
+int cfx_gesv_batched_buffer_size(cfx_handle *h, int32_t count, size_t *bytes);
+int cfx_gesv_batched(cfx_handle *h, int32_t count, const int32_t *n,
+                     const int32_t *nrhs, double *const *A, const int64_t *lda,
+                     double *const *B, const int64_t *ldb, int32_t *const *ipiv,
+                     int32_t *info, void *work, size_t work_bytes, int32_t flags,
+                     void *stream);
+
+/* Autotuner of the batched panel width: for each size class (n <= 32, 64,
+ * 128, 256, 512) it times the batched launch on synthetic diagonally
+ * shifted systems of the class's largest order with v in {8, 16, 32} and
+ * keeps the fastest in the handle's table.  Allocates and frees its own
+ * device buffers (about 2.2 GB); host-blocking on `stream`. */
+int cfx_batched_tune(cfx_handle *h, void *stream);
+/* Read / set the table (host int32[5], entries in {8, 16, 32}). */
+int cfx_batched_tuning(cfx_handle *h, int32_t *vb);
+int cfx_batched_set_tuning(cfx_handle *h, const int32_t *vb);
 
 /* Per-phase device time of the factorisation steps, for measurement.
  * Between cfx_profile_begin and cfx_profile_end every cfx_getrf on the

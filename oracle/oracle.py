@@ -160,3 +160,46 @@ def lu_residual(A0: np.ndarray, LU: np.ndarray, ipiv: np.ndarray) -> float:
 
 def ipiv_sign(ipiv: np.ndarray) -> int:
     return -1 if int(np.sum(ipiv != np.arange(len(ipiv)))) % 2 else 1
+
+
+# --------------------------------------------------------------------------
+# Mixed-precision Schur update (FactorizeA11 of Alg. 1 with low-precision
+# operands).  The paper fixes no low precision; the reading used here: each
+# FP64 operand is rounded to FP32, then to BF16 or FP16, round-to-nearest-
+# even at both steps; products of two such values are exact in FP64, and
+# the accumulation is exact enough in FP64 that this is the reference sum.
+# --------------------------------------------------------------------------
+
+def round_lowp(x, precision: str) -> np.ndarray:
+    """FP64 -> FP32 -> {BF16, FP16} (RNE each step), returned as FP64."""
+    with np.errstate(over="ignore"):
+        x32 = np.asarray(x, dtype=np.float64).astype(np.float32)
+    if precision == "fp16":
+        with np.errstate(over="ignore"):
+            return x32.astype(np.float16).astype(np.float64)
+    if precision != "bf16":
+        raise ValueError(precision)
+    bits = x32.view(np.uint32).astype(np.uint64)
+    # BF16 keeps the top 16 bits of an FP32; round the dropped 16 bits to
+    # nearest, ties to the even kept pattern.
+    kept = (bits + 0x7FFF + ((bits >> 16) & 1)) >> 16
+    out = (kept << 16).astype(np.uint32).view(np.float32).astype(np.float64)
+    nan = np.isnan(x32)
+    out[nan] = np.nan
+    return out
+
+
+def tail_after_lowp_update(A: np.ndarray, v: int, L: int, precision: str):
+    """The first panel of TP(v, L) in FP64 (oracle getrf limited to one
+    panel), then the trailing matrix S = A22 - lowp(L21) lowp(U12) with the
+    rounded operands multiplied and summed in FP64.  Returns (first-panel
+    Factorization, S)."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    f = getrf(A, v, L, npanels=1)
+    n = A.shape[0]
+    vb = min(v, n)
+    PA = A[ipiv_to_perm(np.concatenate([f.ipiv[:vb], np.arange(vb, n)]).astype(np.int32))]
+    L21 = f.LU[vb:, :vb]
+    U12 = f.LU[:vb, vb:]
+    S = PA[vb:, vb:] - round_lowp(L21, precision) @ round_lowp(U12, precision)
+    return f, S

@@ -27,6 +27,19 @@ class LuOpts(C.Structure):
                 ("lookahead", C.c_int32)]
 
 
+class IrOpts(C.Structure):
+    _fields_ = [("lu", LuOpts), ("tol", C.c_double), ("max_outer", C.c_int32),
+                ("gmres_restart", C.c_int32), ("gmres_tol", C.c_double)]
+
+
+class IrReport(C.Structure):
+    _fields_ = [("eta", C.c_double), ("eta_first", C.c_double), ("outer", C.c_int32),
+                ("inner", C.c_int32), ("converged", C.c_int32), ("info", C.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class Profile(C.Structure):
     _fields_ = [("tslu_ms", C.c_double), ("laswp_ms", C.c_double), ("trsm_ms", C.c_double),
                 ("schur_ms", C.c_double), ("schur_flops", C.c_double),
@@ -59,10 +72,21 @@ def lib():
         L.cfx_getrf.argtypes = [vp, i64, vp, i64, vp, vp, C.POINTER(LuOpts), vp, sz, vp]
         L.cfx_tslu.argtypes = [vp, i64, i64, vp, i64, i64, i32, vp, vp, sz, vp]
         L.cfx_getrs.argtypes = [vp, i64, i64, vp, i64, vp, vp, i64, vp]
+        L.cfx_gesv_ir_buffer_size.argtypes = [vp, i64, i64, C.POINTER(IrOpts), C.POINTER(sz)]
+        L.cfx_gesv_ir.argtypes = [vp, i64, i64, vp, i64, vp, i64, vp, i64, C.POINTER(IrOpts),
+                                  C.POINTER(IrReport), vp, sz, vp]
+        L.cfx_gesv_batched_buffer_size.argtypes = [vp, i32, C.POINTER(sz)]
+        L.cfx_gesv_batched.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, i32, vp]
+        L.cfx_batched_tune.argtypes = [vp, vp]
+        L.cfx_batched_tuning.argtypes = [vp, vp]
+        L.cfx_batched_set_tuning.argtypes = [vp, vp]
         L.cfx_profile_begin.argtypes = [vp]
         L.cfx_profile_end.argtypes = [vp, C.POINTER(Profile)]
         for f in ("cfx_create", "cfx_destroy", "cfx_getrf_buffer_size", "cfx_getrf",
-                  "cfx_tslu", "cfx_getrs", "cfx_profile_begin", "cfx_profile_end"):
+                  "cfx_tslu", "cfx_getrs", "cfx_gesv_ir_buffer_size", "cfx_gesv_ir",
+                  "cfx_gesv_batched_buffer_size", "cfx_gesv_batched", "cfx_batched_tune",
+                  "cfx_batched_tuning", "cfx_batched_set_tuning",
+                  "cfx_profile_begin", "cfx_profile_end"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -181,6 +205,114 @@ def getrs(LU, ipiv, B, stream=None, handle=None):
     _check("cfx_getrs", lib().cfx_getrs(h.h, n, nrhs, _ptr(LU), lda, _ptr(ipiv), _ptr(Bm), ldb,
                                         _stream(stream)))
     return B
+
+
+def ir_opts(precision="bf16", v=256, leaves=64, lookahead=0, tol=5e-15, max_outer=20,
+            gmres_restart=30, gmres_tol=1e-6):
+    return IrOpts(LuOpts(v, leaves, PREC[precision], lookahead), tol, max_outer, gmres_restart,
+                  gmres_tol)
+
+
+def gesv_ir_buffer_size(n, nrhs=1, handle=None, **kw):
+    h = handle or default_handle()
+    o = ir_opts(**kw)
+    b = C.c_size_t()
+    _check("cfx_gesv_ir_buffer_size",
+           lib().cfx_gesv_ir_buffer_size(h.h, n, nrhs, C.byref(o), C.byref(b)))
+    return b.value
+
+
+def gesv_ir(A, B, X=None, work=None, stream=None, handle=None, **kw):
+    """cfx_gesv_ir: X = A^{-1} B by (mixed-precision) LU + GMRES-IR.  A and B
+    are not modified.  Returns (X, report dict).  Keyword options as ir_opts."""
+    h = handle or default_handle()
+    lda = _mat(A, "A")
+    n = A.shape[0]
+    vec = B.dim() == 1
+    Bm = B.view(-1, 1) if vec else B
+    ldb = _mat(Bm, "B")
+    nrhs = Bm.shape[1]
+    if X is None:
+        X = torch.empty_like(Bm)
+    Xm = X.view(-1, 1) if X.dim() == 1 else X
+    ldx = _mat(Xm, "X")
+    o = ir_opts(**kw)
+    if work is None:
+        nbytes = gesv_ir_buffer_size(n, nrhs, h, **kw)
+        work = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=A.device)
+    rep = IrReport()
+    _check("cfx_gesv_ir", lib().cfx_gesv_ir(h.h, n, nrhs, _ptr(A), lda, _ptr(Bm), ldb, _ptr(Xm), ldx,
+                                            C.byref(o), C.byref(rep), _ptr(work), work.numel(),
+                                            _stream(stream)))
+    return (X.view(-1) if vec else X), rep.as_dict()
+
+
+class Batch:
+    """Device descriptor arrays of a batch of systems (kept alive with the
+    tensors they point to).  As[i]: n_i x n_i, Bs[i]: n_i x nrhs_i (or n_i),
+    float64 CUDA tensors, row-major (row stride may exceed the width)."""
+
+    def __init__(self, As, Bs, device=None):
+        if len(As) != len(Bs):
+            raise ValueError("As and Bs differ in length")
+        dev = device or (As[0].device if As else "cuda")
+        self.As = list(As)
+        self.Bs = [b.view(-1, 1) if b.dim() == 1 else b for b in Bs]
+        self.count = len(As)
+        n = [a.shape[0] for a in self.As]
+        lda = [_mat(a, "A") for a in self.As]
+        nrhs = [b.shape[1] for b in self.Bs]
+        ldb = [_mat(b, "B") for b in self.Bs]
+        self.ipiv = [torch.empty(max(k, 1), dtype=torch.int32, device=dev) for k in n]
+        i32 = lambda v: torch.tensor(v, dtype=torch.int32, device=dev)
+        i64 = lambda v: torch.tensor(v, dtype=torch.int64, device=dev)
+        self.d_n, self.d_nrhs = i32(n), i32(nrhs)
+        self.d_lda, self.d_ldb = i64(lda), i64(ldb)
+        self.d_A = i64([a.data_ptr() for a in self.As])
+        self.d_B = i64([b.data_ptr() for b in self.Bs])
+        self.d_ipiv = i64([p.data_ptr() for p in self.ipiv])
+        self.info = torch.zeros(max(self.count, 1), dtype=torch.int32, device=dev)
+        self.work = torch.empty(max(gesv_batched_buffer_size(self.count), 256), dtype=torch.uint8,
+                                device=dev)
+
+
+def gesv_batched_buffer_size(count, handle=None):
+    h = handle or default_handle()
+    b = C.c_size_t()
+    _check("cfx_gesv_batched_buffer_size", lib().cfx_gesv_batched_buffer_size(h.h, count, C.byref(b)))
+    return b.value
+
+
+def gesv_batched(batch: Batch, graph=True, stream=None, handle=None):
+    """cfx_gesv_batched on a Batch: factors in place in batch.As, solutions
+    in batch.Bs, pivots in batch.ipiv; returns batch.info (device int32)."""
+    h = handle or default_handle()
+    flags = 0 if graph else 1
+    _check("cfx_gesv_batched", lib().cfx_gesv_batched(
+        h.h, batch.count, _ptr(batch.d_n), _ptr(batch.d_nrhs), _ptr(batch.d_A), _ptr(batch.d_lda),
+        _ptr(batch.d_B), _ptr(batch.d_ldb), _ptr(batch.d_ipiv), _ptr(batch.info), _ptr(batch.work),
+        batch.work.numel(), flags, _stream(stream)))
+    return batch.info[:batch.count]
+
+
+def batched_tune(stream=None, handle=None):
+    """cfx_batched_tune: time v in {8, 16, 32} per size class; returns the table."""
+    h = handle or default_handle()
+    _check("cfx_batched_tune", lib().cfx_batched_tune(h.h, _stream(stream)))
+    return batched_tuning(h)
+
+
+def batched_tuning(handle=None):
+    h = handle or default_handle()
+    t = (C.c_int32 * 5)()
+    _check("cfx_batched_tuning", lib().cfx_batched_tuning(h.h, t))
+    return list(t)
+
+
+def batched_set_tuning(vb, handle=None):
+    h = handle or default_handle()
+    t = (C.c_int32 * 5)(*vb)
+    _check("cfx_batched_set_tuning", lib().cfx_batched_set_tuning(h.h, t))
 
 
 def profile_begin(handle=None):

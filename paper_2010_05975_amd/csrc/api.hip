@@ -1,6 +1,7 @@
 // C ABI entry points (include/cfx.h): argument checks, workspace carving and
 // the host loop over panels of Alg. 1 (TournPivot, interchanges,
 // FactorizeA10/A01, FactorizeA11 per panel).
+#include <cmath>
 #include <new>
 #include <vector>
 
@@ -54,6 +55,18 @@ struct cfx_handle {
     void *scratch = nullptr;        // getrs permutation + gather buffer
     size_t scratch_bytes = 0;
     cfx::Profiler prof;
+    int cu_count = 256;
+    // batched: panel width per size class (the tuner's table) and the graph
+    // of the last batched call, replayed when the arguments repeat
+    int32_t bvb[cfx::kBatchClasses] = {8, 16, 16, 32, 32};
+    int64_t bvb_version = 0;
+    hipGraph_t bgraph = nullptr;
+    hipGraphExec_t bexec = nullptr;
+    struct {
+        int32_t count;
+        const void *p[10];
+        int64_t version;
+    } bkey{};
 };
 
 namespace cfx {
@@ -89,7 +102,7 @@ static Layout layout(int64_t n, int v, int leaves, int precision)
     L.off_utg = o;   o = align_up(o + (size_t)L.max_nodes * 32 * kMaxV * sizeof(double));
     L.off_rtg = o;   o = align_up(o + (size_t)L.max_nodes * 32 * 40 * sizeof(double));
     L.off_mp = o;
-    (void)precision;
+    if (precision != CFX_PREC_FP64) o = align_up(o + lp_pack_bytes(n, v));
     L.total = o;
     return L;
 }
@@ -129,7 +142,8 @@ static int check_opts(const cfx_lu_opts *o)
     if (!o) return 1;
     if (o->v < 1 || o->v > kMaxV) return 1;
     if (o->leaves < 1) return 1;
-    if (o->precision != CFX_PREC_FP64) return 2;   // mixed precision: not in this build yet
+    if (o->precision != CFX_PREC_FP64 && o->precision != CFX_PREC_BF16 && o->precision != CFX_PREC_FP16)
+        return 2;
     if (o->lookahead < 0 || o->lookahead > 1) return 1;
     return 0;
 }
@@ -143,6 +157,50 @@ static int ensure_scratch(cfx_handle *h, size_t bytes)
     CFX_HIP(hipMalloc(&h->scratch, bytes));
     h->scratch_bytes = bytes;
     return CFX_OK;
+}
+
+static int check_ir_opts(const cfx_ir_opts *o)
+{
+    if (!o) return 1;
+    if (int c = check_opts(&o->lu)) return c;
+    if (!(o->tol >= 0)) return 1;
+    if (o->max_outer < 0 || o->max_outer > 10000) return 1;
+    if (o->gmres_restart < 1 || o->gmres_restart > 64) return 1;
+    if (!(o->gmres_tol > 0 && o->gmres_tol < 1)) return 1;
+    return 0;
+}
+
+// Workspace of cfx_gesv_ir: factor copy, ipiv, perm, info, the getrf
+// workspace and the refinement vectors.
+struct IrLayout {
+    size_t off_F, off_ipiv, off_perm, off_info, off_getrf, getrf_bytes, off_vec, total;
+};
+
+static IrLayout ir_layout(int64_t n, const cfx_ir_opts *o)
+{
+    IrLayout L{};
+    size_t p = 0;
+    L.off_F = p;     p = align_up(p + (size_t)n * n * sizeof(double));
+    L.off_ipiv = p;  p = align_up(p + (size_t)n * sizeof(int32_t));
+    L.off_perm = p;  p = align_up(p + (size_t)n * sizeof(int32_t));
+    L.off_info = p;  p = align_up(p + sizeof(int32_t));
+    L.off_getrf = p;
+    L.getrf_bytes = workspace_bytes(n, o->lu.v, o->lu.leaves, o->lu.precision);
+    p = align_up(p + L.getrf_bytes);
+    L.off_vec = p;   p = align_up(p + ir_vec_bytes(n, o->gmres_restart));
+    L.total = p;
+    return L;
+}
+
+// FactorizeA11 on C[0:m, col0:col0+ncols] of the trailing matrix.  In the
+// mixed-precision path the operands were packed once for the panel.
+static int schur_update(int precision, const Workspace &ws, const double *L21, const double *U12,
+                        double *C, int64_t lda, int64_t m, int64_t col0, int64_t ncols, int vb,
+                        hipStream_t st)
+{
+    if (precision == CFX_PREC_FP64)
+        return launch_schur_f64(L21, lda, U12 + col0, lda, C + col0, lda, m, ncols, vb, st);
+    return launch_schur_lp(precision, ws.scratch, m, vb, col0, ncols, C, lda, st);
 }
 
 }  // namespace cfx
@@ -168,6 +226,10 @@ int cfx_create(cfx_handle **h)
         delete p;
         return CFX_EHIP;
     }
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess &&
+        cus > 0)
+        p->cu_count = cus;
     *h = p;
     return CFX_OK;
 }
@@ -216,6 +278,8 @@ int cfx_destroy(cfx_handle *h)
     if (!h) return -1;
     for (hipEvent_t e : h->prof.pool) (void)hipEventDestroy(e);
     if (h->scratch) (void)hipFree(h->scratch);
+    if (h->bexec) (void)hipGraphExecDestroy(h->bexec);
+    if (h->bgraph) (void)hipGraphDestroy(h->bgraph);
     if (h->ev_panel) (void)hipEventDestroy(h->ev_panel);
     if (h->ev_tslu) (void)hipEventDestroy(h->ev_tslu);
     if (h->side) (void)hipStreamDestroy(h->side);
@@ -259,6 +323,7 @@ int cfx_getrf(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *ipiv, i
     if ((rc = carve_workspace(work, work_bytes, n, v, L, opts->precision, &ws))) return rc;
 
     Profiler &pf = h->prof;
+    const int prec = opts->precision;
     if (!opts->lookahead) {
         for (int64_t k = 0; k < n; k += v) {
             const int vb = (int)((n - k) < v ? (n - k) : v);
@@ -274,10 +339,11 @@ int cfx_getrf(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *ipiv, i
                 e = pf.begin(st);
                 if ((rc = launch_trsm(A, lda, k, vb, m, st))) return rc;
                 pf.end(PH_TRSM, e, st);
+                double *L21 = panel + vb * lda, *U12 = panel + vb, *C = panel + vb * lda + vb;
                 e = pf.begin(st);
-                if ((rc = launch_schur_f64(panel + vb * lda, lda, panel + vb, lda, panel + vb * lda + vb,
-                                           lda, m, m, vb, st)))
+                if (prec != CFX_PREC_FP64 && (rc = launch_pack_lp(prec, L21, U12, lda, m, vb, ws.scratch, st)))
                     return rc;
+                if ((rc = schur_update(prec, ws, L21, U12, C, lda, m, 0, m, vb, st))) return rc;
                 pf.end(PH_SCHUR, e, st, 2.0 * (double)m * (double)m * vb);
             }
             if (pf.on) ++pf.panels;
@@ -314,7 +380,9 @@ int cfx_getrf(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *ipiv, i
             const int vbn = (int)(m < v ? m : v);          // next panel width
             double *L21 = panel + vb * lda, *U12 = panel + vb, *C = panel + vb * lda + vb;
             e = pf.begin(st);
-            if ((rc = launch_schur_f64(L21, lda, U12, lda, C, lda, m, vbn, vb, st))) return rc;
+            if (prec != CFX_PREC_FP64 && (rc = launch_pack_lp(prec, L21, U12, lda, m, vb, ws.scratch, st)))
+                return rc;
+            if ((rc = schur_update(prec, ws, L21, U12, C, lda, m, 0, vbn, vb, st))) return rc;
             pf.end(PH_SCHUR, e, st, 2.0 * (double)m * vbn * vb);
             // next panel's tournament on the side stream
             CFX_HIP(hipEventRecord(h->ev_panel, st));
@@ -329,14 +397,262 @@ int cfx_getrf(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *ipiv, i
             // the rest of the update
             if (m > vbn) {
                 e = pf.begin(st);
-                if ((rc = launch_schur_f64(L21, lda, U12 + vbn, lda, C + vbn, lda, m, m - vbn, vb, st)))
-                    return rc;
+                if ((rc = schur_update(prec, ws, L21, U12, C, lda, m, vbn, m - vbn, vb, st))) return rc;
                 pf.end(PH_SCHUR, e, st, 2.0 * (double)m * (double)(m - vbn) * vb);
             }
         }
         if (pf.on) ++pf.panels;
     }
     if (tslu_on_side) CFX_HIP(hipStreamWaitEvent(st, h->ev_tslu, 0));
+    return CFX_OK;
+}
+
+int cfx_gesv_ir_buffer_size(cfx_handle *h, int64_t n, int64_t nrhs, const cfx_ir_opts *opts, size_t *bytes)
+{
+    if (!h) return -1;
+    if (n < 0) return -2;
+    if (nrhs < 0) return -3;
+    if (int c = check_ir_opts(opts)) return c == 2 ? CFX_ENOTSUP : -4;
+    if (!bytes) return -5;
+    *bytes = ir_layout(n, opts).total;
+    return CFX_OK;
+}
+
+int cfx_gesv_ir(cfx_handle *h, int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *B,
+                int64_t ldb, double *X, int64_t ldx, const cfx_ir_opts *opts, cfx_ir_report *rep, void *work,
+                size_t work_bytes, void *stream)
+{
+    if (!h) return -1;
+    if (n < 0 || n > INT32_MAX) return -2;
+    if (nrhs < 0) return -3;
+    if (!A && n > 0) return -4;
+    if (lda < (n > 1 ? n : 1)) return -5;
+    if (!B && n > 0 && nrhs > 0) return -6;
+    if (ldb < (nrhs > 1 ? nrhs : 1)) return -7;
+    if (!X && n > 0 && nrhs > 0) return -8;
+    if (ldx < (nrhs > 1 ? nrhs : 1)) return -9;
+    if (int c = check_ir_opts(opts)) return c == 2 ? CFX_ENOTSUP : -10;
+    if (!rep) return -11;
+    const IrLayout lay = ir_layout(n, opts);
+    if (n > 0 && (!work || (reinterpret_cast<uintptr_t>(work) & 255))) return -12;
+    if (n > 0 && work_bytes < lay.total) return CFX_ENOMEM;
+    cfx_ir_report r{};
+    if (n == 0) {
+        r.converged = 1;
+        *rep = r;
+        return CFX_OK;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char *w = static_cast<char *>(work);
+    double *F = reinterpret_cast<double *>(w + lay.off_F);
+    int32_t *ipiv = reinterpret_cast<int32_t *>(w + lay.off_ipiv);
+    int32_t *perm = reinterpret_cast<int32_t *>(w + lay.off_perm);
+    int32_t *dinfo = reinterpret_cast<int32_t *>(w + lay.off_info);
+    CFX_HIP(hipMemcpy2DAsync(F, (size_t)n * sizeof(double), A, (size_t)lda * sizeof(double),
+                             (size_t)n * sizeof(double), (size_t)n, hipMemcpyDeviceToDevice, st));
+    int rc = cfx_getrf(h, n, F, n, ipiv, dinfo, &opts->lu, w + lay.off_getrf, lay.getrf_bytes, stream);
+    if (rc) return rc;
+    if ((rc = launch_perm(n, ipiv, perm, st))) return rc;
+    CFX_HIP(hipMemcpyAsync(&r.info, dinfo, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    CFX_HIP(hipStreamSynchronize(st));
+    const IrVectors v = carve_ir(w + lay.off_vec, n, opts->gmres_restart);
+    const IrParams p{opts->tol, opts->max_outer, opts->gmres_tol};
+    r.converged = 1;
+    r.eta = 0.0;
+    r.eta_first = 0.0;
+    for (int64_t c = 0; c < nrhs; ++c) {
+        if ((rc = launch_copy_rows(n, 1, B + c, ldb, v.b, 1, st))) return rc;
+        if ((rc = launch_gather_rows(n, 1, v.b, 1, perm, v.x, 1, st))) return rc;
+        if ((rc = launch_trsv(n, 1, F, n, v.x, 1, st))) return rc;
+        IrResult res{};
+        if ((rc = ir_refine(A, lda, F, n, perm, v, p, &res, st))) return rc;
+        if ((rc = launch_copy_rows(n, 1, v.x, 1, X + c, ldx, st))) return rc;
+        r.eta = std::fmax(r.eta, res.eta);
+        r.eta_first = std::fmax(r.eta_first, res.eta_first);
+        if (!(res.eta == res.eta)) r.eta = res.eta;
+        if (res.outer > r.outer) r.outer = res.outer;
+        r.inner += res.inner;
+        r.converged &= res.converged;
+    }
+    CFX_HIP(hipStreamSynchronize(st));
+    *rep = r;
+    return CFX_OK;
+}
+
+int cfx_gesv_batched_buffer_size(cfx_handle *h, int32_t count, size_t *bytes)
+{
+    if (!h) return -1;
+    if (count < 0) return -2;
+    if (!bytes) return -3;
+    *bytes = batched_work_bytes(count);
+    return CFX_OK;
+}
+
+int cfx_gesv_batched(cfx_handle *h, int32_t count, const int32_t *n, const int32_t *nrhs, double *const *A,
+                     const int64_t *lda, double *const *B, const int64_t *ldb, int32_t *const *ipiv,
+                     int32_t *info, void *work, size_t work_bytes, int32_t flags, void *stream)
+{
+    if (!h) return -1;
+    if (count < 0) return -2;
+    if (count == 0) return CFX_OK;
+    if (!n) return -3;
+    if (!nrhs) return -4;
+    if (!A) return -5;
+    if (!lda) return -6;
+    if (!B) return -7;
+    if (!ldb) return -8;
+    if (!ipiv) return -9;
+    if (!info) return -10;
+    if (!work || (reinterpret_cast<uintptr_t>(work) & 255)) return -11;
+    if (work_bytes < batched_work_bytes(count)) return CFX_ENOMEM;
+    if (flags & ~CFX_BATCHED_NO_GRAPH) return -13;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int grid = h->cu_count;   // one resident workgroup per compute unit
+    if (flags & CFX_BATCHED_NO_GRAPH)
+        return launch_gesv_batched(count, n, nrhs, A, lda, B, ldb, ipiv, info, work, h->bvb, grid, st);
+    const void *key[10] = {n, nrhs, A, lda, B, ldb, ipiv, info, work, nullptr};
+    bool same = h->bexec && h->bkey.count == count && h->bkey.version == h->bvb_version;
+    for (int i = 0; same && i < 10; ++i) same = h->bkey.p[i] == key[i];
+    if (!same) {
+        if (h->bexec) (void)hipGraphExecDestroy(h->bexec);
+        if (h->bgraph) (void)hipGraphDestroy(h->bgraph);
+        h->bexec = nullptr;
+        h->bgraph = nullptr;
+        CFX_HIP(hipStreamBeginCapture(h->side, hipStreamCaptureModeThreadLocal));
+        int rc = launch_gesv_batched(count, n, nrhs, A, lda, B, ldb, ipiv, info, work, h->bvb, grid, h->side);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(h->side, &g);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess || !g) return CFX_EHIP;
+        hipGraphExec_t x = nullptr;
+        if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return CFX_EHIP;
+        }
+        h->bgraph = g;
+        h->bexec = x;
+        h->bkey.count = count;
+        h->bkey.version = h->bvb_version;
+        for (int i = 0; i < 10; ++i) h->bkey.p[i] = key[i];
+    }
+    CFX_HIP(hipGraphLaunch(h->bexec, st));
+    return CFX_OK;
+}
+
+int cfx_batched_tune(cfx_handle *h, void *stream)
+{
+    if (!h) return -1;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int grid = h->cu_count;
+    const int count = 4 * grid;
+    const int reps[kBatchClasses] = {32, 64, 128, 256, 512};
+    const int cands[3] = {8, 16, 32};
+    const int nmax = reps[kBatchClasses - 1];
+    double *A = nullptr, *B = nullptr;
+    int32_t *ipiv = nullptr, *info = nullptr, *nv = nullptr, *rv = nullptr;
+    int64_t *ldav = nullptr, *ldbv = nullptr;
+    double **Ap = nullptr, **Bp = nullptr;
+    int32_t **Ip = nullptr;
+    void *work = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = CFX_OK;
+    std::vector<double *> hA(count), hB(count);
+    std::vector<int32_t *> hI(count);
+    std::vector<int32_t> hn(count), hr(count, 1);
+    std::vector<int64_t> hlda(count), hldb(count, 1);
+    int32_t table[kBatchClasses];
+    for (int c = 0; c < kBatchClasses; ++c) table[c] = h->bvb[c];
+    auto fail = [&](int code) { rc = code; };
+    if (hipMalloc(&A, (size_t)count * nmax * nmax * sizeof(double)) != hipSuccess ||
+        hipMalloc(&B, (size_t)count * nmax * sizeof(double)) != hipSuccess ||
+        hipMalloc(&ipiv, (size_t)count * nmax * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&info, (size_t)count * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&nv, (size_t)count * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&rv, (size_t)count * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&ldav, (size_t)count * sizeof(int64_t)) != hipSuccess ||
+        hipMalloc(&ldbv, (size_t)count * sizeof(int64_t)) != hipSuccess ||
+        hipMalloc(&Ap, (size_t)count * sizeof(double *)) != hipSuccess ||
+        hipMalloc(&Bp, (size_t)count * sizeof(double *)) != hipSuccess ||
+        hipMalloc(&Ip, (size_t)count * sizeof(int32_t *)) != hipSuccess ||
+        hipMalloc(&work, batched_work_bytes(count)) != hipSuccess ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        fail(CFX_ENOMEM);
+    for (int c = 0; c < kBatchClasses && rc == CFX_OK; ++c) {
+        const int n = reps[c];
+        for (int i = 0; i < count; ++i) {
+            hA[i] = A + (size_t)i * n * n;
+            hB[i] = B + (size_t)i * n;
+            hI[i] = ipiv + (size_t)i * n;
+            hn[i] = n;
+            hlda[i] = n;
+        }
+        if (hipMemcpyAsync(Ap, hA.data(), count * sizeof(double *), hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(Bp, hB.data(), count * sizeof(double *), hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(Ip, hI.data(), count * sizeof(int32_t *), hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(nv, hn.data(), count * sizeof(int32_t), hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(rv, hr.data(), count * sizeof(int32_t), hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(ldav, hlda.data(), count * sizeof(int64_t), hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(ldbv, hldb.data(), count * sizeof(int64_t), hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            fail(CFX_EHIP);
+            break;
+        }
+        float best = 0.f;
+        int bestv = table[c];
+        for (int ci = 0; ci < 3 && rc == CFX_OK; ++ci) {
+            table[c] = cands[ci];
+            float tmin = 0.f;
+            for (int rep = 0; rep < 2 && rc == CFX_OK; ++rep) {
+                int r2 = launch_batched_synth(A, n, count, 1234 + rep, st);
+                if (!r2) r2 = launch_batched_synth(B, 1, (int64_t)count * n, 99, st);
+                if (!r2 && hipEventRecord(e0, st) != hipSuccess) r2 = CFX_EHIP;
+                if (!r2) r2 = launch_gesv_batched(count, nv, rv, Ap, ldav, Bp, ldbv, Ip, info, work, table, grid, st);
+                if (!r2 && hipEventRecord(e1, st) != hipSuccess) r2 = CFX_EHIP;
+                float ms = 0.f;
+                if (!r2 && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                    r2 = CFX_EHIP;
+                if (r2) fail(r2);
+                else if (rep == 0 || ms < tmin) tmin = ms;
+            }
+            if (rc == CFX_OK && (ci == 0 || tmin < best)) {
+                best = tmin;
+                bestv = cands[ci];
+            }
+        }
+        table[c] = bestv;
+    }
+    if (rc == CFX_OK) {
+        for (int c = 0; c < kBatchClasses; ++c) h->bvb[c] = table[c];
+        ++h->bvb_version;
+    }
+    (void)hipStreamSynchronize(st);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    for (void *p : {(void *)A, (void *)B, (void *)ipiv, (void *)info, (void *)nv, (void *)rv, (void *)ldav,
+                    (void *)ldbv, (void *)Ap, (void *)Bp, (void *)Ip, work})
+        if (p) (void)hipFree(p);
+    return rc;
+}
+
+int cfx_batched_tuning(cfx_handle *h, int32_t *vb)
+{
+    if (!h) return -1;
+    if (!vb) return -2;
+    for (int c = 0; c < kBatchClasses; ++c) vb[c] = h->bvb[c];
+    return CFX_OK;
+}
+
+int cfx_batched_set_tuning(cfx_handle *h, const int32_t *vb)
+{
+    if (!h) return -1;
+    if (!vb) return -2;
+    for (int c = 0; c < kBatchClasses; ++c)
+        if (vb[c] != 8 && vb[c] != 16 && vb[c] != 32) return -2;
+    for (int c = 0; c < kBatchClasses; ++c) h->bvb[c] = vb[c];
+    ++h->bvb_version;
     return CFX_OK;
 }
 

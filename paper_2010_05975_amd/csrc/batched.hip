@@ -1,0 +1,624 @@
+// Batched LU + solve of many independent small systems in one persistent
+// launch.  Each system is the factorisation of Alg. 1 with one tournament
+// leaf per panel (TP(v, 1): the leaf's GEPP is the panel's pivot search,
+// Sec. 7.3), followed by the solve with its right-hand sides.
+//
+// Scheduling: a one-workgroup prologue sorts the systems by order n,
+// largest first (counting sort), and clears the queue counter; the
+// persistent kernel's workgroups then take systems from the sorted queue
+// with an atomic ticket until it is empty (longest-processing-time-first
+// keeps the tail short).  Every workgroup exits once the queue is drained.
+//
+// One system on one workgroup of 256 threads (n <= 512); the kernel needs
+// about 460 registers per lane, so one workgroup is resident per compute
+// unit and the persistent grid is one workgroup per compute unit.
+//   panel    thread t owns rows t and t + 256; the panel's vb columns of
+//            those rows live in registers.  Each pivot step is a wavefront
+//            argmax (ties to the smaller row) combined across the 4
+//            wavefronts in LDS; rows move between owners through LDS.
+//   swaps    the panel's interchanges, composed into (destination, source)
+//            pairs, applied to the columns outside the panel.
+//   U12      L11^{-1} A12, one column per thread, L11 in LDS.
+//   Schur    A22 -= L21 U12 on the FP64 matrix cores (16x16x4 blocks,
+//            32x32 per wavefront per pass), operands from L2.
+//   solve    B gathered by the row permutation into LDS, forward and back
+//            substitution in 32-row blocks (off-diagonal parts as dot
+//            products, diagonal blocks by lane broadcast), written back.
+// The panel width v per size class comes from the handle's tuning table.
+#include <climits>
+#include <utility>
+
+#include "cfx_internal.h"
+
+namespace cfx {
+namespace {
+
+constexpr int NT = 256;
+constexpr int kMaxN = 512;
+constexpr int kMaxRhs = 16;
+constexpr int kMaxVB = 32;
+constexpr int SBK = 32;   // substitution block
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+template <int... Is, typename F>
+__device__ __forceinline__ void static_for_impl(std::integer_sequence<int, Is...>, F &&f)
+{
+    (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, typename F> __device__ __forceinline__ void static_for(F &&f)
+{
+    static_for_impl(std::make_integer_sequence<int, N>{}, f);
+}
+
+__device__ __forceinline__ double bcast(double x, int l)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u & 0xffffffffull), l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+struct Smem {
+    double X[kMaxN * kMaxRhs];        // solve: permuted right-hand sides
+    double L11[kMaxVB * (kMaxVB + 1)];
+    double rowP[kMaxVB], rowC[kMaxVB];
+    double redv[4];
+    int redr[4];
+    int perm[kMaxN];                  // position -> original row
+    int iperm[kMaxN];                 // original row -> position before the panel
+    int pivs[kMaxVB];
+    int tdst[2 * kMaxVB], tsrc[2 * kMaxVB];
+    int ntouch;
+    int info;
+    int ticket;
+};
+
+// The workgroup-wide pivot of column j of the panel: the largest |value|
+// among rows >= col, ties to the smaller row; rows whose values are all
+// NaN leave p = col.
+__device__ __forceinline__ int wg_argmax(double bv, int br, Smem &s)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double ov = __shfl_xor(bv, off);
+        const int orow = __shfl_xor(br, off);
+        if (ov > bv || (ov == bv && orow < br)) {
+            bv = ov;
+            br = orow;
+        }
+    }
+    if (lane == 0) {
+        s.redv[wave] = bv;
+        s.redr[wave] = br;
+    }
+    __syncthreads();
+    bv = s.redv[0];
+    br = s.redr[0];
+#pragma unroll
+    for (int w = 1; w < 4; ++w) {
+        const double ov = s.redv[w];
+        const int orow = s.redr[w];
+        if (ov > bv || (ov == bv && orow < br)) {
+            bv = ov;
+            br = orow;
+        }
+    }
+    return br;
+}
+
+// One 32x32 block of A22 -= L21 U12 per wavefront pass, K = vb (zero
+// padded to a multiple of 4).  f64 16x16x4 MFMA: A lane l = (row l%16,
+// k l/16), B lane l = (k l/16, col l%16), D lane l element q = (row
+// l/16 + 4q, col l%16).
+__device__ __forceinline__ void schur_tiles(double *A, int64_t lda, int n, int k, int vb)
+{
+    const int m = n - k - vb;
+    if (m <= 0) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int tiles = (m + 31) / 32;
+    const int r0 = k + vb;
+    for (int tix = wave; tix < tiles * tiles; tix += 4) {
+        const int ti = tix / tiles, tj = tix - ti * tiles;
+        const int i0 = r0 + ti * 32, j0 = r0 + tj * 32;
+        d4 acc[2][2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int gi = i0 + a * 16 + lk + 4 * q, gj = j0 + b * 16 + lr;
+                    acc[a][b][q] = (gi < n && gj < n) ? A[(int64_t)gi * lda + gj] : 0.0;
+                }
+        for (int kk = 0; kk < vb; kk += 4) {
+            const int kc = kk + lk;
+            double af[2], bf[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const int gi = i0 + a * 16 + lr;
+                af[a] = (gi < n && kc < vb) ? -A[(int64_t)gi * lda + k + kc] : 0.0;
+            }
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const int gj = j0 + b * 16 + lr;
+                bf[b] = (gj < n && kc < vb) ? A[(int64_t)(k + kc) * lda + gj] : 0.0;
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int gi = i0 + a * 16 + lk + 4 * q, gj = j0 + b * 16 + lr;
+                    if (gi < n && gj < n) A[(int64_t)gi * lda + gj] = acc[a][b][q];
+                }
+    }
+}
+
+// One full-width panel of W columns at column k (k + W <= n): GEPP on rows
+// k..n in registers, interchanges on the other columns, U12, Schur update.
+// No loop unrolled over a compile-time range tests a run-time bound here
+// (such masks are loop invariant and would be hoisted out of the
+// persistent loop, all live at once).
+template <int W>
+__device__ __forceinline__ void panel(double *A, int64_t lda, int n, int k, int32_t *ipiv, Smem &s)
+{
+    const int t = threadIdx.x;
+    double P[2][W];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int r = t + NT * q;
+        const bool ok = r >= k && r < n;
+        const double *row = A + (int64_t)(ok ? r : k) * lda + k;
+        static_for<W>([&](auto C) {
+            constexpr int c = decltype(C)::value;
+            P[q][c] = row[c];
+        });
+    }
+    static_for<W>([&](auto J) {
+        constexpr int j = decltype(J)::value;
+        const int col = k + j;
+        double bv = -1.0;
+        int br = INT_MAX;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int r = t + NT * q;
+            if (r >= col && r < n) {
+                const double a = fabs(P[q][j]);
+                if (a > bv || (a == bv && r < br)) {
+                    bv = a;
+                    br = r;
+                }
+            }
+        }
+        int p = wg_argmax(bv, br, s);
+        if (p == INT_MAX) p = col;
+        // exchange rows col and p between their owners
+        if (t == (p & (NT - 1))) {
+            const int q = p >> 8;
+            static_for<W>([&](auto C) {
+                constexpr int c = decltype(C)::value;
+                s.rowP[c] = q ? P[1][c] : P[0][c];
+            });
+        }
+        if (t == (col & (NT - 1))) {
+            const int q = col >> 8;
+            static_for<W>([&](auto C) {
+                constexpr int c = decltype(C)::value;
+                s.rowC[c] = q ? P[1][c] : P[0][c];
+            });
+        }
+        __syncthreads();
+        if (p != col) {
+            // value selects only (a store through a selected element address
+            // would keep P out of registers)
+            const bool own_c = t == (col & (NT - 1)), own_p = t == (p & (NT - 1));
+            const int qc = col >> 8, qp = p >> 8;
+            static_for<W>([&](auto C) {
+                constexpr int c = decltype(C)::value;
+                const double vp = s.rowP[c], vc = s.rowC[c];
+                P[0][c] = (own_c && qc == 0) ? vp : (own_p && qp == 0) ? vc : P[0][c];
+                P[1][c] = (own_c && qc == 1) ? vp : (own_p && qp == 1) ? vc : P[1][c];
+            });
+        }
+        if (t == 0) {
+            s.pivs[j] = p;
+            ipiv[col] = p;
+            const int a = s.perm[col];
+            s.perm[col] = s.perm[p];
+            s.perm[p] = a;
+        }
+        const double piv = s.rowP[j];
+        if (piv != 0.0) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int r = t + NT * q;
+                if (r > col && r < n) {
+                    const double l = P[q][j] / piv;
+                    P[q][j] = l;
+                    static_for<W>([&](auto C) {
+                        constexpr int c = decltype(C)::value;
+                        if constexpr (c > j) P[q][c] -= l * s.rowP[c];
+                    });
+                }
+            }
+        } else if (t == 0 && s.info == 0) {
+            s.info = col + 1;
+        }
+        __syncthreads();
+    });
+    // ---- write the panel back
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int r = t + NT * q;
+        if (r >= k && r < n) {
+            double *row = A + (int64_t)r * lda + k;
+            static_for<W>([&](auto C) {
+                constexpr int c = decltype(C)::value;
+                row[c] = P[q][c];
+            });
+        }
+    }
+    // ---- the panel's interchanges on the other columns: destinations
+    // k..k+W and every pivot row beyond; source = old position of the row
+    // that now sits at the destination.
+    if (t == 0) {
+        int nt = 0;
+        for (int j = 0; j < W; ++j) {
+            s.tdst[nt] = k + j;
+            s.tsrc[nt] = s.iperm[s.perm[k + j]];
+            ++nt;
+        }
+        for (int j = 0; j < W; ++j) {
+            const int p = s.pivs[j];
+            if (p >= k + W) {
+                bool seen = false;
+                for (int e = W; e < nt; ++e) seen |= s.tdst[e] == p;
+                if (!seen) {
+                    s.tdst[nt] = p;
+                    s.tsrc[nt] = s.iperm[s.perm[p]];
+                    ++nt;
+                }
+            }
+        }
+        s.ntouch = nt;
+    }
+    __syncthreads();
+    {
+        // all sources of a column are read (staged in LDS) before any
+        // destination is written; columns in chunks that fit the stage
+        const int nt = s.ntouch;
+        const int cw = (kMaxN * kMaxRhs) / nt;
+        for (int c0 = 0; c0 < n; c0 += cw) {
+            const int cn = n - c0 < cw ? n - c0 : cw;
+            for (int e = t; e < nt * cn; e += NT) {
+                const int i = e / cn, cc = e - i * cn;
+                s.X[e] = A[(int64_t)s.tsrc[i] * lda + c0 + cc];
+            }
+            __syncthreads();
+            for (int e = t; e < nt * cn; e += NT) {
+                const int i = e / cn, cc = e - i * cn, c = c0 + cc;
+                if (c < k || c >= k + W) A[(int64_t)s.tdst[i] * lda + c] = s.X[e];
+            }
+            __syncthreads();
+        }
+    }
+    // positions of the moved rows, for the next panel
+    for (int e = t; e < s.ntouch; e += NT) {
+        const int d = s.tdst[e];
+        s.iperm[s.perm[d]] = d;
+    }
+    // L11 (unit lower) into LDS
+    for (int e = t; e < W * W; e += NT) {
+        const int i = e / W, j = e - i * W;
+        s.L11[i * (kMaxVB + 1) + j] = A[(int64_t)(k + i) * lda + k + j];
+    }
+    __syncthreads();
+    // ---- U12 = L11^{-1} A12, one column per thread
+    for (int c = k + W + t; c < n; c += NT) {
+        double x[W];
+        static_for<W>([&](auto Q) {
+            constexpr int q = decltype(Q)::value;
+            x[q] = A[(int64_t)(k + q) * lda + c];
+        });
+        static_for<W>([&](auto Q) {
+            constexpr int q = decltype(Q)::value;
+            static_for<q>([&](auto R) {
+                constexpr int r = decltype(R)::value;
+                x[q] -= s.L11[q * (kMaxVB + 1) + r] * x[r];
+            });
+        });
+        static_for<W>([&](auto Q) {
+            constexpr int q = decltype(Q)::value;
+            A[(int64_t)(k + q) * lda + c] = x[q];
+        });
+    }
+    __syncthreads();
+    schur_tiles(A, lda, n, k, W);
+    __syncthreads();
+}
+
+// Panels of width VB while they fit, then of 8, then single columns (every
+// panel full width).
+template <int VB>
+__device__ __forceinline__ void factor(double *A, int64_t lda, int n, int32_t *ipiv, Smem &s)
+{
+    int k = 0;
+    for (; k + VB <= n; k += VB) panel<VB>(A, lda, n, k, ipiv, s);
+    if constexpr (VB > 8)
+        for (; k + 8 <= n; k += 8) panel<8>(A, lda, n, k, ipiv, s);
+    for (; k < n; ++k) panel<1>(A, lda, n, k, ipiv, s);
+}
+
+// X (LDS, stride kMaxRhs) <- U^{-1} L^{-1} X with the factors in A.  The
+// diagonal blocks are staged zero-padded in LDS (s.L11), so the unrolled
+// elimination has no run-time tests.
+__device__ __forceinline__ void solve(const double *A, int64_t lda, int n, int nrhs, Smem &s)
+{
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    constexpr int LD = kMaxVB + 1;
+    static_assert(SBK <= kMaxVB, "diagonal block must fit the L11 stage");
+    // forward, unit L
+    for (int I0 = 0; I0 < n; I0 += SBK) {
+        const int bs = n - I0 < SBK ? n - I0 : SBK;
+        for (int e = t; e < bs * nrhs; e += NT) {
+            const int i = I0 + e / nrhs, c = e % nrhs;
+            const double *row = A + (int64_t)i * lda;
+            double s0 = 0.0, s1 = 0.0;
+            int j = 0;
+            for (; j + 1 < I0; j += 2) {
+                s0 += row[j] * s.X[j * kMaxRhs + c];
+                s1 += row[j + 1] * s.X[(j + 1) * kMaxRhs + c];
+            }
+            if (j < I0) s0 += row[j] * s.X[j * kMaxRhs + c];
+            s.X[i * kMaxRhs + c] -= s0 + s1;
+        }
+        // strictly lower part of the diagonal block, zero elsewhere
+        for (int e = t; e < SBK * SBK; e += NT) {
+            const int i = e / SBK, j = e - i * SBK;
+            s.L11[i * LD + j] = (i < bs && j < i) ? A[(int64_t)(I0 + i) * lda + I0 + j] : 0.0;
+        }
+        __syncthreads();
+        if (lane < SBK) {
+            const bool okr = lane < bs;
+            for (int c = wave; c < nrhs; c += 4) {
+                double x = okr ? s.X[(I0 + lane) * kMaxRhs + c] : 0.0;
+                static_for<SBK>([&](auto J) {
+                    constexpr int j = decltype(J)::value;
+                    x -= s.L11[lane * LD + j] * bcast(x, j);
+                });
+                if (okr) s.X[(I0 + lane) * kMaxRhs + c] = x;
+            }
+        }
+        __syncthreads();
+    }
+    // backward, U: lane j's value is final (undivided) at step j; every
+    // other lane uses x_j / u_jj, and each lane divides its own at the end
+    for (int I0 = ((n - 1) / SBK) * SBK; I0 >= 0; I0 -= SBK) {
+        const int bs = n - I0 < SBK ? n - I0 : SBK;
+        const int j1 = I0 + bs;
+        for (int e = t; e < bs * nrhs; e += NT) {
+            const int i = I0 + e / nrhs, c = e % nrhs;
+            const double *row = A + (int64_t)i * lda;
+            double s0 = 0.0, s1 = 0.0;
+            int j = j1;
+            for (; j + 1 < n; j += 2) {
+                s0 += row[j] * s.X[j * kMaxRhs + c];
+                s1 += row[j + 1] * s.X[(j + 1) * kMaxRhs + c];
+            }
+            if (j < n) s0 += row[j] * s.X[j * kMaxRhs + c];
+            s.X[i * kMaxRhs + c] -= s0 + s1;
+        }
+        // strictly upper part (zero elsewhere) and the diagonal (1 outside)
+        for (int e = t; e < SBK * SBK; e += NT) {
+            const int i = e / SBK, j = e - i * SBK;
+            double v = 0.0;
+            if (i < bs && j < bs && j >= i) v = A[(int64_t)(I0 + i) * lda + I0 + j];
+            if (j == i && i >= bs) v = 1.0;
+            s.L11[i * LD + j] = v;
+        }
+        __syncthreads();
+        if (lane < SBK) {
+            const bool okr = lane < bs;
+            const double d = s.L11[lane * LD + lane];
+            for (int c = wave; c < nrhs; c += 4) {
+                double x = okr ? s.X[(I0 + lane) * kMaxRhs + c] : 0.0;
+                static_for<SBK>([&](auto J) {
+                    constexpr int j = SBK - 1 - decltype(J)::value;
+                    const double xj = bcast(x, j) / s.L11[j * LD + j];
+                    // lanes above j subtract u_ij x_j; lane j and below see
+                    // a zero (u_jj is excluded: the diagonal is applied below)
+                    const double u = j > lane ? s.L11[lane * LD + j] : 0.0;
+                    x -= u * xj;
+                });
+                x = x / d;
+                if (okr) s.X[(I0 + lane) * kMaxRhs + c] = x;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+struct BatchArgs {
+    int count;
+    const int32_t *n, *nrhs;
+    double *const *A;
+    const int64_t *lda;
+    double *const *B;
+    const int64_t *ldb;
+    int32_t *const *ipiv;
+    int32_t *info;
+    int32_t *order;
+    int32_t *counter;
+    int32_t vb_class[kBatchClasses];
+};
+
+__device__ __forceinline__ int size_class(int n)
+{
+    return n <= 32 ? 0 : n <= 64 ? 1 : n <= 128 ? 2 : n <= 256 ? 3 : 4;
+}
+
+// Counting sort of the systems by n, descending (invalid sizes last), and
+// the queue counter reset.  One workgroup.
+__global__ __launch_bounds__(1024) void batched_prep_kernel(BatchArgs a)
+{
+    __shared__ int hist[kMaxN + 2];
+    __shared__ int base[kMaxN + 2];
+    for (int b = threadIdx.x; b < kMaxN + 2; b += 1024) hist[b] = 0;
+    if (threadIdx.x == 0) a.counter[0] = 0;
+    __syncthreads();
+    // bucket 0 holds n = kMaxN, ..., bucket kMaxN holds n = 0, kMaxN + 1 invalid
+    for (int i = threadIdx.x; i < a.count; i += 1024) {
+        const int nn = a.n[i];
+        const int b = (nn < 0 || nn > kMaxN) ? kMaxN + 1 : kMaxN - nn;
+        atomicAdd(&hist[b], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int b = 0; b < kMaxN + 2; ++b) {
+            base[b] = run;
+            run += hist[b];
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < a.count; i += 1024) {
+        const int nn = a.n[i];
+        const int b = (nn < 0 || nn > kMaxN) ? kMaxN + 1 : kMaxN - nn;
+        const int pos = atomicAdd(&base[b], 1);
+        a.order[pos] = i;
+    }
+}
+
+__global__ __launch_bounds__(NT) void batched_gesv_kernel(BatchArgs a)
+{
+    __shared__ Smem s;
+    const int t = threadIdx.x;
+    for (;;) {
+        if (t == 0) s.ticket = atomicAdd(a.counter, 1);
+        __syncthreads();
+        const int idx = s.ticket;
+        __syncthreads();
+        if (idx >= a.count) break;
+        const int sys = a.order[idx];
+        const int n = a.n[sys], nrhs = a.nrhs[sys];
+        const int64_t lda = a.lda[sys], ldb = a.ldb[sys];
+        double *A = a.A[sys];
+        double *B = a.B[sys];
+        int32_t *ipiv = a.ipiv[sys];
+        int bad = 0;
+        if (n < 0 || n > kMaxN) bad = 1;
+        else if (n > 0 && (A == nullptr || ipiv == nullptr)) bad = 2;
+        else if (lda < (n > 1 ? n : 1)) bad = 3;
+        else if (nrhs < 0 || nrhs > kMaxRhs) bad = 4;
+        else if (n > 0 && nrhs > 0 && B == nullptr) bad = 5;
+        else if (ldb < (nrhs > 1 ? nrhs : 1)) bad = 6;
+        if (bad) {
+            if (t == 0) a.info[sys] = -bad;
+            continue;
+        }
+        if (n == 0) {
+            if (t == 0) a.info[sys] = 0;
+            continue;
+        }
+        for (int i = t; i < n; i += NT) {
+            s.perm[i] = i;
+            s.iperm[i] = i;
+        }
+        if (t == 0) s.info = 0;
+        __syncthreads();
+        const int vb = a.vb_class[size_class(n)];
+        if (vb <= 8) factor<8>(A, lda, n, ipiv, s);
+        else if (vb <= 16) factor<16>(A, lda, n, ipiv, s);
+        else factor<32>(A, lda, n, ipiv, s);
+        if (nrhs > 0) {
+            for (int e = t; e < n * nrhs; e += NT) {
+                const int i = e / nrhs, c = e % nrhs;
+                s.X[i * kMaxRhs + c] = B[(int64_t)s.perm[i] * ldb + c];
+            }
+            __syncthreads();
+            solve(A, lda, n, nrhs, s);
+            for (int e = t; e < n * nrhs; e += NT) {
+                const int i = e / nrhs, c = e % nrhs;
+                B[(int64_t)i * ldb + c] = s.X[i * kMaxRhs + c];
+            }
+        }
+        if (t == 0) a.info[sys] = s.info;
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+size_t batched_work_bytes(int32_t count)
+{
+    return 256 + (((size_t)(count > 0 ? count : 0) * sizeof(int32_t) + 255) & ~(size_t)255);
+}
+
+int launch_gesv_batched(int32_t count, const int32_t *n, const int32_t *nrhs, double *const *A,
+                        const int64_t *lda, double *const *B, const int64_t *ldb, int32_t *const *ipiv,
+                        int32_t *info, void *work, const int32_t *vb_class, int grid, hipStream_t st)
+{
+    if (count <= 0) return CFX_OK;
+    BatchArgs a;
+    a.count = count;
+    a.n = n;
+    a.nrhs = nrhs;
+    a.A = A;
+    a.lda = lda;
+    a.B = B;
+    a.ldb = ldb;
+    a.ipiv = ipiv;
+    a.info = info;
+    a.counter = static_cast<int32_t *>(work);
+    a.order = reinterpret_cast<int32_t *>(static_cast<char *>(work) + 256);
+    for (int c = 0; c < kBatchClasses; ++c) a.vb_class[c] = vb_class[c];
+    hipLaunchKernelGGL(batched_prep_kernel, dim3(1), dim3(1024), 0, st, a);
+    CFX_HIP(hipGetLastError());
+    const int g = grid < count ? grid : count;
+    hipLaunchKernelGGL(batched_gesv_kernel, dim3(g), dim3(NT), 0, st, a);
+    CFX_HIP(hipGetLastError());
+    return CFX_OK;
+}
+
+}  // namespace cfx
+
+namespace cfx {
+namespace {
+
+// Tuner input: entries in [-1, 1) from a counter hash (splitmix64 of the
+// element index and seed) plus 2 sqrt(n) on the diagonal.
+__global__ void synth_kernel(double *A, int n, int64_t total, uint64_t seed)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    uint64_t z = (uint64_t)e + seed * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    double v = (double)(z >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
+    const int64_t local = e % ((int64_t)n * n);
+    if (local / n == local % n) v += 2.0 * sqrt((double)n);
+    A[e] = v;
+}
+
+}  // namespace
+
+int launch_batched_synth(double *A, int n, int64_t count, uint64_t seed, hipStream_t st)
+{
+    const int64_t total = count * n * n;
+    if (total <= 0) return CFX_OK;
+    hipLaunchKernelGGL(synth_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, A, n, total, seed);
+    CFX_HIP(hipGetLastError());
+    return CFX_OK;
+}
+
+}  // namespace cfx

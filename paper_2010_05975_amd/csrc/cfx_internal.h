@@ -16,6 +16,7 @@ namespace cfx {
 
 constexpr int kMaxV = 256;        // largest supported panel width
 constexpr int kMaxLeafRows = 8192; // largest supported tournament node height
+constexpr int kBatchClasses = 5;   // batched size classes: n <= 32, 64, 128, 256, 512
 
 // ---------------------------------------------------------------------------
 // Workspace of one factorisation (carved out of the caller's `work`).
@@ -56,6 +57,16 @@ int launch_tslu(const double *W, int64_t ldw, int64_t row0, int64_t rows, int vb
 int launch_getrs(int64_t n, int64_t nrhs, const double *LU, int64_t lda,
                  const int32_t *ipiv, double *B, int64_t ldb, int32_t *perm,
                  double *tmp, hipStream_t st);
+// perm[i] = source row of row i of P B (ipiv interchanges composed).
+int launch_perm(int64_t n, const int32_t *ipiv, int32_t *perm, hipStream_t st);
+// T[i, :] = B[perm[i], :]  /  B[i, :] = T[i, :]   (n x nrhs).
+int launch_gather_rows(int64_t n, int64_t nrhs, const double *B, int64_t ldb,
+                       const int32_t *perm, double *T, int64_t ldt, hipStream_t st);
+int launch_copy_rows(int64_t n, int64_t nrhs, const double *T, int64_t ldt,
+                     double *B, int64_t ldb, hipStream_t st);
+// X <- U^{-1} L^{-1} X in place (X n x nrhs, stride ldx).
+int launch_trsv(int64_t n, int64_t nrhs, const double *LU, int64_t lda, double *X,
+                int64_t ldx, hipStream_t st);
 
 // Apply the row-move plan to all n columns of A; the diagonal block of the
 // panel (rows k..k+vb, columns k..k+vb) is written from ws.lu00.
@@ -72,6 +83,66 @@ int launch_schur_f64(const double *L, int64_t ldl, const double *U, int64_t ldu,
                      double *C, int64_t ldc, int64_t mr, int64_t nc, int K,
                      hipStream_t st);
 
+// Mixed-precision FactorizeA11.  launch_pack_lp rounds L21 (m x K at L21)
+// and U12 (K x m at U12, both stride lda) to the working precision into
+// `buf` (lp_pack_bytes(m, K) bytes); launch_schur_lp then applies
+// C[0:m, col0:col0+ncols] -= L21 U12[:, col0:col0+ncols] from the packed
+// operands, FP32 accumulation, FP64 C.
+size_t lp_pack_bytes(int64_t m, int K);
+int launch_pack_lp(int precision, const double *L21, const double *U12, int64_t lda,
+                   int64_t m, int K, void *buf, hipStream_t st);
+int launch_schur_lp(int precision, const void *buf, int64_t m, int K, int64_t col0,
+                    int64_t ncols, double *C, int64_t ldc, hipStream_t st);
+
 int launch_set_int(int32_t *p, int32_t value, hipStream_t st);
+
+// Batched LU + solve (one persistent launch after a one-workgroup sort).
+// work: batched_work_bytes(count) bytes; vb_class: panel width per size
+// class; grid: persistent workgroups.
+size_t batched_work_bytes(int32_t count);
+int launch_gesv_batched(int32_t count, const int32_t *n, const int32_t *nrhs, double *const *A,
+                        const int64_t *lda, double *const *B, const int64_t *ldb,
+                        int32_t *const *ipiv, int32_t *info, void *work,
+                        const int32_t *vb_class, int grid, hipStream_t st);
+// count systems of order n, contiguous (n x n each), for the tuner.
+int launch_batched_synth(double *A, int n, int64_t count, uint64_t seed, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Iterative refinement (GMRES-IR) pieces.
+// ---------------------------------------------------------------------------
+// y = A x (plain FP64), and r = b - A x with compensated row sums
+// (rowabs_i = sum_j |A_ij| when rowabs is not null).
+int launch_gemv(const double *A, int64_t lda, int64_t n, const double *x, double *y,
+                hipStream_t st);
+int launch_residual(const double *A, int64_t lda, int64_t n, const double *x,
+                    const double *b, double *r, double *rowabs, hipStream_t st);
+
+// Device vectors of one refinement: x, r, b are consecutive at stride ldv.
+struct IrVectors {
+    int64_t n;
+    int restart;
+    double *x, *r, *b, *w, *z, *rowabs, *tmp;
+    double *V;          // restart + 1 Krylov vectors at stride ldv
+    int64_t ldv;
+    double *partial;    // block partial sums
+    double *out;        // small reduction results
+};
+struct IrParams {
+    double tol;
+    int max_outer;
+    double gmres_tol;
+};
+struct IrResult {
+    double eta, eta_first;
+    int outer, inner, converged;
+};
+size_t ir_vec_bytes(int64_t n, int restart);
+IrVectors carve_ir(void *base, int64_t n, int restart);
+// Refine v.x (holding the initial solution) for the right-hand side v.b of
+// A x = b, preconditioned by the factors F (stride ldf) with permutation
+// perm.  Host-blocking on st.
+int ir_refine(const double *A, int64_t lda, const double *F, int64_t ldf,
+              const int32_t *perm, const IrVectors &v, const IrParams &p,
+              IrResult *res, hipStream_t st);
 
 }  // namespace cfx

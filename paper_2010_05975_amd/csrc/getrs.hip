@@ -1,20 +1,47 @@
 // Solve A X = B from the factors A = P L U (the problem statement of Sec. 2.2
-// applied to a right-hand side; LAPACK getrs conventions).
+// applied to right-hand sides; LAPACK getrs conventions).
 //
 // 1. perm: the ipiv interchanges composed into one gather (one workgroup,
 //    the index array in LDS).
-// 2. X = B[perm] (gather into a temporary, then back).
-// 3. Forward substitution with unit L and back substitution with U, blocked
-//    by 256 rows: a one-workgroup kernel solves the diagonal triangle, and the
-//    FP64 MFMA update kernel applies the off-diagonal block to the remaining
-//    rows (C -= L_block * X_block).
+// 2. X = B[perm] into a contiguous temporary.
+// 3. Forward substitution with unit L, then back substitution with U,
+//    blocked by SB = 128 rows.  One launch per block: every workgroup
+//    subtracts the just-solved block's contribution from its rows
+//    (x_i -= LU[i, blk] x_blk, an HBM-bound sweep over the factor), and
+//    workgroup 0, whose rows are the next diagonal block, then solves that
+//    block in registers.  No workgroup ever waits on another; the stream
+//    order between launches carries the dependency.  Each factor element
+//    is read once per triangular solve (8 n^2 bytes per getrs).
+// 4. B = X.
+#include <utility>
+
 #include "cfx_internal.h"
 
 namespace cfx {
 namespace {
 
 constexpr int kPermLds = 36864;   // n up to this uses the LDS permutation (144 KiB)
-constexpr int TRB = 256;          // triangle block
+constexpr int SB = 128;           // block of the substitution
+constexpr int HB = 64;            // half block solved by one wavefront's lanes
+constexpr int RPW = 64;           // rows per updating workgroup
+
+template <int... Is, typename F>
+__device__ __forceinline__ void static_for_impl(std::integer_sequence<int, Is...>, F &&f)
+{
+    (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, typename F> __device__ __forceinline__ void static_for(F &&f)
+{
+    static_for_impl(std::make_integer_sequence<int, N>{}, f);
+}
+
+__device__ __forceinline__ double bcast(double x, int l)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u & 0xffffffffull), l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 
 __global__ __launch_bounds__(256) void perm_lds_kernel(const int32_t *ipiv, int n, int32_t *perm)
 {
@@ -42,97 +69,330 @@ __global__ void perm_global_kernel(const int32_t *ipiv, int64_t n, int32_t *perm
 }
 
 __global__ void gather_rows_kernel(const double *B, int64_t ldb, const int32_t *perm, int64_t n,
-                                   int64_t nrhs, double *T)
+                                   int64_t nrhs, double *T, int64_t ldt)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n * nrhs) return;
     const int64_t i = e / nrhs, c = e - i * nrhs;
-    T[e] = B[(int64_t)perm[i] * ldb + c];
+    T[i * ldt + c] = B[(int64_t)perm[i] * ldb + c];
 }
 
-__global__ void copy_back_kernel(const double *T, int64_t n, int64_t nrhs, double *B, int64_t ldb)
+__global__ void copy_rows_kernel(const double *T, int64_t ldt, int64_t n, int64_t nrhs, double *B,
+                                 int64_t ldb)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n * nrhs) return;
     const int64_t i = e / nrhs, c = e - i * nrhs;
-    B[i * ldb + c] = T[e];
+    B[i * ldb + c] = T[i * ldt + c];
 }
 
-// Triangle solve of the block rows r0 .. r0+bs of X (n x nrhs, stride ldx)
-// in place.  lower != 0: unit lower L; else upper U (non-unit).
-__global__ __launch_bounds__(256) void trsv_block_kernel(const double *LU, int64_t lda, double *X,
-                                                         int64_t ldx, int64_t r0, int bs, int nrhs,
-                                                         int lower)
+// x_i[c] -= sum_{k < bs} LU[i][c0 + k] * ys[k][c] for rows rbeg <= i < rend
+// and the nc right-hand sides cc .. cc+nc of this chunk.  A wavefront takes
+// 4 rows at a time, 16 lanes per row.
+template <int NRC>
+__device__ __forceinline__ void update_rows(const double *__restrict__ LU, int64_t lda, double *X,
+                                            int64_t ldx, int cc, int nc, int64_t rbeg, int64_t rend,
+                                            int64_t c0, int bs, const double *ys)
 {
-    const int tid = threadIdx.x;
-    if (lower) {
-        for (int j = 0; j < bs; ++j) {
-            // rows below j inside the block get x_i -= L_ij x_j
-            for (int e = tid; e < (bs - j - 1) * nrhs; e += 256) {
-                const int i = j + 1 + e / nrhs, c = e % nrhs;
-                X[(r0 + i) * ldx + c] -= LU[(r0 + i) * lda + r0 + j] * X[(r0 + j) * ldx + c];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int sub = lane >> 4, q = lane & 15;
+    for (int64_t i0 = rbeg + wave * 4; i0 < rend; i0 += 16) {
+        const int64_t i = i0 + sub;
+        const bool ok = i < rend;
+        const double *row = LU + (ok ? i : rbeg) * lda + c0;
+        if constexpr (NRC == 1) {
+            // lane q owns the 8 consecutive columns 8q .. 8q+7
+            double s = 0.0;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int k = 8 * q + e;
+                if (k < bs) s += row[k] * ys[k];
             }
-            __syncthreads();
-        }
-    } else {
-        for (int j = bs - 1; j >= 0; --j) {
-            const double d = LU[(r0 + j) * lda + r0 + j];
-            for (int c = tid; c < nrhs; c += 256) X[(r0 + j) * ldx + c] /= d;
-            __syncthreads();
-            for (int e = tid; e < j * nrhs; e += 256) {
-                const int i = e / nrhs, c = e % nrhs;
-                X[(r0 + i) * ldx + c] -= LU[(r0 + i) * lda + r0 + j] * X[(r0 + j) * ldx + c];
+            s += __shfl_xor(s, 8, 16);
+            s += __shfl_xor(s, 4, 16);
+            s += __shfl_xor(s, 2, 16);
+            s += __shfl_xor(s, 1, 16);
+            if (ok && q == 0) X[i * ldx + cc] -= s;
+        } else {
+            // lane q owns right-hand side cc + q
+            double s0 = 0.0, s1 = 0.0;
+            int k = 0;
+            for (; k + 1 < bs; k += 2) {
+                s0 += row[k] * ys[k * NRC + q];
+                s1 += row[k + 1] * ys[(k + 1) * NRC + q];
             }
-            __syncthreads();
+            if (k < bs) s0 += row[k] * ys[k * NRC + q];
+            if (ok && q < nc) X[i * ldx + cc + q] -= s0 + s1;
         }
     }
 }
 
+// Unit lower triangular solve of the diagonal block rows r0 .. r0+bs
+// (bs <= SB) in place in X, as two halves of HB rows.  Lane t of a
+// wavefront owns row t of the half and keeps that row of L in registers;
+// column j is eliminated by broadcasting lane j's finished value.
+template <int NRC>
+__device__ void diag_lower(const double *__restrict__ LU, int64_t lda, double *X, int64_t ldx, int cc,
+                           int nc, int64_t r0, int bs, double *yh)
+{
+    constexpr int CPW = NRC == 1 ? 1 : NRC / 4;   // right-hand sides per wavefront
+    const int t = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const bool active = wave * CPW < NRC;
+    for (int h = 0; h < 2; ++h) {
+        const int hb = bs - HB * h < HB ? bs - HB * h : HB;
+        if (hb <= 0) break;
+        const int64_t rb = r0 + HB * h;
+        const bool okr = t < hb;
+        if (active) {
+            const double *row = LU + (rb + (okr ? t : 0)) * lda;
+            double Lr[HB];
+            static_for<HB>([&](auto J) {
+                constexpr int j = decltype(J)::value;
+                Lr[j] = (okr && j < t) ? row[rb + j] : 0.0;
+            });
+            double xv[CPW];
+#pragma unroll
+            for (int e = 0; e < CPW; ++e) {
+                const int c = wave * CPW + e;
+                xv[e] = (okr && c < nc) ? X[(rb + t) * ldx + cc + c] : 0.0;
+            }
+            if (h == 1) {
+                // contribution of the solved first half (rows r0 .. r0+HB)
+                for (int k = 0; k < HB; ++k) {
+                    const double l = okr ? row[r0 + k] : 0.0;
+#pragma unroll
+                    for (int e = 0; e < CPW; ++e) xv[e] -= l * yh[k * NRC + wave * CPW + e];
+                }
+            }
+            static_for<HB>([&](auto J) {
+                constexpr int j = decltype(J)::value;
+#pragma unroll
+                for (int e = 0; e < CPW; ++e) xv[e] -= Lr[j] * bcast(xv[e], j);
+            });
+#pragma unroll
+            for (int e = 0; e < CPW; ++e) {
+                const int c = wave * CPW + e;
+                if (okr && c < nc) X[(rb + t) * ldx + cc + c] = xv[e];
+                if (h == 0) yh[t * NRC + c] = xv[e];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Upper (non-unit) triangular solve of the diagonal block rows r0 .. r0+bs
+// in place in X: the second half first, then the first.
+template <int NRC>
+__device__ void diag_upper(const double *__restrict__ LU, int64_t lda, double *X, int64_t ldx, int cc,
+                           int nc, int64_t r0, int bs, double *yh)
+{
+    constexpr int CPW = NRC == 1 ? 1 : NRC / 4;
+    const int t = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const bool active = wave * CPW < NRC;
+    for (int h = 1; h >= 0; --h) {
+        const int hb = bs - HB * h < HB ? bs - HB * h : HB;
+        if (hb <= 0) continue;
+        const int64_t rb = r0 + HB * h;
+        const bool okr = t < hb;
+        if (active) {
+            const double *row = LU + (rb + (okr ? t : 0)) * lda;
+            double Ur[HB];
+            static_for<HB>([&](auto J) {
+                constexpr int j = decltype(J)::value;
+                Ur[j] = (okr && j > t && j < hb) ? row[rb + j] : 0.0;
+            });
+            const double d = okr ? row[rb + t] : 1.0;
+            double xv[CPW];
+#pragma unroll
+            for (int e = 0; e < CPW; ++e) {
+                const int c = wave * CPW + e;
+                xv[e] = (okr && c < nc) ? X[(rb + t) * ldx + cc + c] : 0.0;
+            }
+            if (h == 0 && bs > HB) {
+                // contribution of the solved second half (rows r0+HB .. r0+bs)
+                for (int k = 0; k < bs - HB; ++k) {
+                    const double u = okr ? row[r0 + HB + k] : 0.0;
+#pragma unroll
+                    for (int e = 0; e < CPW; ++e) xv[e] -= u * yh[k * NRC + wave * CPW + e];
+                }
+            }
+            static_for<HB>([&](auto J) {
+                constexpr int j = HB - 1 - decltype(J)::value;
+                if (j < hb) {
+#pragma unroll
+                    for (int e = 0; e < CPW; ++e) {
+                        if (t == j) xv[e] = xv[e] / d;
+                        xv[e] -= Ur[j] * bcast(xv[e], j);
+                    }
+                }
+            });
+#pragma unroll
+            for (int e = 0; e < CPW; ++e) {
+                const int c = wave * CPW + e;
+                if (okr && c < nc) X[(rb + t) * ldx + cc + c] = xv[e];
+                if (h == 1) yh[t * NRC + c] = xv[e];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int NRC>
+__device__ __forceinline__ void stage_block(const double *X, int64_t ldx, int cc, int nc, int64_t c0, int bs,
+                                            double *ys)
+{
+    for (int e = threadIdx.x; e < SB * NRC; e += 256) {
+        const int k = e / NRC, c = e - k * NRC;
+        ys[e] = (k < bs && c < nc) ? X[(c0 + k) * ldx + cc + c] : 0.0;
+    }
+    __syncthreads();
+}
+
+// Forward step: when c0 >= 0 the block rows c0 .. c0+bs are solved and
+// every row below is updated with them; workgroup 0 owns the next block
+// rows r0 .. r0+bsn (r0 = c0 + bs) and then solves it.  Workgroup g >= 1
+// owns rows r0 + bsn + (g-1) RPW .. + RPW.
+template <int NRC>
+__global__ __launch_bounds__(256) void fwd_step_kernel(const double *__restrict__ LU, int64_t lda, double *X,
+                                                       int64_t ldx, int64_t n, int nrhs, int64_t c0, int bs,
+                                                       int64_t r0, int bsn)
+{
+    __shared__ double ys[SB * NRC];
+    __shared__ double yh[HB * NRC];
+    const int cc = blockIdx.y * NRC;
+    const int nc = nrhs - cc < NRC ? nrhs - cc : NRC;
+    if (c0 >= 0) {
+        stage_block<NRC>(X, ldx, cc, nc, c0, bs, ys);
+        int64_t rbeg, rend;
+        if (blockIdx.x == 0) {
+            rbeg = r0;
+            rend = r0 + bsn;
+        } else {
+            rbeg = r0 + bsn + (int64_t)(blockIdx.x - 1) * RPW;
+            rend = rbeg + RPW < n ? rbeg + RPW : n;
+        }
+        update_rows<NRC>(LU, lda, X, ldx, cc, nc, rbeg, rend, c0, bs, ys);
+    }
+    if (blockIdx.x != 0 || bsn <= 0) return;
+    __syncthreads();
+    diag_lower<NRC>(LU, lda, X, ldx, cc, nc, r0, bsn, yh);
+}
+
+// Backward step: when c0 >= 0 the block rows c0 .. c0+bs are solved and
+// every row above is updated with them; workgroup 0 owns the block rows
+// r0 .. r0+bsn just above (r0 + bsn = c0) and then solves it.  Workgroup
+// g >= 1 owns rows (g-1) RPW .. + RPW below r0.
+template <int NRC>
+__global__ __launch_bounds__(256) void bwd_step_kernel(const double *__restrict__ LU, int64_t lda, double *X,
+                                                       int64_t ldx, int nrhs, int64_t c0, int bs, int64_t r0,
+                                                       int bsn)
+{
+    __shared__ double ys[SB * NRC];
+    __shared__ double yh[HB * NRC];
+    const int cc = blockIdx.y * NRC;
+    const int nc = nrhs - cc < NRC ? nrhs - cc : NRC;
+    if (c0 >= 0) {
+        stage_block<NRC>(X, ldx, cc, nc, c0, bs, ys);
+        int64_t rbeg, rend;
+        if (blockIdx.x == 0) {
+            rbeg = r0;
+            rend = r0 + bsn;
+        } else {
+            rbeg = (int64_t)(blockIdx.x - 1) * RPW;
+            rend = rbeg + RPW < r0 ? rbeg + RPW : r0;
+        }
+        update_rows<NRC>(LU, lda, X, ldx, cc, nc, rbeg, rend, c0, bs, ys);
+    }
+    if (blockIdx.x != 0 || bsn <= 0) return;
+    __syncthreads();
+    diag_upper<NRC>(LU, lda, X, ldx, cc, nc, r0, bsn, yh);
+}
+
+template <int NRC>
+int trsv_impl(int64_t n, int nrhs, const double *LU, int64_t lda, double *X, int64_t ldx, hipStream_t st)
+{
+    const int64_t nb = (n + SB - 1) / SB;
+    const unsigned gy = (unsigned)((nrhs + NRC - 1) / NRC);
+    auto bsz = [&](int64_t J) { return (int)((n - J * SB) < SB ? (n - J * SB) : SB); };
+    auto cdiv = [](int64_t a, int64_t b) { return (a + b - 1) / b; };
+    // forward: L y = x
+    hipLaunchKernelGGL(fwd_step_kernel<NRC>, dim3(1, gy), dim3(256), 0, st, LU, lda, X, ldx, n, nrhs,
+                       (int64_t)-1, 0, (int64_t)0, bsz(0));
+    CFX_HIP(hipGetLastError());
+    for (int64_t J = 0; J + 1 < nb; ++J) {
+        const int64_t c0 = J * SB, r0 = c0 + SB;
+        const int bsn = bsz(J + 1);
+        const int64_t below = n - r0 - bsn;
+        const unsigned gx = (unsigned)(1 + cdiv(below, RPW));
+        hipLaunchKernelGGL(fwd_step_kernel<NRC>, dim3(gx, gy), dim3(256), 0, st, LU, lda, X, ldx, n, nrhs, c0,
+                           SB, r0, bsn);
+        CFX_HIP(hipGetLastError());
+    }
+    // backward: U x = y
+    hipLaunchKernelGGL(bwd_step_kernel<NRC>, dim3(1, gy), dim3(256), 0, st, LU, lda, X, ldx, nrhs,
+                       (int64_t)-1, 0, (nb - 1) * SB, bsz(nb - 1));
+    CFX_HIP(hipGetLastError());
+    for (int64_t J = nb - 1; J >= 1; --J) {
+        const int64_t c0 = J * SB, r0 = c0 - SB;
+        const unsigned gx = (unsigned)(1 + cdiv(r0, RPW));
+        hipLaunchKernelGGL(bwd_step_kernel<NRC>, dim3(gx, gy), dim3(256), 0, st, LU, lda, X, ldx, nrhs, c0,
+                           bsz(J), r0, SB);
+        CFX_HIP(hipGetLastError());
+    }
+    return CFX_OK;
+}
+
 }  // namespace
 
-int launch_getrs(int64_t n, int64_t nrhs, const double *LU, int64_t lda, const int32_t *ipiv,
-                 double *B, int64_t ldb, int32_t *perm, double *tmp, hipStream_t st)
+int launch_perm(int64_t n, const int32_t *ipiv, int32_t *perm, hipStream_t st)
 {
-    if (n == 0 || nrhs == 0) return CFX_OK;
+    if (n <= 0) return CFX_OK;
     if (n <= kPermLds)
         hipLaunchKernelGGL(perm_lds_kernel, dim3(1), dim3(256), 0, st, ipiv, (int)n, perm);
     else
         hipLaunchKernelGGL(perm_global_kernel, dim3(1), dim3(64), 0, st, ipiv, n, perm);
     CFX_HIP(hipGetLastError());
-    const int64_t tot = n * nrhs;
-    const unsigned g = (unsigned)((tot + 255) / 256);
-    hipLaunchKernelGGL(gather_rows_kernel, dim3(g), dim3(256), 0, st, B, ldb, perm, n, nrhs, tmp);
-    CFX_HIP(hipGetLastError());
-    hipLaunchKernelGGL(copy_back_kernel, dim3(g), dim3(256), 0, st, tmp, n, nrhs, B, ldb);
-    CFX_HIP(hipGetLastError());
-
-    // forward: L y = P b
-    for (int64_t r0 = 0; r0 < n; r0 += TRB) {
-        const int bs = (int)((n - r0) < TRB ? (n - r0) : TRB);
-        hipLaunchKernelGGL(trsv_block_kernel, dim3(1), dim3(256), 0, st, LU, lda, B, ldb, r0, bs,
-                           (int)nrhs, 1);
-        CFX_HIP(hipGetLastError());
-        const int64_t below = n - r0 - bs;
-        if (below > 0) {
-            int rc = launch_schur_f64(LU + (r0 + bs) * lda + r0, lda, B + r0 * ldb, ldb,
-                                      B + (r0 + bs) * ldb, ldb, below, nrhs, bs, st);
-            if (rc) return rc;
-        }
-    }
-    // backward: U x = y
-    int64_t nb = (n + TRB - 1) / TRB;
-    for (int64_t b = nb - 1; b >= 0; --b) {
-        const int64_t r0 = b * TRB;
-        const int bs = (int)((n - r0) < TRB ? (n - r0) : TRB);
-        hipLaunchKernelGGL(trsv_block_kernel, dim3(1), dim3(256), 0, st, LU, lda, B, ldb, r0, bs,
-                           (int)nrhs, 0);
-        CFX_HIP(hipGetLastError());
-        if (r0 > 0) {
-            int rc = launch_schur_f64(LU + r0, lda, B + r0 * ldb, ldb, B, ldb, r0, nrhs, bs, st);
-            if (rc) return rc;
-        }
-    }
     return CFX_OK;
+}
+
+int launch_gather_rows(int64_t n, int64_t nrhs, const double *B, int64_t ldb, const int32_t *perm, double *T,
+                       int64_t ldt, hipStream_t st)
+{
+    const int64_t tot = n * nrhs;
+    if (tot <= 0) return CFX_OK;
+    hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, B, ldb, perm,
+                       n, nrhs, T, ldt);
+    CFX_HIP(hipGetLastError());
+    return CFX_OK;
+}
+
+int launch_copy_rows(int64_t n, int64_t nrhs, const double *T, int64_t ldt, double *B, int64_t ldb,
+                     hipStream_t st)
+{
+    const int64_t tot = n * nrhs;
+    if (tot <= 0) return CFX_OK;
+    hipLaunchKernelGGL(copy_rows_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, T, ldt, n, nrhs,
+                       B, ldb);
+    CFX_HIP(hipGetLastError());
+    return CFX_OK;
+}
+
+int launch_trsv(int64_t n, int64_t nrhs, const double *LU, int64_t lda, double *X, int64_t ldx, hipStream_t st)
+{
+    if (n <= 0 || nrhs <= 0) return CFX_OK;
+    if (nrhs == 1) return trsv_impl<1>(n, 1, LU, lda, X, ldx, st);
+    return trsv_impl<16>(n, (int)nrhs, LU, lda, X, ldx, st);
+}
+
+int launch_getrs(int64_t n, int64_t nrhs, const double *LU, int64_t lda, const int32_t *ipiv, double *B,
+                 int64_t ldb, int32_t *perm, double *tmp, hipStream_t st)
+{
+    if (n == 0 || nrhs == 0) return CFX_OK;
+    int rc;
+    if ((rc = launch_perm(n, ipiv, perm, st))) return rc;
+    if ((rc = launch_gather_rows(n, nrhs, B, ldb, perm, tmp, nrhs, st))) return rc;
+    if ((rc = launch_trsv(n, nrhs, LU, lda, tmp, nrhs, st))) return rc;
+    return launch_copy_rows(n, nrhs, tmp, nrhs, B, ldb, st);
 }
 
 }  // namespace cfx

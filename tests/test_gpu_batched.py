@@ -1,0 +1,174 @@
+"""GPU parity of the batched persistent LU + solve (cfx_gesv_batched)
+against the CPU oracle, system by system: each system is TP(v, 1), whose
+pivots are those of partial pivoting with ties to the smaller row, so the
+oracle runs with leaves = 1."""
+import numpy as np
+import pytest
+
+import cfx_inputs as G
+from oracle import oracle as O
+from tests.gpu_util import compare_panels, say, to_dev
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cfx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2010_05975_amd import cfx as m
+    m.lib()
+    return m
+
+
+def check_system(A, B, LU, ipiv, info, X, tag):
+    n = A.shape[0]
+    ref = O.getrf(A, 32, 1)
+    assert info == ref.info, tag
+    if n == 0:
+        return
+    compared = compare_panels(ipiv, ref.ipiv, ref.margins, 32)
+    assert O.lu_residual(A, LU, ipiv) <= 1e-12, tag
+    if compared == len(ref.margins):
+        np.testing.assert_allclose(LU, ref.LU, rtol=0, atol=1e-9 * max(1.0, np.abs(ref.LU).max()),
+                                   err_msg=tag)
+    if B.shape[1]:
+        Xref = O.getrs(ref.LU, ref.ipiv, B)
+        assert O.eta(A, X, B) <= max(4 * O.eta(A, Xref, B), 1e-15), tag
+        np.testing.assert_allclose(X, Xref, rtol=1e-8, atol=1e-8 * max(1.0, np.abs(Xref).max()),
+                                   err_msg=tag)
+
+
+def run_batch(cfx, systems, graph=True, pad=0):
+    As = []
+    Bs = []
+    for A, B in systems:
+        n, r = B.shape
+        dA = torch.zeros((n, n + pad), dtype=torch.float64, device="cuda")
+        dA[:, :n] = to_dev(A)
+        dB = torch.zeros((n, r + pad), dtype=torch.float64, device="cuda")
+        dB[:, :r] = to_dev(B)
+        As.append(dA[:, :n])
+        Bs.append(dB[:, :r])
+    batch = cfx.Batch(As, Bs)
+    info = cfx.gesv_batched(batch, graph=graph).cpu().numpy()
+    torch.cuda.synchronize()
+    return batch, info
+
+
+EDGE_SIZES = [1, 2, 7, 8, 9, 15, 16, 17, 31, 32, 33, 63, 64, 65, 100, 255, 256, 257, 300, 511, 512]
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_batched_edge_sizes_match_oracle(cfx, graph):
+    say(f"batched edge sizes graph={graph}")
+    systems = []
+    for i, n in enumerate(EDGE_SIZES):
+        A = G.normal_matrix(n, 100 + i)
+        B = G.rhs(n, (i % 17), 200 + i)
+        systems.append((A, B))
+    batch, info = run_batch(cfx, systems, graph=graph, pad=3)
+    for i, (A, B) in enumerate(systems):
+        n = A.shape[0]
+        check_system(A, B, batch.As[i].cpu().numpy(), batch.ipiv[i][:n].cpu().numpy(), int(info[i]),
+                     batch.Bs[i].cpu().numpy(), f"system {i} n={n} nrhs={B.shape[1]}")
+
+
+def test_batched_workload_sample_matches_oracle(cfx):
+    """Systems drawn like the batched workload (n ~ U{16..512}, N(0,1) plus a
+    diagonal shift of 0 or 2 sqrt(n), 1-8 right-hand sides)."""
+    spec = G.batched_spec(160, 4)
+    say("batched workload sample (160 systems)")
+    systems = [G.batched_system(spec, i) for i in range(160)]
+    batch, info = run_batch(cfx, systems)
+    for i, (A, B) in enumerate(systems):
+        n = A.shape[0]
+        check_system(A, B, batch.As[i].cpu().numpy(), batch.ipiv[i][:n].cpu().numpy(), int(info[i]),
+                     batch.Bs[i].cpu().numpy(), f"system {i} n={n}")
+
+
+def test_batched_graph_replays_match_eager(cfx):
+    """The first call captures the launches into a graph; later calls with
+    the same arguments replay it.  Between replays the inputs are restored
+    by ordinary (eager) copies; every replay must equal the eager result."""
+    spec = G.batched_spec(48, 9)
+    say("batched graph replays")
+    systems = [G.batched_system(spec, i) for i in range(48)]
+    eager, _ = run_batch(cfx, systems, graph=False)
+    want = [(a.cpu().numpy(), b.cpu().numpy(), p.cpu().numpy()) for a, b, p in
+            zip(eager.As, eager.Bs, eager.ipiv)]
+    batch, _ = run_batch(cfx, systems, graph=True)
+    for rep in range(3):
+        if rep:
+            for i, (A, B) in enumerate(systems):
+                batch.As[i].copy_(to_dev(A))
+                batch.Bs[i].copy_(to_dev(B))
+            torch.cuda.synchronize()
+            cfx.gesv_batched(batch, graph=True)
+            torch.cuda.synchronize()
+        for i in range(len(systems)):
+            assert np.array_equal(batch.As[i].cpu().numpy(), want[i][0]), (rep, i)
+            assert np.array_equal(batch.Bs[i].cpu().numpy(), want[i][1]), (rep, i)
+            assert np.array_equal(batch.ipiv[i].cpu().numpy(), want[i][2]), (rep, i)
+
+
+def test_batched_invalid_and_singular(cfx):
+    say("batched invalid descriptors and singular system")
+    dev = "cuda"
+    good = G.normal_matrix(40, 1)
+    sing = G.normal_matrix(30, 2)
+    sing[:, 11] = 0.0
+    As = [to_dev(good), to_dev(sing), torch.zeros((0, 0), dtype=torch.float64, device=dev),
+          to_dev(G.normal_matrix(20, 3))]
+    Bs = [to_dev(G.rhs(40, 2, 5)), to_dev(G.rhs(30, 1, 6)),
+          torch.zeros((0, 1), dtype=torch.float64, device=dev), to_dev(G.rhs(20, 1, 7))]
+    batch = cfx.Batch(As, Bs)
+    # corrupt descriptors of system 3 one field at a time
+    for field, value, code in [("d_n", 513, -1), ("d_lda", 5, -3), ("d_nrhs", 17, -4)]:
+        arr = getattr(batch, field)
+        old = arr[3].item()
+        arr[3] = value
+        info = cfx.gesv_batched(batch, graph=False).cpu().numpy()
+        arr[3] = old
+        assert info[3] == code, field
+    As[0].copy_(to_dev(good))
+    As[1].copy_(to_dev(sing))
+    info = cfx.gesv_batched(batch, graph=False).cpu().numpy()
+    assert info[0] == 0 and info[1] == 12 and info[2] == 0 and info[3] == 0
+    ref = O.getrf(sing, 32, 1)
+    assert ref.info == 12
+    assert np.array_equal(batch.ipiv[1].cpu().numpy(), ref.ipiv)
+
+
+def test_batched_tuner(cfx):
+    say("batched tuner")
+    old = cfx.batched_tuning()
+    table = cfx.batched_tune()
+    say(f"  tuned {table} (default {old})")
+    assert len(table) == 5 and all(v in (8, 16, 32) for v in table)
+    spec = G.batched_spec(24, 12)
+    systems = [G.batched_system(spec, i) for i in range(24)]
+    batch, info = run_batch(cfx, systems)
+    for i, (A, B) in enumerate(systems):
+        n = A.shape[0]
+        check_system(A, B, batch.As[i].cpu().numpy(), batch.ipiv[i][:n].cpu().numpy(), int(info[i]),
+                     batch.Bs[i].cpu().numpy(), f"tuned system {i}")
+    cfx.batched_set_tuning(old)
+
+
+@pytest.mark.parametrize("vb", [8, 16, 32])
+def test_batched_every_panel_width(cfx, vb):
+    say(f"batched panel width {vb}")
+    old = cfx.batched_tuning()
+    cfx.batched_set_tuning([vb] * 5)
+    try:
+        sizes = [5, 8, 40, 97, 130, 260, 512]
+        systems = [(G.normal_matrix(n, 300 + n), G.rhs(n, 3, 400 + n)) for n in sizes]
+        batch, info = run_batch(cfx, systems)
+        for i, (A, B) in enumerate(systems):
+            n = A.shape[0]
+            check_system(A, B, batch.As[i].cpu().numpy(), batch.ipiv[i][:n].cpu().numpy(),
+                         int(info[i]), batch.Bs[i].cpu().numpy(), f"vb={vb} n={n}")
+    finally:
+        cfx.batched_set_tuning(old)

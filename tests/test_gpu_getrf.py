@@ -135,7 +135,10 @@ def test_getrf_empty(cfx):
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("n,nrhs,v,L", [(512, 1, 32, 4), (300, 5, 32, 3), (1000, 64, 64, 4),
-                                        (600, 1, 256, 2)])
+                                        (600, 1, 256, 2), (1, 1, 32, 4), (63, 2, 16, 2),
+                                        (64, 1, 16, 2), (65, 17, 16, 2), (127, 16, 32, 3),
+                                        (128, 1, 32, 3), (129, 64, 32, 3), (257, 3, 64, 2),
+                                        (2000, 1, 128, 8)])
 def test_getrs_matches_oracle(cfx, n, nrhs, v, L):
     say(f"getrs n={n} nrhs={nrhs}")
     A = G.normal_matrix(n, 3)
