@@ -225,6 +225,94 @@ int cfx_batched_tune(cfx_handle *h, void *stream);
 int cfx_batched_tuning(cfx_handle *h, int32_t *vb);
 int cfx_batched_set_tuning(cfx_handle *h, const int32_t *vb);
 
+/* ------------------------------------------------------------------------
+ * Serving: a request loop on one device.  Requests (solve A X = B, or solve
+ * again with factors kept from an earlier request) are queued by
+ * cfx_serve_submit from any thread; worker threads, one per slot, each with
+ * its own stream, admit them in arrival order as soon as a slot is free and
+ * the request's device memory fits in the caller's arena (resident factors
+ * nobody is using are evicted, least recently used first, to make room).
+ * Admitted requests run concurrently on their streams.  Consecutive queued
+ * systems of order <= 512 are admitted together and solved by one
+ * cfx_gesv_batched launch (FP64; their factors may be kept resident too).
+ * Larger systems are factored by cfx_getrf with the configured precision
+ * and solved with cfx_getrs semantics (FP64), refined by GMRES-IR
+ * (BF16/FP16).  Every result reports its eta (as cfx_gesv_ir), and its
+ * arithmetic does not depend on what else runs: a request gives the same
+ * bits alone and in a mix.
+ * ------------------------------------------------------------------------ */
+typedef struct cfx_server cfx_server;
+
+typedef struct {
+    void *arena;             /* device memory owned by the caller           */
+    size_t arena_bytes;      /* the HBM budget of the server                */
+    int32_t max_slots;       /* concurrent requests (worker threads), 1..64 */
+    cfx_ir_opts ir;          /* factorisation + refinement options; with
+                                ir.lu.precision FP64, ir.max_outer = 0 gives
+                                the plain solve                            */
+    int32_t batch_max;       /* max systems per batched launch (0: 256)     */
+} cfx_serve_cfg;
+
+enum { CFX_SOLVE = 0, CFX_RESOLVE = 1 };
+
+/* One request.  A, B, X are DEVICE pointers owned by the caller and must
+ * stay valid (A and B unchanged) until the result has been polled.
+ *   kind          : CFX_SOLVE, or CFX_RESOLVE to reuse the resident factors
+ *                   `factor_id` (refactored from A when they were evicted).
+ *   n, nrhs       : order (1 .. INT32_MAX) and right-hand sides (>= 1).
+ *   A / lda       : n x n row-major (read only).
+ *   B / ldb       : n x nrhs row-major (read only).
+ *   X / ldx       : n x nrhs row-major, receives the solution.
+ *   keep_resident : keep the factors on the device after the request. */
+typedef struct {
+    int32_t kind;
+    int32_t keep_resident;
+    uint64_t factor_id;
+    int64_t n, nrhs;
+    const double *A;
+    int64_t lda;
+    const double *B;
+    int64_t ldb;
+    double *X;
+    int64_t ldx;
+} cfx_request;
+
+typedef struct {
+    int32_t status;      /* CFX_OK, or CFX_ENOMEM (does not fit the arena)
+                            or another error code of the solve             */
+    int32_t info;        /* factorisation info                             */
+    uint64_t factor_id;  /* id of the factors used (new or reused)         */
+    int32_t resident_hit;/* RESOLVE found its factors on the device        */
+    int32_t batched;     /* solved inside a batched launch                 */
+    int32_t outer, inner;/* refinement steps / GMRES iterations            */
+    double eta;          /* backward error of X (max over right-hand sides) */
+    double t_submit, t_admit, t_start, t_done; /* seconds, steady clock,
+                            from server creation                           */
+} cfx_result;
+
+typedef struct {
+    int64_t submitted, completed, failed;
+    int64_t resident_hits, resident_misses, evictions;
+    int64_t batches, batched_requests;
+    int64_t resident_factors;
+    size_t bytes_in_use, bytes_peak;
+} cfx_serve_stats;
+
+/* Start the workers (host threads) on the current device.  cfg is copied. */
+int cfx_serve_create(const cfx_serve_cfg *cfg, cfx_server **out);
+/* Queue a request (non-blocking, thread-safe); *ticket identifies it.
+ * Returns -2 for an invalid request. */
+int cfx_serve_submit(cfx_server *s, const cfx_request *req, uint64_t *ticket);
+/* CFX_PENDING while the request is queued or running; CFX_OK once done,
+ * with *out filled and the ticket retired.  -2: unknown ticket. */
+int cfx_serve_poll(cfx_server *s, uint64_t ticket, cfx_result *out);
+/* Drop resident factors (CFX_EBUSY while a request is using them). */
+int cfx_serve_release(cfx_server *s, uint64_t factor_id);
+int cfx_serve_stats_get(cfx_server *s, cfx_serve_stats *out);
+/* Finish every queued request, stop the workers, free the server.  Results
+ * not yet polled are discarded. */
+int cfx_serve_destroy(cfx_server *s);
+
 /* Per-phase device time of the factorisation steps, for measurement.
  * Between cfx_profile_begin and cfx_profile_end every cfx_getrf on the
  * handle records HIP events around each phase on the stream that runs it.

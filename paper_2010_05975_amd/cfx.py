@@ -40,6 +40,38 @@ class IrReport(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class ServeCfg(C.Structure):
+    _fields_ = [("arena", C.c_void_p), ("arena_bytes", C.c_size_t), ("max_slots", C.c_int32),
+                ("ir", IrOpts), ("batch_max", C.c_int32)]
+
+
+class Request(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("keep_resident", C.c_int32), ("factor_id", C.c_uint64),
+                ("n", C.c_int64), ("nrhs", C.c_int64), ("A", C.c_void_p), ("lda", C.c_int64),
+                ("B", C.c_void_p), ("ldb", C.c_int64), ("X", C.c_void_p), ("ldx", C.c_int64)]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("info", C.c_int32), ("factor_id", C.c_uint64),
+                ("resident_hit", C.c_int32), ("batched", C.c_int32), ("outer", C.c_int32),
+                ("inner", C.c_int32), ("eta", C.c_double), ("t_submit", C.c_double),
+                ("t_admit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class ServeStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
+                ("resident_hits", C.c_int64), ("resident_misses", C.c_int64),
+                ("evictions", C.c_int64), ("batches", C.c_int64), ("batched_requests", C.c_int64),
+                ("resident_factors", C.c_int64), ("bytes_in_use", C.c_size_t),
+                ("bytes_peak", C.c_size_t)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class Profile(C.Structure):
     _fields_ = [("tslu_ms", C.c_double), ("laswp_ms", C.c_double), ("trsm_ms", C.c_double),
                 ("schur_ms", C.c_double), ("schur_flops", C.c_double),
@@ -80,12 +112,20 @@ def lib():
         L.cfx_batched_tune.argtypes = [vp, vp]
         L.cfx_batched_tuning.argtypes = [vp, vp]
         L.cfx_batched_set_tuning.argtypes = [vp, vp]
+        L.cfx_serve_create.argtypes = [C.POINTER(ServeCfg), C.POINTER(vp)]
+        L.cfx_serve_submit.argtypes = [vp, C.POINTER(Request), C.POINTER(C.c_uint64)]
+        L.cfx_serve_poll.argtypes = [vp, C.c_uint64, C.POINTER(Result)]
+        L.cfx_serve_release.argtypes = [vp, C.c_uint64]
+        L.cfx_serve_stats_get.argtypes = [vp, C.POINTER(ServeStats)]
+        L.cfx_serve_destroy.argtypes = [vp]
         L.cfx_profile_begin.argtypes = [vp]
         L.cfx_profile_end.argtypes = [vp, C.POINTER(Profile)]
         for f in ("cfx_create", "cfx_destroy", "cfx_getrf_buffer_size", "cfx_getrf",
                   "cfx_tslu", "cfx_getrs", "cfx_gesv_ir_buffer_size", "cfx_gesv_ir",
                   "cfx_gesv_batched_buffer_size", "cfx_gesv_batched", "cfx_batched_tune",
-                  "cfx_batched_tuning", "cfx_batched_set_tuning",
+                  "cfx_batched_tuning", "cfx_batched_set_tuning", "cfx_serve_create",
+                  "cfx_serve_submit", "cfx_serve_poll", "cfx_serve_release", "cfx_serve_stats_get",
+                  "cfx_serve_destroy",
                   "cfx_profile_begin", "cfx_profile_end"):
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -313,6 +353,76 @@ def batched_set_tuning(vb, handle=None):
     h = handle or default_handle()
     t = (C.c_int32 * 5)(*vb)
     _check("cfx_batched_set_tuning", lib().cfx_batched_set_tuning(h.h, t))
+
+
+SOLVE, RESOLVE = 0, 1
+
+
+class Server:
+    """cfx_serve_*: a request loop on the current device.  The arena is a
+    uint8 CUDA tensor owned here; A, B, X of a request are held until its
+    result is polled (the library reads and writes them meanwhile)."""
+
+    def __init__(self, arena_bytes, max_slots=4, batch_max=0, **ir_kw):
+        self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
+        cfg = ServeCfg(C.c_void_p(self.arena.data_ptr()), arena_bytes, max_slots, ir_opts(**ir_kw),
+                       batch_max)
+        s = C.c_void_p()
+        _check("cfx_serve_create", lib().cfx_serve_create(C.byref(cfg), C.byref(s)))
+        self.s = s
+        self.held = {}
+
+    def submit(self, A, B, X, kind=SOLVE, factor_id=0, keep_resident=False):
+        lda = _mat(A, "A")
+        Bm = B.view(-1, 1) if B.dim() == 1 else B
+        Xm = X.view(-1, 1) if X.dim() == 1 else X
+        ldb, ldx = _mat(Bm, "B"), _mat(Xm, "X")
+        r = Request(kind, int(bool(keep_resident)), factor_id, A.shape[0], Bm.shape[1], A.data_ptr(), lda,
+                    Bm.data_ptr(), ldb, Xm.data_ptr(), ldx)
+        t = C.c_uint64()
+        _check("cfx_serve_submit", lib().cfx_serve_submit(self.s, C.byref(r), C.byref(t)))
+        self.held[t.value] = (A, B, X)
+        return t.value
+
+    def poll(self, ticket):
+        res = Result()
+        rc = lib().cfx_serve_poll(self.s, ticket, C.byref(res))
+        if rc == 1:
+            return None
+        _check("cfx_serve_poll", rc)
+        self.held.pop(ticket, None)
+        return res.as_dict()
+
+    def wait(self, ticket, sleep=1e-4, timeout=120.0):
+        import time as _t
+        t0 = _t.monotonic()
+        while True:
+            r = self.poll(ticket)
+            if r is not None:
+                return r
+            if _t.monotonic() - t0 > timeout:
+                raise TimeoutError(f"request {ticket} not done after {timeout} s")
+            _t.sleep(sleep)
+
+    def release(self, factor_id):
+        return lib().cfx_serve_release(self.s, factor_id)
+
+    def stats(self):
+        st = ServeStats()
+        _check("cfx_serve_stats_get", lib().cfx_serve_stats_get(self.s, C.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if self.s:
+            lib().cfx_serve_destroy(self.s)
+            self.s = None
+            self.held.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def profile_begin(handle=None):

@@ -622,3 +622,104 @@ int launch_batched_synth(double *A, int n, int64_t count, uint64_t seed, hipStre
 }
 
 }  // namespace cfx
+
+namespace cfx {
+namespace {
+
+__device__ __forceinline__ void two_sum_b(double a, double b, double &s, double &e)
+{
+    s = a + b;
+    const double z = s - a;
+    e = (a - (s - z)) + (b - z);
+}
+
+// eta_i = max over the right-hand sides c of system i of
+// |b - A x|_inf / (|A|_inf |x|_inf + |b|_inf), residual rows summed with
+// compensated (Dot2) sums.  One workgroup per system, one wavefront per
+// row at a time.
+__global__ __launch_bounds__(256) void batched_eta_kernel(int count, const int32_t *nv, const int32_t *rv,
+                                                          double *const *Av, const int64_t *ldav,
+                                                          double *const *Bv, const int64_t *ldbv,
+                                                          double *const *Xv, const int64_t *ldxv, double *eta)
+{
+#pragma clang fp contract(off)
+    __shared__ double red[4][4];
+    const int sys = blockIdx.x;
+    if (sys >= count) return;
+    const int n = nv[sys], nrhs = rv[sys];
+    const double *A = Av[sys];
+    const double *B = Bv[sys];
+    const double *X = Xv[sys];
+    const int64_t lda = ldav[sys], ldb = ldbv[sys], ldx = ldxv[sys];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double worst = 0.0;
+    for (int c = 0; c < nrhs; ++c) {
+        double rmax = 0.0, xmax = 0.0, bmax = 0.0, amax = 0.0;
+        for (int i = wave; i < n; i += 4) {
+            const double *row = A + (int64_t)i * lda;
+            double s = 0.0, cc = 0.0, ab = 0.0;
+            for (int j = lane; j < n; j += 64) {
+                const double a = row[j], x = X[(int64_t)j * ldx + c];
+                const double p = a * x;
+                const double e = fma(a, x, -p);
+                double t;
+                two_sum_b(s, p, s, t);
+                cc += t + e;
+                ab += fabs(a);
+            }
+            for (int off = 32; off >= 1; off >>= 1) {
+                const double so = __shfl_xor(s, off), co = __shfl_xor(cc, off);
+                double t;
+                two_sum_b(s, so, s, t);
+                cc += co + t;
+                ab += __shfl_xor(ab, off);
+            }
+            double u, e;
+            const double bi = B[(int64_t)i * ldb + c];
+            two_sum_b(bi, -s, u, e);
+            const double r = fabs(u + (e - cc));
+            const double xi = fabs(X[(int64_t)i * ldx + c]);
+            rmax = (r > rmax || r != r) ? r : rmax;
+            xmax = (xi > xmax || xi != xi) ? xi : xmax;
+            bmax = fabs(bi) > bmax ? fabs(bi) : bmax;
+            amax = ab > amax ? ab : amax;
+        }
+        if (lane == 0) {
+            red[wave][0] = rmax;
+            red[wave][1] = xmax;
+            red[wave][2] = bmax;
+            red[wave][3] = amax;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double m[4] = {0, 0, 0, 0};
+            for (int w = 0; w < 4; ++w)
+                for (int q = 0; q < 4; ++q) {
+                    const double v = red[w][q];
+                    m[q] = (v > m[q] || v != v) ? v : m[q];
+                }
+            const double den = m[3] * m[1] + m[2];
+            double e;
+            if (m[0] != m[0] || m[1] != m[1] || !(m[1] < INFINITY)) e = NAN;
+            else e = den > 0 ? m[0] / den : (m[0] > 0 ? INFINITY : 0.0);
+            worst = (e > worst || e != e) ? e : worst;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) eta[sys] = worst;
+}
+
+}  // namespace
+
+int launch_batched_eta(int count, const int32_t *n, const int32_t *nrhs, double *const *A, const int64_t *lda,
+                       double *const *B, const int64_t *ldb, double *const *X, const int64_t *ldx, double *eta,
+                       hipStream_t st)
+{
+    if (count <= 0) return CFX_OK;
+    hipLaunchKernelGGL(batched_eta_kernel, dim3(count), dim3(256), 0, st, count, n, nrhs, A, lda, B, ldb, X, ldx,
+                       eta);
+    CFX_HIP(hipGetLastError());
+    return CFX_OK;
+}
+
+}  // namespace cfx

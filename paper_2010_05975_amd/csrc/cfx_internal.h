@@ -104,6 +104,11 @@ int launch_gesv_batched(int32_t count, const int32_t *n, const int32_t *nrhs, do
                         const int64_t *lda, double *const *B, const int64_t *ldb,
                         int32_t *const *ipiv, int32_t *info, void *work,
                         const int32_t *vb_class, int grid, hipStream_t st);
+// eta[i] = max over right-hand sides of the normwise backward error of X_i
+// for A_i X_i = B_i (compensated residual rows).  One workgroup per system.
+int launch_batched_eta(int count, const int32_t *n, const int32_t *nrhs, double *const *A,
+                       const int64_t *lda, double *const *B, const int64_t *ldb,
+                       double *const *X, const int64_t *ldx, double *eta, hipStream_t st);
 // count systems of order n, contiguous (n x n each), for the tuner.
 int launch_batched_synth(double *A, int n, int64_t count, uint64_t seed, hipStream_t st);
 
