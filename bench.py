@@ -2,7 +2,7 @@
 """Throughput of the tournament-pivoted FP64 LU on one MI355X.
 
 One step = cfx_getrf + cfx_getrs (1 right-hand side) on a seeded N x N matrix
-with N(0,1) entries, panel width v = 256 and L = 64 tournament leaves (the
+with N(0,1) entries, panel width v = 256 and L = 8 tournament leaves (the
 plain FP64 blocked LU + solve workload at N = 32768).  The matrix is
 restored from a pristine device copy before each step, outside the timed
 interval; each step is timed with HIP events on the stream the library runs
@@ -39,6 +39,27 @@ def lu_flops_of_columns(n, k0, k1):
     j = np.arange(k0, k1, dtype=np.float64)
     r = n - j - 1
     return float(np.sum(2.0 * r * r + r))
+
+
+def committed_traffic(n, v, L):
+    """HBM bytes per launch of the FP64 Schur kernel from the committed
+    rocprofv3 PMC summary of this workload (FETCH_SIZE and WRITE_SIZE runs,
+    calibrated by a plain copy), or None if there is none or the kernel's
+    source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"schur_f64_kernel_traffic_n{n}_v{v}_L{L}.md")
+    src = os.path.join(ROOT, "paper_2010_05975_amd", "csrc", "schur_f64.hip")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("|", "#", "`")):
+            key, _, val = line.partition(":")
+            fields[key.strip()] = val.strip()
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if fields.get("kernel_source_sha256_16") != sha or "traffic_bytes_per_launch" not in fields:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(A_host, n, v, L, panels):
@@ -194,7 +215,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=32768)
     ap.add_argument("--v", type=int, default=256)
-    ap.add_argument("--leaves", type=int, default=64)
+    ap.add_argument("--leaves", type=int, default=8)
     ap.add_argument("--lookahead", type=int, default=1)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-panels", type=int, default=2)
@@ -202,6 +223,8 @@ def main():
     ap.add_argument("--no-ir", action="store_true", help="skip the mixed-precision IR leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched leg")
     ap.add_argument("--batched-count", type=int, default=20000)
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="end with a plain 1 GiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--ir-conds", default="1e2,1e6,1e10")
     ap.add_argument("--ir-precs", default="bf16,fp16")
     ap.add_argument("--ir-oracle-check", action="store_true",
@@ -312,7 +335,7 @@ def main():
         "roofline": {"bound": "mfma", "kernel": "schur_f64_kernel",
                      "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-                     "traffic": None, "avg_launch_ms": round(schur_avg_ms, 4),
+                     "traffic": committed_traffic(n, v, L), "avg_launch_ms": round(schur_avg_ms, 4),
                      "avg_launch_flops": schur_avg_flops},
         "checks": {"eta": eta, "projected_residual": proj, "info": info_v},
     }
@@ -324,6 +347,13 @@ def main():
         out["ir"] = ir_leg(cfx, G, torch, n, v, L, conds, precs, args.seed + 7, args.ir_oracle_check)
     if not args.no_batched:
         out["batched"] = batched_leg(cfx, G, torch, args.batched_count, args.seed + 11, max(args.steps, 1))
+    if args.calibration_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A_host, n, v, L, args.cpu_panels)
     print(json.dumps(out), flush=True)

@@ -165,27 +165,35 @@ def ipiv_sign(ipiv: np.ndarray) -> int:
 # --------------------------------------------------------------------------
 # Mixed-precision Schur update (FactorizeA11 of Alg. 1 with low-precision
 # operands).  The paper fixes no low precision; the reading used here: each
-# FP64 operand is rounded to FP32, then to BF16 or FP16, round-to-nearest-
-# even at both steps; products of two such values are exact in FP64, and
-# the accumulation is exact enough in FP64 that this is the reference sum.
+# FP64 operand is rounded once, directly to BF16 or FP16 (round to nearest,
+# ties to even; no intermediate FP32 rounding); products of two such values
+# are exact in FP64, and the FP64 sum of the products is the reference for
+# the FP32 accumulation of the matrix cores.
 # --------------------------------------------------------------------------
 
+_FORMATS = {"bf16": (8, -126, 3.3895313892515355e38),   # precision, emin, max finite
+            "fp16": (11, -14, 65504.0)}
+
+
 def round_lowp(x, precision: str) -> np.ndarray:
-    """FP64 -> FP32 -> {BF16, FP16} (RNE each step), returned as FP64."""
-    with np.errstate(over="ignore"):
-        x32 = np.asarray(x, dtype=np.float64).astype(np.float32)
-    if precision == "fp16":
-        with np.errstate(over="ignore"):
-            return x32.astype(np.float16).astype(np.float64)
-    if precision != "bf16":
+    """Round FP64 values to BF16 or FP16 (nearest, ties to even), returned as
+    FP64.  Written from the format definition: a value with exponent e
+    (2^e <= |x| < 2^(e+1), e clamped below at emin for subnormals) is rounded
+    to a multiple of 2^(e - p + 1); beyond the largest finite value (after
+    rounding) the result is infinite."""
+    if precision not in _FORMATS:
         raise ValueError(precision)
-    bits = x32.view(np.uint32).astype(np.uint64)
-    # BF16 keeps the top 16 bits of an FP32; round the dropped 16 bits to
-    # nearest, ties to the even kept pattern.
-    kept = (bits + 0x7FFF + ((bits >> 16) & 1)) >> 16
-    out = (kept << 16).astype(np.uint32).view(np.float32).astype(np.float64)
-    nan = np.isnan(x32)
-    out[nan] = np.nan
+    p, emin, vmax = _FORMATS[precision]
+    x = np.asarray(x, dtype=np.float64)
+    out = np.array(x, dtype=np.float64, copy=True)
+    fin = np.isfinite(x) & (x != 0)
+    xf = x[fin]
+    _, e2 = np.frexp(np.abs(xf))                 # |x| = m 2^e2, m in [0.5, 1)
+    e = np.maximum(e2 - 1, emin)
+    q = np.ldexp(1.0, e - p + 1)                 # quantum, a power of two
+    r = np.rint(xf / q) * q                      # exact scaling; rint ties to even
+    r[np.abs(r) > vmax] = np.inf * np.sign(r[np.abs(r) > vmax])
+    out[fin] = r
     return out
 
 

@@ -52,6 +52,7 @@ struct cfx_handle {
     hipStream_t side = nullptr;     // lookahead stream (default priority)
     hipEvent_t ev_panel = nullptr;  // next panel's columns updated
     hipEvent_t ev_tslu = nullptr;   // next panel's tournament done
+
     void *scratch = nullptr;        // getrs permutation + gather buffer
     size_t scratch_bytes = 0;
     cfx::Profiler prof;
@@ -230,6 +231,7 @@ int cfx_create(cfx_handle **h)
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess &&
         cus > 0)
         p->cu_count = cus;
+
     *h = p;
     return CFX_OK;
 }
@@ -385,21 +387,23 @@ int cfx_getrf(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *ipiv, i
             if ((rc = schur_update(prec, ws, L21, U12, C, lda, m, 0, vbn, vb, st))) return rc;
             pf.end(PH_SCHUR, e, st, 2.0 * (double)m * vbn * vb);
             // next panel's tournament on the side stream
+            hipStream_t ts = side, us = st;
             CFX_HIP(hipEventRecord(h->ev_panel, st));
-            CFX_HIP(hipStreamWaitEvent(side, h->ev_panel, 0));
+            CFX_HIP(hipStreamWaitEvent(ts, h->ev_panel, 0));
             const int64_t kn = k + vb;
-            e = pf.begin(side);
-            if ((rc = launch_tslu(A + kn * lda + kn, lda, kn, n - kn, vbn, L, ws, nullptr, ipiv, info, side)))
+            e = pf.begin(ts);
+            if ((rc = launch_tslu(A + kn * lda + kn, lda, kn, n - kn, vbn, L, ws, nullptr, ipiv, info, ts)))
                 return rc;
-            pf.end(PH_TSLU, e, side);
-            CFX_HIP(hipEventRecord(h->ev_tslu, side));
+            pf.end(PH_TSLU, e, ts);
+            CFX_HIP(hipEventRecord(h->ev_tslu, ts));
             tslu_on_side = true;
             // the rest of the update
             if (m > vbn) {
-                e = pf.begin(st);
-                if ((rc = schur_update(prec, ws, L21, U12, C, lda, m, vbn, m - vbn, vb, st))) return rc;
-                pf.end(PH_SCHUR, e, st, 2.0 * (double)m * (double)(m - vbn) * vb);
+                e = pf.begin(us);
+                if ((rc = schur_update(prec, ws, L21, U12, C, lda, m, vbn, m - vbn, vb, us))) return rc;
+                pf.end(PH_SCHUR, e, us, 2.0 * (double)m * (double)(m - vbn) * vb);
             }
+
         }
         if (pf.on) ++pf.panels;
     }

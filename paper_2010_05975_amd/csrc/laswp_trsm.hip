@@ -8,11 +8,14 @@
 // writes every destination, so no stripe depends on another.  The diagonal
 // block of the panel is written from the root's factored block (L00\U00).
 //
-// L21 = A21 U00^{-1}: a workgroup owns 32 rows and the whole panel width,
-// sweeps 32-column blocks left to right (update by the finished blocks, then
-// substitution against the diagonal 32 x 32 triangle).  U12 = L00^{-1} A12:
-// a workgroup owns 32 columns and sweeps 32-row blocks top to bottom.  Both
-// work in LDS and write their strip back in place.
+// L21 = A21 U00^{-1} and U12 = L00^{-1} A12 are one solve shape: X U = B
+// with U upper triangular, for X = L21 (U = U00) and for X = U12^T
+// (U = L00^T, unit diagonal).  One wavefront owns a strip of 16 rows of X
+// (16 rows of L21, or 16 columns of U12 read transposed) in LDS and sweeps
+// 32-column blocks left to right: the finished blocks are applied on the
+// FP64 matrix cores (X_b -= X_{<b} U_{<b,b}), then each lane solves one row
+// against the 32 x 32 diagonal triangle by substitution with true division
+// (a zero diagonal leaves that column unscaled).
 #include "cfx_internal.h"
 
 namespace cfx {
@@ -56,131 +59,105 @@ __global__ __launch_bounds__(256) void laswp_kernel(double *A, int64_t lda, int6
 // ---------------------------------------------------------------------------
 // triangular solves
 // ---------------------------------------------------------------------------
-constexpr int TB = 32;          // strip size and inner block
-constexpr int XLD = kMaxV + 1;  // padded strip row (L21 kernel)
+constexpr int TSB = 32;               // diagonal block of the solve
+constexpr int TSR = 16;               // rows of X per wavefront
+constexpr int XLD = kMaxV + 4;        // padded LDS row of the strip
 
-// L21 strip: rows i0 .. i0+rows of A21 (m x vb), U00 upper (non-unit).
-__device__ void trsm_l21_strip(double *A, int64_t lda, int64_t k, int vb, int64_t m, int64_t i0,
-                               double *smem)
+typedef double d4t __attribute__((ext_vector_type(4)));
+
+// U(r, c) of the solve: U00 for L21 (mode 0), L00^T for U12 (mode 1).
+template <int MODE>
+__device__ __forceinline__ double uval(const double *P, int64_t lda, int r, int c)
 {
-    const int tid = threadIdx.x;
-    double *Xs = smem;                    // TB x XLD
-    double *Ub = smem + TB * XLD;         // (vb) x (TB+1): U[0:jb+TB, jb:jb+TB]
-    const double *U = A + k * lda + k;
-    double *X = A + (k + vb) * lda + k;
-    const int rows = (int)((m - i0) < TB ? (m - i0) : TB);
-
-    for (int e = tid; e < rows * vb; e += 256) {
-        const int i = e / vb, c = e - i * vb;
-        Xs[i * XLD + c] = X[(i0 + i) * lda + c];
-    }
-    for (int jb = 0; jb < vb; jb += TB) {
-        const int bc = (vb - jb) < TB ? (vb - jb) : TB;
-        for (int e = tid; e < (jb + bc) * bc; e += 256) {
-            const int l = e / bc, c = e - l * bc;
-            Ub[l * (TB + 1) + c] = U[l * lda + jb + c];
-        }
-        __syncthreads();
-        // update by finished blocks: T = X[:, jb:jb+bc] - X[:, 0:jb] U[0:jb, jb:jb+bc]
-        {
-            const int i = tid >> 3, c4 = (tid & 7) * 4;
-            if (i < rows && jb > 0) {
-                double acc[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) acc[q] = (c4 + q < bc) ? Xs[i * XLD + jb + c4 + q] : 0.0;
-                for (int l = 0; l < jb; ++l) {
-                    const double x = Xs[i * XLD + l];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) acc[q] -= x * Ub[l * (TB + 1) + c4 + q];
-                }
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (c4 + q < bc) Xs[i * XLD + jb + c4 + q] = acc[q];
-            }
-        }
-        __syncthreads();
-        // substitution against the diagonal triangle
-        if (tid < rows) {
-            double *xi = Xs + tid * XLD + jb;
-            for (int j = 0; j < bc; ++j) {
-                double s = xi[j];
-                for (int l = 0; l < j; ++l) s -= xi[l] * Ub[(jb + l) * (TB + 1) + j];
-                const double d = Ub[(jb + j) * (TB + 1) + j];
-                xi[j] = d != 0.0 ? s / d : s;
-            }
-        }
-        __syncthreads();
-    }
-    for (int e = tid; e < rows * vb; e += 256) {
-        const int i = e / vb, c = e - i * vb;
-        X[(i0 + i) * lda + c] = Xs[i * XLD + c];
-    }
+    if constexpr (MODE == 0) return P[(int64_t)r * lda + c];
+    else return r == c ? 1.0 : P[(int64_t)c * lda + r];
 }
 
-// U12 strip: columns j0 .. j0+cols of A12 (vb x m), L00 unit lower.
-__device__ void trsm_u12_strip(double *A, int64_t lda, int64_t k, int vb, int64_t m, int64_t j0,
-                               double *smem)
+template <int MODE>
+__global__ __launch_bounds__(64) void trsm_kernel(double *A, int64_t lda, int64_t k, int vb, int64_t m)
 {
-    const int tid = threadIdx.x;
-    double *Xs = smem;                       // vb x (TB+1)
-    double *Lb = smem + kMaxV * (TB + 1);    // TB x XLD: L[jb:jb+TB, 0:jb+TB]
-    const double *L = A + k * lda + k;
-    double *X = A + k * lda + (k + vb);
-    const int cols = (int)((m - j0) < TB ? (m - j0) : TB);
-
-    for (int e = tid; e < vb * TB; e += 256) {
-        const int l = e / TB, c = e - l * TB;
-        if (c < cols) Xs[l * (TB + 1) + c] = X[l * lda + j0 + c];
+    __shared__ double X[TSR][XLD];
+    __shared__ double Ub[TSB][TSB + 1];
+    const int lane = threadIdx.x;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int64_t r0 = (int64_t)blockIdx.x * TSR;
+    const int rows = (m - r0) < TSR ? (int)(m - r0) : TSR;
+    const double *P = A + k * lda + k;     // the panel's diagonal block
+    // X[i][c]: L21 row r0+i (mode 0) or U12 column r0+i (mode 1)
+    auto xaddr = [&](int i, int c) -> double * {
+        if constexpr (MODE == 0) return A + (k + vb + r0 + i) * lda + k + c;
+        else return A + (k + c) * lda + k + vb + r0 + i;
+    };
+    for (int e = lane; e < TSR * vb; e += 64) {
+        int i, c;
+        if constexpr (MODE == 0) { i = e / vb; c = e - i * vb; }
+        else { c = e / TSR; i = e - c * TSR; }      // 16 consecutive columns of A12 per row
+        X[i][c] = i < rows ? *xaddr(i, c) : 0.0;
     }
-    for (int jb = 0; jb < vb; jb += TB) {
-        const int bc = (vb - jb) < TB ? (vb - jb) : TB;
-        for (int e = tid; e < bc * (jb + bc); e += 256) {
-            const int j = e / (jb + bc), l = e - j * (jb + bc);
-            Lb[j * XLD + l] = L[(jb + j) * lda + l];
-        }
-        __syncthreads();
-        {
-            const int c = tid & 31, j4 = (tid >> 5) * 4;
-            if (c < cols && jb > 0) {
-                double acc[4];
+    __syncthreads();
+    for (int b0 = 0; b0 < vb; b0 += TSB) {
+        const int bc = (vb - b0) < TSB ? (vb - b0) : TSB;
+        // X_b -= X[:, 0:b0] U[0:b0, b0:b0+bc] (two 16 x 16 tiles)
+        if (b0 > 0) {
+            d4t acc[2];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) acc[q] = (j4 + q < bc) ? Xs[(jb + j4 + q) * (TB + 1) + c] : 0.0;
-                for (int l = 0; l < jb; ++l) {
-                    const double x = Xs[l * (TB + 1) + c];
+            for (int t = 0; t < 2; ++t)
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) acc[q] -= Lb[(j4 + q) * XLD + l] * x;
+                for (int q = 0; q < 4; ++q) acc[t][q] = X[lk + 4 * q][b0 + 16 * t + lr];
+            for (int kk = 0; kk < b0; kk += 4) {
+                const double a = -X[lr][kk + lk];
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const int c = b0 + 16 * t + lr;
+                    const double bop = c < vb ? uval<MODE>(P, lda, kk + lk, c) : 0.0;
+                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bop, acc[t], 0, 0, 0);
                 }
+            }
+            __syncthreads();
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (j4 + q < bc) Xs[(jb + j4 + q) * (TB + 1) + c] = acc[q];
-            }
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int c = b0 + 16 * t + lr;
+                    if (c < vb) X[lk + 4 * q][c] = acc[t][q];
+                }
+        }
+        // the diagonal block of U
+        for (int e = lane; e < bc * bc; e += 64) {
+            const int r = e / bc, c = e - r * bc;
+            Ub[r][c] = uval<MODE>(P, lda, b0 + r, b0 + c);
         }
         __syncthreads();
-        if (tid < cols) {
-            for (int j = 1; j < bc; ++j) {
-                double s = Xs[(jb + j) * (TB + 1) + tid];
-                for (int l = 0; l < j; ++l) s -= Lb[j * XLD + jb + l] * Xs[(jb + l) * (TB + 1) + tid];
-                Xs[(jb + j) * (TB + 1) + tid] = s;
+        if (lane < TSR) {
+            double x[TSB];
+#pragma unroll
+            for (int j = 0; j < TSB; ++j) x[j] = j < bc ? X[lane][b0 + j] : 0.0;
+#pragma unroll
+            for (int j = 0; j < TSB; ++j) {
+                if (j < bc) {
+                    double sj = x[j];
+#pragma unroll
+                    for (int l = 0; l < j; ++l) sj -= x[l] * Ub[l][j];
+                    if constexpr (MODE == 0) {
+                        const double d = Ub[j][j];
+                        x[j] = d != 0.0 ? sj / d : sj;
+                    } else {
+                        x[j] = sj;
+                    }
+                }
             }
+#pragma unroll
+            for (int j = 0; j < TSB; ++j)
+                if (j < bc) X[lane][b0 + j] = x[j];
         }
         __syncthreads();
     }
-    for (int e = tid; e < vb * TB; e += 256) {
-        const int l = e / TB, c = e - l * TB;
-        if (c < cols) X[l * lda + j0 + c] = Xs[l * (TB + 1) + c];
+    for (int e = lane; e < TSR * vb; e += 64) {
+        int i, c;
+        if constexpr (MODE == 0) { i = e / vb; c = e - i * vb; }
+        else { c = e / TSR; i = e - c * TSR; }
+        if (i < rows) *xaddr(i, c) = X[i][c];
     }
-}
-
-constexpr size_t kTrsmLds = (size_t)(TB * XLD + kMaxV * (TB + 1)) * sizeof(double);
-
-__global__ __launch_bounds__(256) void trsm_kernel(double *A, int64_t lda, int64_t k, int vb, int64_t m,
-                                                   int nstrips)
-{
-    extern __shared__ double smem[];
-    if ((int)blockIdx.x < nstrips)
-        trsm_l21_strip(A, lda, k, vb, m, (int64_t)blockIdx.x * TB, smem);
-    else
-        trsm_u12_strip(A, lda, k, vb, m, (int64_t)(blockIdx.x - nstrips) * TB, smem);
 }
 
 __global__ void set_int_kernel(int32_t *p, int32_t v) { *p = v; }
@@ -199,15 +176,11 @@ int launch_laswp(double *A, int64_t lda, int64_t n, int64_t k, int vb, const Wor
 
 int launch_trsm(double *A, int64_t lda, int64_t k, int vb, int64_t m, hipStream_t st)
 {
-    static bool attr_set = false;
-    if (!attr_set) {
-        CFX_HIP(hipFuncSetAttribute((const void *)trsm_kernel,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTrsmLds));
-        attr_set = true;
-    }
     if (m <= 0) return CFX_OK;
-    const int nstrips = (int)((m + TB - 1) / TB);
-    hipLaunchKernelGGL(trsm_kernel, dim3(2 * nstrips), dim3(256), kTrsmLds, st, A, lda, k, vb, m, nstrips);
+    const unsigned g = (unsigned)((m + TSR - 1) / TSR);
+    hipLaunchKernelGGL(trsm_kernel<0>, dim3(g), dim3(64), 0, st, A, lda, k, vb, m);
+    CFX_HIP(hipGetLastError());
+    hipLaunchKernelGGL(trsm_kernel<1>, dim3(g), dim3(64), 0, st, A, lda, k, vb, m);
     CFX_HIP(hipGetLastError());
     return CFX_OK;
 }

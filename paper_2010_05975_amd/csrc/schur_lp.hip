@@ -56,6 +56,28 @@ __device__ __forceinline__ void tile_of(int bid, int nb, int tm, int tn, int &ti
     tj = r / gsz;
 }
 
+// FP64 -> T rounded once, to nearest with ties to even (no intermediate
+// FP32 rounding).  BF16: round to FP32 by truncation toward zero with the
+// sticky "odd" bit (round-to-odd keeps the information a second rounding
+// needs), then to BF16 by round-to-nearest-even on the bits; FP16: the
+// direct conversion.
+template <typename T> __device__ __forceinline__ T to_lowp(double x);
+template <> __device__ __forceinline__ __bf16 to_lowp<__bf16>(double x)
+{
+    if (x != x) return __builtin_bit_cast(__bf16, (unsigned short)0x7FC0);
+    float f = (float)x;                               // nearest
+    unsigned b = __float_as_uint(f);
+    const double back = (double)f;
+    if (back != x && !__builtin_isinf(f)) {
+        // step to the neighbour on x's side if f is even: the odd one of
+        // the two FP32 values around x
+        if ((b & 1u) == 0u) b = (fabs(x) > fabs(back)) ? b + 1u : b - 1u;
+    }
+    const unsigned r = (b + 0x7FFFu + ((b >> 16) & 1u)) >> 16;
+    return __builtin_bit_cast(__bf16, (unsigned short)r);
+}
+template <> __device__ __forceinline__ _Float16 to_lowp<_Float16>(double x) { return (_Float16)x; }
+
 // Round an FP64 panel to T: Lp[i][k] = T(L[i][k]) for i < m, k < K, zero for
 // K <= k < Kp.
 template <typename T>
@@ -66,29 +88,29 @@ __global__ void pack_rows_kernel(const double *__restrict__ L, int64_t ldl, int6
     if (e >= m * Kp) return;
     const int64_t i = e / Kp;
     const int k = (int)(e - i * Kp);
-    out[e] = (T)(k < K ? (float)L[i * ldl + k] : 0.0f);
+    out[e] = to_lowp<T>(k < K ? L[i * ldl + k] : 0.0);
 }
 
-// Ut[j][k] = T(U[k][j]) for j < n, k < K (transposed through LDS), zero for
-// K <= k < Kp.
+// Ut[j][k] = T(U[k][j]) for j < n, k < K (transposed through LDS in FP64),
+// zero for K <= k < Kp.
 template <typename T>
 __global__ __launch_bounds__(256) void pack_cols_kernel(const double *__restrict__ U, int64_t ldu, int64_t n,
                                                         int K, int Kp, T *__restrict__ out)
 {
-    __shared__ float tile[32][33];
+    __shared__ double tile[32][33];
     const int64_t j0 = (int64_t)blockIdx.x * 32;
     const int k0 = blockIdx.y * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
     for (int r = ty; r < 32; r += 8) {
         const int k = k0 + r;
         const int64_t j = j0 + tx;
-        tile[r][tx] = (k < K && j < n) ? (float)U[(int64_t)k * ldu + j] : 0.0f;
+        tile[r][tx] = (k < K && j < n) ? U[(int64_t)k * ldu + j] : 0.0;
     }
     __syncthreads();
     for (int r = ty; r < 32; r += 8) {
         const int64_t j = j0 + r;
         const int k = k0 + tx;
-        if (j < n && k < Kp) out[j * Kp + k] = (T)tile[tx][r];
+        if (j < n && k < Kp) out[j * Kp + k] = to_lowp<T>(tile[tx][r]);
     }
 }
 

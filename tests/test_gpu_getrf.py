@@ -27,7 +27,8 @@ def cfx():
 
 @pytest.mark.parametrize("rows,vb,L", [(64, 8, 4), (512, 32, 4), (300, 32, 3), (1000, 16, 7),
                                        (2048, 64, 8), (4096, 256, 16), (1024, 256, 1),
-                                       (700, 128, 5), (33, 32, 64)])
+                                       (700, 128, 5), (33, 32, 64), (8192, 256, 1),
+                                       (6000, 256, 1), (4096, 128, 2), (2500, 256, 1)])
 def test_tslu_matches_oracle(cfx, rows, vb, L):
     say(f"tslu rows={rows} vb={vb} L={L}")
     W = G.normal_matrix(rows, rows + vb)[:, :vb].copy()
@@ -73,6 +74,10 @@ def lu_tolerance(ref_LU, n):
     ("normal", 1024, 64, 8),
     ("normal", 2048, 256, 4),
     ("normal", 777, 256, 2),
+    ("normal", 4096, 256, 1),    # one 4096-row leaf (16 rows per thread)
+    ("normal", 4096, 256, 2),    # 2048-row leaves
+    ("normal", 3000, 128, 3),    # 1000-row leaves, ragged
+    ("normal", 6000, 256, 8),    # the bench's leaf count, 750-row leaves
 ])
 @pytest.mark.parametrize("lookahead", [0, 1])
 def test_getrf_matches_oracle(cfx, gen, n, v, L, lookahead):
@@ -157,12 +162,13 @@ def test_getrs_matches_oracle(cfx, n, nrhs, v, L):
     np.testing.assert_allclose(X, Xref, rtol=1e-8, atol=1e-8 * np.abs(Xref).max())
 
 
-def test_getrf_lookahead_bitwise_equal(cfx):
+@pytest.mark.parametrize("n,v,L", [(1500, 128, 4), (3000, 256, 8)])
+def test_getrf_lookahead_bitwise_equal(cfx, n, v, L):
     """Lookahead only reorders independent launches: the factors are
     bitwise the same as without it."""
-    say("lookahead bitwise")
-    A = G.normal_matrix(1500, 8)
-    a = run_getrf(cfx, A, 128, 4, 0)
-    b = run_getrf(cfx, A, 128, 4, 1)
+    say(f"lookahead bitwise n={n} v={v} L={L}")
+    A = G.normal_matrix(n, 8)
+    a = run_getrf(cfx, A, v, L, 0)
+    b = run_getrf(cfx, A, v, L, 1)
     assert np.array_equal(a[1], b[1])
     assert np.array_equal(a[0], b[0])

@@ -68,17 +68,24 @@ def test_lowp_single_update_matches_oracle(cfx, prec, n, v, L):
     tol = 1e-9 * np.abs(f.LU).max()
     np.testing.assert_allclose(LU[:v, :], f.LU[:v, :], rtol=0, atol=tol)
     # the tail: the GPU's last panel factors its own low-precision Schur
-    # complement S_gpu in FP64, so L22 U22 = P22 S_gpu up to FP64 rounding,
-    # and S_gpu differs from the oracle's S (exact sums of the rounded
-    # products) only by the FP32 accumulation: relative 2^-24 per term.
+    # complement S_gpu in FP64, so L22 U22 = P22 S_gpu up to FP64 rounding.
+    # The rounding to the low format is a quantisation decided from FP64
+    # values: the check rounds the GPU's own first-panel factors (equal to
+    # the oracle's to 1e-9, but an ulp apart can round to different BF16
+    # neighbours), multiplies and sums them exactly (FP64), and allows the
+    # FP32 accumulation of the matrix cores: K terms, relative 2^-24 each.
     perm22 = O.ipiv_to_perm((ipiv[v:] - v).astype(np.int32))
+    perm0 = O.ipiv_to_perm(np.concatenate([f.ipiv[:v], np.arange(v, n)]).astype(np.int32))
+    PA22 = A[perm0][v:, v:][perm22]
     L22, U22 = O.unpack(LU[v:, v:])
     R = L22 @ U22
-    scale = (np.abs(O.round_lowp(f.LU[v:, :v], prec)) @ np.abs(O.round_lowp(f.LU[:v, v:], prec))).max()
-    d_lp = np.abs(R - S[perm22]).max()
-    d_64 = np.abs(R - f.LU[v:, v:][perm22]).max()       # FP64 Schur complement
+    Lr, Ur = O.round_lowp(LU[v:, :v], prec), O.round_lowp(LU[:v, v:], prec)
+    Sg = PA22 - Lr @ Ur
+    scale = (np.abs(Lr) @ np.abs(Ur)).max()
+    d_lp = np.abs(R - Sg).max()
+    d_64 = np.abs(R - (PA22 - LU[v:, :v] @ LU[:v, v:])).max()     # FP64 complement
     say(f"  |L22U22 - P S_lowp| = {d_lp:.3e}, vs FP64 complement {d_64:.3e}, scale {scale:.3e}")
-    assert d_lp <= 2.0 ** -24 * v * scale + 1e-12 * np.abs(S).max()
+    assert d_lp <= 2.0 ** -24 * v * scale + 1e-12 * np.abs(Sg).max()
     assert d_64 > 1e-6 * scale            # the operands really were rounded
     # L21 as the oracle's, its rows moved by the last panel's interchanges
     np.testing.assert_allclose(LU[v:, :v], f.LU[v:, :v][perm22], rtol=0, atol=tol)

@@ -17,18 +17,32 @@ def test_bf16_round_to_nearest_even():
     assert np.array_equal(np.signbit(got), np.signbit(want))
 
 
-def test_bf16_rounds_through_fp32():
-    # 1 + 2^-8 + 2^-30 is above the BF16 midpoint in FP64, but FP32 rounds it
-    # onto the midpoint first, and the tie then goes to the even value 1.
-    assert O.round_lowp(np.array([1 + 2.0 ** -8 + 2.0 ** -30]), "bf16")[0] == 1.0
+def test_rounding_is_direct_from_fp64():
+    # 1 + 2^-8 + 2^-30 lies above the BF16 midpoint 1 + 2^-8: the nearest BF16
+    # value is 1 + 2^-7 (an FP32 intermediate would first land exactly on the
+    # midpoint and then tie to 1).  Likewise for FP16 around 1 + 2^-11.
+    assert O.round_lowp(np.array([1 + 2.0 ** -8 + 2.0 ** -30]), "bf16")[0] == 1 + 2.0 ** -7
+    assert O.round_lowp(np.array([1 + 2.0 ** -11 + 2.0 ** -40]), "fp16")[0] == 1 + 2.0 ** -10
+    assert O.round_lowp(np.array([-(1 + 2.0 ** -8 + 2.0 ** -30)]), "bf16")[0] == -(1 + 2.0 ** -7)
 
 
 def test_bf16_special_values():
-    x = np.array([np.inf, -np.inf, np.nan, 1e39, 3.3895313892515355e38])
+    x = np.array([np.inf, -np.inf, np.nan, 1e39, 3.3895313892515355e38, 2.0 ** -130, 3 * 2.0 ** -134,
+                  2.0 ** -134])
     got = O.round_lowp(x, "bf16")
     assert got[0] == np.inf and got[1] == -np.inf and np.isnan(got[2])
-    assert got[3] == np.inf                       # beyond FP32
+    assert got[3] == np.inf                       # beyond the largest finite value
     assert got[4] == 3.3895313892515355e38        # largest finite BF16
+    assert got[5] == 2.0 ** -130                  # subnormal, representable
+    # subnormal quantum 2^-133: 1.5 quanta ties to the even 2 quanta, 0.5 to 0
+    assert got[6] == 2.0 ** -132 and got[7] == 0.0
+
+
+def test_matches_numpy_float16():
+    """Special case that reduces to a library routine: numpy's FP16 cast
+    rounds FP64 directly to nearest-even."""
+    x = G.normal_matrix(128, 5).ravel() * np.logspace(-9, 4, 128 * 128)
+    assert np.array_equal(O.round_lowp(x, "fp16"), x.astype(np.float16).astype(np.float64))
 
 
 def test_bf16_error_bound_and_format():
