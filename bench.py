@@ -223,6 +223,9 @@ def main():
     ap.add_argument("--no-ir", action="store_true", help="skip the mixed-precision IR leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched leg")
     ap.add_argument("--batched-count", type=int, default=20000)
+    ap.add_argument("--device-gen", action="store_true",
+                    help="draw A and b on the device (seeded torch generator) instead of on the host; "
+                         "used for the counter runs (no CPU baseline then)")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="end with a plain 1 GiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--ir-conds", default="1e2,1e6,1e10")
@@ -243,12 +246,21 @@ def main():
     from paper_2010_05975_amd import cfx
 
     n, v, L = args.n, args.v, args.leaves
-    log(f"generating A ({n}x{n}, N(0,1), seed {args.seed})")
-    A_host = G.normal_matrix(n, args.seed)
-    b_host = G.rhs(n, 1, args.seed + 1)
     dev = torch.device("cuda:0")
-    pristine = torch.from_numpy(A_host).to(dev)
-    pb = torch.from_numpy(b_host).to(dev)
+    if args.device_gen:
+        log(f"generating A ({n}x{n}, N(0,1), device generator seed {args.seed})")
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(args.seed)
+        pristine = torch.randn(n, n, dtype=torch.float64, device=dev, generator=gen)
+        pb = torch.randn(n, 1, dtype=torch.float64, device=dev, generator=gen)
+        A_host = None
+        args.no_cpu_baseline = True
+    else:
+        log(f"generating A ({n}x{n}, N(0,1), seed {args.seed})")
+        A_host = G.normal_matrix(n, args.seed)
+        b_host = G.rhs(n, 1, args.seed + 1)
+        pristine = torch.from_numpy(A_host).to(dev)
+        pb = torch.from_numpy(b_host).to(dev)
     A = torch.empty_like(pristine)
     B = torch.empty_like(pb)
     work = cfx.workspace(n, v, L, "fp64", args.lookahead, dev)

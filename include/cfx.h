@@ -256,7 +256,10 @@ typedef struct {
 enum { CFX_SOLVE = 0, CFX_RESOLVE = 1 };
 
 /* One request.  A, B, X are DEVICE pointers owned by the caller and must
- * stay valid (A and B unchanged) until the result has been polled.
+ * stay valid (A and B unchanged) until the result has been polled.  The
+ * server's streams do not wait for any stream of the caller: A and B must
+ * be written, and no pending work may touch X, when the request is
+ * submitted.
  *   kind          : CFX_SOLVE, or CFX_RESOLVE to reuse the resident factors
  *                   `factor_id` (refactored from A when they were evicted).
  *   n, nrhs       : order (1 .. INT32_MAX) and right-hand sides (>= 1).

@@ -379,6 +379,9 @@ class Server:
         ldb, ldx = _mat(Bm, "B"), _mat(Xm, "X")
         r = Request(kind, int(bool(keep_resident)), factor_id, A.shape[0], Bm.shape[1], A.data_ptr(), lda,
                     Bm.data_ptr(), ldb, Xm.data_ptr(), ldx)
+        # the server's streams do not wait for the caller's: finish the work
+        # queued on the current stream (that may still be writing A, B or X)
+        torch.cuda.current_stream().synchronize()
         t = C.c_uint64()
         _check("cfx_serve_submit", lib().cfx_serve_submit(self.s, C.byref(r), C.byref(t)))
         self.held[t.value] = (A, B, X)

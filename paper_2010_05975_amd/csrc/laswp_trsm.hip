@@ -104,14 +104,23 @@ __global__ __launch_bounds__(64) void trsm_kernel(double *A, int64_t lda, int64_
             for (int t = 0; t < 2; ++t)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) acc[t][q] = X[lk + 4 * q][b0 + 16 * t + lr];
-            for (int kk = 0; kk < b0; kk += 4) {
-                const double a = -X[lr][kk + lk];
+            // b0 is a multiple of 32: chunks of 8 k-steps, all operand loads
+            // of a chunk issued before its matrix-core operations
+            const bool c0ok = b0 + lr < vb, c1ok = b0 + 16 + lr < vb;
+            for (int kc = 0; kc < b0; kc += 32) {
+                double av[8], bv[8][2];
 #pragma unroll
-                for (int t = 0; t < 2; ++t) {
-                    const int c = b0 + 16 * t + lr;
-                    const double bop = c < vb ? uval<MODE>(P, lda, kk + lk, c) : 0.0;
-                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bop, acc[t], 0, 0, 0);
+                for (int s8 = 0; s8 < 8; ++s8) {
+                    const int kr = kc + 4 * s8 + lk;
+                    av[s8] = -X[lr][kr];
+                    bv[s8][0] = c0ok ? uval<MODE>(P, lda, kr, b0 + lr) : 0.0;
+                    bv[s8][1] = c1ok ? uval<MODE>(P, lda, kr, b0 + 16 + lr) : 0.0;
                 }
+#pragma unroll
+                for (int s8 = 0; s8 < 8; ++s8)
+#pragma unroll
+                    for (int t = 0; t < 2; ++t)
+                        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s8], bv[s8][t], acc[t], 0, 0, 0);
             }
             __syncthreads();
 #pragma unroll

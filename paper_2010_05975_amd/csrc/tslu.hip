@@ -40,8 +40,6 @@
 namespace cfx {
 namespace {
 
-constexpr int NT = 256;
-constexpr int NW = NT / 64;
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef double d2 __attribute__((ext_vector_type(2)));
@@ -140,13 +138,13 @@ struct BlockW {
     static constexpr int value = (64 / RPT) < 32 ? (64 / RPT) : 32;
 };
 
-template <int BW>
+template <int BW, int NWV>
 struct Lds {
-    d2 cand[2][NW][BW / 2 > 0 ? BW / 2 : 1];   // published pivot-row candidates
-    double slot_a[2][NW];
-    int slot_g[2][NW];
-    int slot_t[2][NW];
-    int slot_s[2][NW];
+    d2 cand[2][NWV][BW / 2 > 0 ? BW / 2 : 1];   // published pivot-row candidates
+    double slot_a[2][NWV];
+    int slot_g[2][NWV];
+    int slot_t[2][NWV];
+    int slot_s[2][NWV];
     double RT[BW][BW + 8];      // RT[l][i] = multiplier of block pivot i on pivot l
     double PR[8][BW + 2];       // the current sub-panel's pivot rows
     union {
@@ -197,11 +195,12 @@ __device__ __forceinline__ int node_gid(const NodeArgs &p, const NodeRows &n, in
 // ---------------------------------------------------------------------------
 // P: pivot steps and U rows of one block, one workgroup per node.
 // ---------------------------------------------------------------------------
-template <int RPT>
+template <int RPT, int NT>
 __global__ __launch_bounds__(NT) void tslu_panel_kernel(NodeArgs p)
 {
     constexpr int BW = BlockW<RPT>::value;
-    using L = Lds<BW>;
+    constexpr int NW = NT / 64;
+    using L = Lds<BW, NW>;
     extern __shared__ double smem_raw[];
     L &s = *reinterpret_cast<L *>(smem_raw);
 
@@ -304,14 +303,27 @@ __global__ __launch_bounds__(NT) void tslu_panel_kernel(NodeArgs p)
                     wave_argmax(wa, wg);
                     // gids are unique, so exactly one lane owns the wave's best
                     if (bq >= 0 && bg == wg) {
-                        static_for<RPT>([&](auto QC) {
-                            constexpr int q = decltype(QC)::value;
-                            if (q == bq) {
+                        // the winning row by value selects (a branch per row
+                        // would become a select of the row's address and
+                        // keep x out of registers)
 #pragma unroll
-                                for (int c = 0; c + 1 < BW; c += 2) s.cand[par][wave][c / 2] = d2{x[q][c], x[q][c + 1]};
-                                if (BW & 1) s.cand[par][wave][BW / 2][0] = x[q][BW - 1];
-                            }
-                        });
+                        for (int c = 0; c + 1 < BW; c += 2) {
+                            double v0 = 0.0, v1 = 0.0;
+                            static_for<RPT>([&](auto QC) {
+                                constexpr int q = decltype(QC)::value;
+                                v0 = q == bq ? x[q][c] : v0;
+                                v1 = q == bq ? x[q][c + 1] : v1;
+                            });
+                            s.cand[par][wave][c / 2] = d2{v0, v1};
+                        }
+                        if (BW & 1) {
+                            double v0 = 0.0;
+                            static_for<RPT>([&](auto QC) {
+                                constexpr int q = decltype(QC)::value;
+                                v0 = q == bq ? x[q][BW - 1] : v0;
+                            });
+                            s.cand[par][wave][BW / 2][0] = v0;
+                        }
                         s.slot_t[par][wave] = tid;
                         s.slot_s[par][wave] = bq;
                     }
@@ -627,14 +639,14 @@ __global__ __launch_bounds__(256) void tslu_gather_kernel(NodeArgs p, int tiles_
     if (tcol == 0 && tid < 64 && r0 + tid < r) p.rsel[(size_t)node * p.rs_node + r0 + tid] = 0;
 }
 
-template <int RPT>
+template <int RPT, int NT>
 int launch_level(NodeArgs a, int grid, int rows_cap, hipStream_t st)
 {
     constexpr int BW = BlockW<RPT>::value;
     static bool attr_set = false;
-    const size_t lds = sizeof(Lds<BW>);
+    const size_t lds = sizeof(Lds<BW, NT / 64>);
     if (!attr_set) {
-        CFX_HIP(hipFuncSetAttribute((const void *)tslu_panel_kernel<RPT>,
+        CFX_HIP(hipFuncSetAttribute((const void *)tslu_panel_kernel<RPT, NT>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         attr_set = true;
     }
@@ -648,7 +660,7 @@ int launch_level(NodeArgs a, int grid, int rows_cap, hipStream_t st)
     }
     for (int jb = 0; jb < nsel_max; jb += BW) {
         a.jb = jb;
-        hipLaunchKernelGGL(tslu_panel_kernel<RPT>, dim3(grid), dim3(NT), lds, st, a);
+        hipLaunchKernelGGL((tslu_panel_kernel<RPT, NT>), dim3(grid), dim3(NT), lds, st, a);
         CFX_HIP(hipGetLastError());
         const int ncol_max = nsel_max - (jb + BW);
         if (ncol_max > 0) {
@@ -661,14 +673,18 @@ int launch_level(NodeArgs a, int grid, int rows_cap, hipStream_t st)
     return CFX_OK;
 }
 
+// Node kernel shape by node height: up to 512 rows one workgroup of 256
+// threads; taller nodes 512 threads (two wavefronts per SIMD still leave
+// each lane 256 registers), so that the register block x[RPT][BW] can be
+// twice as wide as with 256 threads: fewer blocks, fewer update passes.
 int launch_node_level(const NodeArgs &a, int grid, int rows_cap, hipStream_t st)
 {
-    if (rows_cap <= 256) return launch_level<1>(a, grid, rows_cap, st);
-    if (rows_cap <= 512) return launch_level<2>(a, grid, rows_cap, st);
-    if (rows_cap <= 1024) return launch_level<4>(a, grid, rows_cap, st);
-    if (rows_cap <= 2048) return launch_level<8>(a, grid, rows_cap, st);
-    if (rows_cap <= 4096) return launch_level<16>(a, grid, rows_cap, st);
-    if (rows_cap <= 8192) return launch_level<32>(a, grid, rows_cap, st);
+    if (rows_cap <= 256) return launch_level<1, 256>(a, grid, rows_cap, st);
+    if (rows_cap <= 512) return launch_level<2, 256>(a, grid, rows_cap, st);
+    if (rows_cap <= 1024) return launch_level<2, 512>(a, grid, rows_cap, st);
+    if (rows_cap <= 2048) return launch_level<4, 512>(a, grid, rows_cap, st);
+    if (rows_cap <= 4096) return launch_level<8, 512>(a, grid, rows_cap, st);
+    if (rows_cap <= 8192) return launch_level<16, 512>(a, grid, rows_cap, st);
     return CFX_ENOTSUP;
 }
 
