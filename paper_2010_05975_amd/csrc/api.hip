@@ -74,6 +74,11 @@ namespace cfx {
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
+#ifndef CFX_LOOKAHEAD_CHUNK
+#define CFX_LOOKAHEAD_CHUNK 1024
+#endif
+constexpr int64_t kLookaheadChunk = CFX_LOOKAHEAD_CHUNK;   // columns per Schur launch with lookahead
+
 struct Layout {
     int64_t max_nodes, node_rows;
     size_t off_S, off_cand0, off_cand1, off_cnt0, off_cnt1, off_plan, off_lu00, off_selg, off_rsel,
@@ -397,11 +402,14 @@ int cfx_getrf(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *ipiv, i
             pf.end(PH_TSLU, e, ts);
             CFX_HIP(hipEventRecord(h->ev_tslu, ts));
             tslu_on_side = true;
-            // the rest of the update
-            if (m > vbn) {
+            // the rest of the update, in column chunks: between two chunks
+            // the dispatcher can start the tournament's launches queued on
+            // the side stream instead of leaving them behind one huge grid
+            for (int64_t c0 = vbn; c0 < m; c0 += kLookaheadChunk) {
+                const int64_t cw = (m - c0) < kLookaheadChunk ? (m - c0) : kLookaheadChunk;
                 e = pf.begin(us);
-                if ((rc = schur_update(prec, ws, L21, U12, C, lda, m, vbn, m - vbn, vb, us))) return rc;
-                pf.end(PH_SCHUR, e, us, 2.0 * (double)m * (double)(m - vbn) * vb);
+                if ((rc = schur_update(prec, ws, L21, U12, C, lda, m, c0, cw, vb, us))) return rc;
+                pf.end(PH_SCHUR, e, us, 2.0 * (double)m * (double)cw * vb);
             }
 
         }
