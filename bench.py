@@ -48,16 +48,18 @@ def committed_traffic(n, v, L):
     source changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"schur_f64_kernel_traffic_n{n}_v{v}_L{L}.md")
-    src = os.path.join(ROOT, "paper_2010_05975_amd", "csrc", "schur_f64.hip")
     if not os.path.exists(path):
         return None
     fields = {}
     for line in open(path):
         if ":" in line and not line.startswith(("|", "#", "`")):
             key, _, val = line.partition(":")
-            fields[key.strip()] = val.strip()
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if fields.get("kernel_source_sha256_16") != sha or "traffic_bytes_per_launch" not in fields:
+            fields[key.strip()] = val.split()[0] if val.split() else ""
+    # the kernel and the host loop that shapes its launches
+    h = hashlib.sha256()
+    for name in ("schur_f64.hip", "api.hip"):
+        h.update(open(os.path.join(ROOT, "paper_2010_05975_amd", "csrc", name), "rb").read())
+    if fields.get("kernel_source_sha256_16") != h.hexdigest()[:16] or "traffic_bytes_per_launch" not in fields:
         return None
     return float(fields["traffic_bytes_per_launch"])
 
@@ -208,6 +210,95 @@ def batched_leg(cfx, G, torch, count, seed, steps):
     return out
 
 
+def serve_leg(cfx, G, torch, rate, duration, seed, arena_gb, slots, nmax):
+    """The serving loop on a seeded Poisson stream: arrivals at `rate` per
+    second for `duration` seconds, n log-uniform in [64, nmax], cond
+    log-uniform in [1e2, 1e8] (Householder construction), 1-16 right-hand
+    sides, 30 % re-solves of an earlier request's factors (kept resident).
+    The inputs are built on the device before the clock starts; requests are
+    submitted at their arrival times from this thread.  Run once with FP64
+    factors and once with BF16 factors + GMRES-IR (target 5e-15)."""
+    dev = torch.device("cuda:0")
+    reqs = G.serving_stream(rate, duration, seed, nmax=nmax)
+    built = []
+    for i, r in enumerate(reqs):
+        src = r if r.resolve_of < 0 else reqs[r.resolve_of]
+        if r.resolve_of < 0:
+            A = G.householder_matrix(G.householder_spec(r.n, r.cond, r.seed % (2**31)), device="cuda:0")
+        else:
+            A = built[r.resolve_of][0]
+        g = torch.Generator(device=dev)
+        g.manual_seed(r.seed % (2**31))
+        B = torch.randn(r.n, r.nrhs, dtype=torch.float64, device=dev, generator=g)
+        built.append((A, B))
+    torch.cuda.synchronize()
+    out = {"rate_per_s": rate, "duration_s": duration, "requests": len(reqs), "n_range": [64, nmax],
+           "arena_gb": arena_gb, "slots": slots}
+    for prec in ("fp64", "bf16"):
+        kw = dict(precision=prec, v=256 if prec == "fp64" else 256, leaves=8, tol=5e-15,
+                  max_outer=4 if prec == "fp64" else 30, gmres_restart=30, gmres_tol=1e-6)
+        srv = cfx.Server(int(arena_gb * (1 << 30)), max_slots=slots, **kw)
+        tickets = [None] * len(reqs)
+        xs = [torch.zeros_like(b) for _, b in built]
+        torch.cuda.synchronize()
+        fid = {}
+        results = [None] * len(reqs)
+        t0 = time.perf_counter()
+        pending = []
+        for i, r in enumerate(reqs):
+            while time.perf_counter() - t0 < r.t_arrival:
+                time.sleep(2e-4)
+            A, B = built[i]
+            if r.resolve_of >= 0 and r.resolve_of in fid:
+                tickets[i] = srv.submit(A, B, xs[i], kind=cfx.RESOLVE, factor_id=fid[r.resolve_of])
+            else:
+                tickets[i] = srv.submit(A, B, xs[i], keep_resident=r.resolve_of < 0)
+            pending.append(i)
+            if (i + 1) % 50 == 0:
+                log(f"serve {prec}: submitted {i + 1}/{len(reqs)}, {len(pending)} pending")
+            still = []
+            for j in pending:      # collect finished results without blocking
+                res = srv.poll(tickets[j])
+                if res is None:
+                    still.append(j)
+                    continue
+                results[j] = res
+                if reqs[j].resolve_of < 0:
+                    fid[j] = res["factor_id"]
+            pending = still
+        for c, j in enumerate(pending):
+            results[j] = srv.wait(tickets[j], timeout=600)
+            if (c + 1) % 20 == 0:
+                log(f"serve {prec}: draining, {c + 1}/{len(pending)} done")
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        lat = np.array([r["t_done"] - r["t_submit"] for r in results])
+        ok = [r for r in results if r["status"] == 0]
+        new_flops = sum(2.0 * reqs[i].n ** 3 / 3 for i, r in enumerate(results)
+                        if r["status"] == 0 and not r["resident_hit"])
+        solve_flops = sum(2.0 * reqs[i].n ** 2 * reqs[i].nrhs for i, r in enumerate(results) if r["status"] == 0)
+        etas = np.array([r["eta"] for r in ok])
+        resolves = [i for i, q in enumerate(reqs) if q.resolve_of >= 0]
+        hits = sum(1 for i in resolves if results[i]["resident_hit"])
+        out[prec] = {"p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
+                     "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
+                     "max_ms": round(1e3 * float(lat.max()), 3),
+                     "wall_s": round(wall, 3),
+                     "lu_tflops": round(new_flops / wall / 1e12, 3),
+                     "lu_plus_solve_tflops": round((new_flops + solve_flops) / wall / 1e12, 3),
+                     "failed": len(results) - len(ok),
+                     "eta_max": float(etas.max()) if len(etas) else None,
+                     "eta_le_5e-15": int(np.sum(etas <= 5e-15)),
+                     "resolves": len(resolves), "resident_hits": hits,
+                     "batched_requests": st["batched_requests"], "evictions": st["evictions"],
+                     "bytes_peak_gb": round(st["bytes_peak"] / 2**30, 2)}
+        log(f"serve {prec}: {out[prec]}")
+    del built
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -223,6 +314,12 @@ def main():
     ap.add_argument("--no-ir", action="store_true", help="skip the mixed-precision IR leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched leg")
     ap.add_argument("--batched-count", type=int, default=20000)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-rate", type=float, default=50.0)
+    ap.add_argument("--serve-duration", type=float, default=6.0)
+    ap.add_argument("--serve-nmax", type=int, default=8192)
+    ap.add_argument("--serve-arena-gb", type=float, default=64.0)
+    ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--device-gen", action="store_true",
                     help="draw A and b on the device (seeded torch generator) instead of on the host; "
                          "used for the counter runs (no CPU baseline then)")
@@ -359,6 +456,9 @@ def main():
         out["ir"] = ir_leg(cfx, G, torch, n, v, L, conds, precs, args.seed + 7, args.ir_oracle_check)
     if not args.no_batched:
         out["batched"] = batched_leg(cfx, G, torch, args.batched_count, args.seed + 11, max(args.steps, 1))
+    if not args.no_serve:
+        out["serve"] = serve_leg(cfx, G, torch, args.serve_rate, args.serve_duration, args.seed + 13,
+                                 args.serve_arena_gb, args.serve_slots, args.serve_nmax)
     if args.calibration_copy:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)

@@ -75,7 +75,7 @@ namespace cfx {
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 #ifndef CFX_LOOKAHEAD_CHUNK
-#define CFX_LOOKAHEAD_CHUNK 1024
+#define CFX_LOOKAHEAD_CHUNK 512
 #endif
 constexpr int64_t kLookaheadChunk = CFX_LOOKAHEAD_CHUNK;   // columns per Schur launch with lookahead
 
