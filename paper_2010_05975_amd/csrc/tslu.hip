@@ -9,14 +9,16 @@
 // block of one tree level is two launches:
 //
 //  P (one workgroup of 256 threads per node): thread t owns physical rows
-//    t, t+256, ... and keeps their block columns in registers.  Pivot steps:
-//    each thread scores its unselected rows, a DPP/readlane reduction picks
-//    the wave's best, the winning lane publishes its row into a
-//    double-buffered LDS slot, one barrier, and every thread picks the
-//    overall winner and eliminates its rows against it.  Then the block's
-//    pivot rows are extended to the trailing columns (U rows, unit-lower
-//    substitution in registers).  The node's state (selection, row mask,
-//    negated U rows) is kept in the workspace between launches.
+//    t, t+NT, ... and keeps their block columns in registers.  Pivot steps:
+//    each thread scores its unselected rows; two branch-free DPP/readlane
+//    reductions give the wave's best score and the smallest global row
+//    holding it; that row publishes the rest of its sub-panel into a
+//    double-buffered LDS slot; one barrier; every thread picks the overall
+//    winner from the slots and eliminates its rows against it.  Selected
+//    rows are frozen, so their owners publish them whole once per
+//    sub-panel, for the U rows of the rest of the block.  The node's state
+//    (selection, row mask, negated U rows) is kept in the workspace between
+//    launches.
 //  E (many workgroups, all nodes of the level): the rank-BW update of the
 //    trailing columns on the FP64 matrix cores, C^T -= U^T L^T, in 64 x 64
 //    tiles; a node's update is spread over the whole GPU instead of being
@@ -87,40 +89,45 @@ __device__ __forceinline__ void static_for(F &&f)
     static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
-__device__ __forceinline__ bool beats(double a, int g, double b, int gb)
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double a)
 {
-    return a > b || (a == b && g < gb);
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(a), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(a), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
 }
 
-// (a, g) of the wavefront's best candidate, uniform across lanes: a DPP
-// butterfly inside each row of 16 lanes (xor 1, xor 2, half-mirror,
-// mirror), then the four row results combined through readlane.
-__device__ __forceinline__ void wave_argmax(double &a, int &g)
+__device__ __forceinline__ double readlane_f64(double a, int l)
 {
-    auto dpp_step = [&](auto CTRL) {
-        constexpr int ctrl = decltype(CTRL)::value;
-        const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(a), ctrl, 0xF, 0xF, false);
-        const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(a), ctrl, 0xF, 0xF, false);
-        const int g2 = __builtin_amdgcn_update_dpp(0, g, ctrl, 0xF, 0xF, false);
-        const double a2 = __hiloint2double(hi, lo);
-        if (beats(a2, g2, a, g)) { a = a2; g = g2; }
-    };
-    dpp_step(std::integral_constant<int, 0xB1>{});   // quad_perm [1,0,3,2]
-    dpp_step(std::integral_constant<int, 0x4E>{});   // quad_perm [2,3,0,1]
-    dpp_step(std::integral_constant<int, 0x141>{});  // row_half_mirror
-    dpp_step(std::integral_constant<int, 0x140>{});  // row_mirror
-    double ba = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(a), 0),
-                                 __builtin_amdgcn_readlane(__double2loint(a), 0));
-    int bg = __builtin_amdgcn_readlane(g, 0);
-#pragma unroll
-    for (int row = 1; row < 4; ++row) {
-        const double ra = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(a), 16 * row),
-                                           __builtin_amdgcn_readlane(__double2loint(a), 16 * row));
-        const int rg = __builtin_amdgcn_readlane(g, 16 * row);
-        if (beats(ra, rg, ba, bg)) { ba = ra; bg = rg; }
-    }
-    a = ba;
-    g = bg;
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(a), l),
+                            __builtin_amdgcn_readlane(__double2loint(a), l));
+}
+
+__device__ __forceinline__ double max2(double a, double b) { return b > a ? b : a; }
+
+// Largest value over the wavefront, uniform across lanes: a DPP butterfly
+// inside each row of 16 lanes (xor 1, xor 2, half-mirror, mirror leave the
+// row's maximum in every lane of the row), then the four rows through
+// readlane.  Exact: only comparisons.
+__device__ __forceinline__ double wave_max(double a)
+{
+    a = max2(a, dpp_f64<0xB1>(a));   // quad_perm [1,0,3,2]
+    a = max2(a, dpp_f64<0x4E>(a));   // quad_perm [2,3,0,1]
+    a = max2(a, dpp_f64<0x141>(a));  // row_half_mirror
+    a = max2(a, dpp_f64<0x140>(a));  // row_mirror
+    return max2(max2(readlane_f64(a, 0), readlane_f64(a, 16)),
+                max2(readlane_f64(a, 32), readlane_f64(a, 48)));
+}
+
+// Smallest integer over the wavefront, uniform across lanes (same pattern).
+__device__ __forceinline__ int wave_min(int g)
+{
+    g = min(g, __builtin_amdgcn_update_dpp(0, g, 0xB1, 0xF, 0xF, false));
+    g = min(g, __builtin_amdgcn_update_dpp(0, g, 0x4E, 0xF, 0xF, false));
+    g = min(g, __builtin_amdgcn_update_dpp(0, g, 0x141, 0xF, 0xF, false));
+    g = min(g, __builtin_amdgcn_update_dpp(0, g, 0x140, 0xF, 0xF, false));
+    return min(min(__builtin_amdgcn_readlane(g, 0), __builtin_amdgcn_readlane(g, 16)),
+               min(__builtin_amdgcn_readlane(g, 32), __builtin_amdgcn_readlane(g, 48)));
 }
 
 // Score of a candidate value: |a|; NaN ranks below every number but above
@@ -140,11 +147,10 @@ struct BlockW {
 
 template <int BW, int NWV>
 struct Lds {
-    d2 cand[2][NWV][BW / 2 > 0 ? BW / 2 : 1];   // published pivot-row candidates
-    double slot_a[2][NWV];
-    int slot_g[2][NWV];
-    int slot_t[2][NWV];
-    int slot_s[2][NWV];
+    double cand[2][NWV][8];     // each wave's best row: its current sub-panel values
+    double slot_a[2][NWV];      // each wave's best score
+    int slot_g[2][NWV];         // ... the smallest global row holding it
+    int slot_p[2][NWV];         // ... and that row's physical index in the node
     double RT[BW][BW + 8];      // RT[l][i] = multiplier of block pivot i on pivot l
     double PR[8][BW + 2];       // the current sub-panel's pivot rows
     union {
@@ -281,89 +287,88 @@ __global__ __launch_bounds__(NT) void tslu_panel_kernel(NodeArgs p)
             const int spc = (bwc - sp0) < SP ? (bwc - sp0) : SP;   // steps in this sub-panel
             const int rem = bwc - sp0 - SP;                        // block columns right of it
             bool open[RPT];     // live when the sub-panel starts: writes its columns back
+            int selstep[RPT];   // step of this sub-panel that selected the row, or -1
             static_for<RPT>([&](auto QC) {
                 constexpr int q = decltype(QC)::value;
                 open[q] = live[q];
+                selstep[q] = -1;
             });
             static_for<SP>([&](auto JC) {
                 constexpr int j = decltype(JC)::value;
                 if (j < spc) {
                     const int par = j & 1;
-                    double ba = -1.0;
-                    int bg = INT_MAX, bq = -1;
+                    // this thread's scores, the wave's best score, then the
+                    // smallest global row holding it (exact, no branches)
+                    double sc[RPT];
+                    double m = -1.0;
                     static_for<RPT>([&](auto QC) {
                         constexpr int q = decltype(QC)::value;
-                        if (live[q]) {
-                            const double a = score(x[q][j]);
-                            if (beats(a, gid[q], ba, bg)) { ba = a; bg = gid[q]; bq = q; }
-                        }
+                        sc[q] = live[q] ? score(x[q][j]) : -1.0;
+                        m = max2(m, sc[q]);
                     });
-                    double wa = ba;
-                    int wg = bg;
-                    wave_argmax(wa, wg);
-                    // gids are unique, so exactly one lane owns the wave's best
-                    if (bq >= 0 && bg == wg) {
-                        // the winning row by value selects (a branch per row
-                        // would become a select of the row's address and
-                        // keep x out of registers)
-#pragma unroll
-                        for (int c = 0; c + 1 < BW; c += 2) {
-                            double v0 = 0.0, v1 = 0.0;
-                            static_for<RPT>([&](auto QC) {
-                                constexpr int q = decltype(QC)::value;
-                                v0 = q == bq ? x[q][c] : v0;
-                                v1 = q == bq ? x[q][c + 1] : v1;
-                            });
-                            s.cand[par][wave][c / 2] = d2{v0, v1};
-                        }
-                        if (BW & 1) {
-                            double v0 = 0.0;
-                            static_for<RPT>([&](auto QC) {
-                                constexpr int q = decltype(QC)::value;
-                                v0 = q == bq ? x[q][BW - 1] : v0;
-                            });
-                            s.cand[par][wave][BW / 2][0] = v0;
-                        }
-                        s.slot_t[par][wave] = tid;
-                        s.slot_s[par][wave] = bq;
-                    }
+                    m = wave_max(m);
+                    int c = INT_MAX;
+                    static_for<RPT>([&](auto QC) {
+                        constexpr int q = decltype(QC)::value;
+                        c = sc[q] == m ? min(c, gid[q]) : c;
+                    });
+                    const int wg = wave_min(c);
                     if (lane == 0) {
-                        s.slot_a[par][wave] = wa;
+                        s.slot_a[par][wave] = m;
                         s.slot_g[par][wave] = wg;
                     }
-                    __syncthreads();
-                    double ma = s.slot_a[par][0];
-                    int mg = s.slot_g[par][0], mw = 0;
+                    // the row (unique: global rows are distinct) publishes its
+                    // sub-panel values from column j on
+                    if (wg != INT_MAX) {
+                        static_for<RPT>([&](auto QC) {
+                            constexpr int q = decltype(QC)::value;
+                            if (gid[q] == wg) {
+                                s.slot_p[par][wave] = tid + q * NT;
 #pragma unroll
-                    for (int w = 1; w < NW; ++w) {
-                        const double aw = s.slot_a[par][w];
-                        const int gw = s.slot_g[par][w];
-                        if (beats(aw, gw, ma, mg)) { ma = aw; mg = gw; mw = w; }
+                                for (int cc = j; cc < SP; ++cc) s.cand[par][wave][cc] = x[q][cc];
+                            }
+                        });
                     }
-                    const int ot = s.slot_t[par][mw], oq = s.slot_s[par][mw];
-                    const double *prow = reinterpret_cast<const double *>(&s.cand[par][mw][0]);
+                    __syncthreads();
+                    // the node's winner: best score, ties to the smallest
+                    // global row (some row is live at every step, so the
+                    // best score is at least -0.5 and its wave published)
+                    double M = s.slot_a[par][0];
+#pragma unroll
+                    for (int w = 1; w < NW; ++w) M = max2(M, s.slot_a[par][w]);
+                    int Gw = INT_MAX;
+#pragma unroll
+                    for (int w = 0; w < NW; ++w)
+                        Gw = s.slot_a[par][w] == M ? min(Gw, s.slot_g[par][w]) : Gw;
+                    int mw = 0;
+#pragma unroll
+                    for (int w = 1; w < NW; ++w) mw = s.slot_g[par][w] == Gw ? w : mw;
+                    const int pw = s.slot_p[par][mw];
+                    const double *prow = &s.cand[par][mw][0];
                     if (tid == 0) {
-                        s.sel[jb + sp0 + j] = mg;
-                        s.selp[jb + sp0 + j] = ot + oq * NT;
-                        s.rowsel[ot + oq * NT] = 1;
+                        s.sel[jb + sp0 + j] = Gw;
+                        s.selp[jb + sp0 + j] = pw;
+                        s.rowsel[pw] = 1;
                     }
-                    if (tid < BW) s.PR[j][tid] = prow[tid];
                     static_for<RPT>([&](auto QC) {
                         constexpr int q = decltype(QC)::value;
-                        if (tid == ot && q == oq) live[q] = false;
+                        if (tid + q * NT == pw) {
+                            live[q] = false;
+                            selstep[q] = j;
+                        }
                     });
                     const double piv = prow[j];
                     if (piv != 0.0) {
                         double pv[SP];
 #pragma unroll
-                        for (int c = j + 1; c < SP; ++c) pv[c] = prow[c];
+                        for (int cc = j + 1; cc < SP; ++cc) pv[cc] = prow[cc];
                         static_for<RPT>([&](auto QC) {
                             constexpr int q = decltype(QC)::value;
                             if (live[q]) {
                                 const double l = x[q][j] / piv;
                                 x[q][j] = l;
 #pragma unroll
-                                for (int c = j + 1; c < SP; ++c) x[q][c] -= l * pv[c];
+                                for (int cc = j + 1; cc < SP; ++cc) x[q][cc] -= l * pv[cc];
                             }
                         });
                     }
@@ -381,6 +386,15 @@ __global__ __launch_bounds__(NT) void tslu_panel_kernel(NodeArgs p)
                 }
             });
             if (rem > 0) {
+                // the sub-panel's pivot rows as they were when selected
+                // (frozen since), from the threads that hold them
+                static_for<RPT>([&](auto QC) {
+                    constexpr int q = decltype(QC)::value;
+                    if (selstep[q] >= 0) {
+#pragma unroll
+                        for (int cc = 0; cc < BW; ++cc) s.PR[selstep[q]][cc] = x[q][cc];
+                    }
+                });
                 __syncthreads();
                 // U rows of the sub-panel's pivots at the rest of the block:
                 // PR[i][SP + c] -= sum_{l<i} PR[i][l] * U[l][SP + c]
