@@ -105,18 +105,28 @@ __device__ __forceinline__ double readlane_f64(double a, int l)
 
 __device__ __forceinline__ double max2(double a, double b) { return b > a ? b : a; }
 
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_rows_f64(double a)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(a), CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(a), CTRL, ROWS, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
 // Largest value over the wavefront, uniform across lanes: a DPP butterfly
 // inside each row of 16 lanes (xor 1, xor 2, half-mirror, mirror leave the
-// row's maximum in every lane of the row), then the four rows through
-// readlane.  Exact: only comparisons.
+// row's maximum in every lane of the row), then row broadcasts (lane 15 into
+// rows 1 and 3, lane 31 into rows 2 and 3) leave the wave's maximum in lane
+// 63.  Exact: only comparisons.
 __device__ __forceinline__ double wave_max(double a)
 {
     a = max2(a, dpp_f64<0xB1>(a));   // quad_perm [1,0,3,2]
     a = max2(a, dpp_f64<0x4E>(a));   // quad_perm [2,3,0,1]
     a = max2(a, dpp_f64<0x141>(a));  // row_half_mirror
     a = max2(a, dpp_f64<0x140>(a));  // row_mirror
-    return max2(max2(readlane_f64(a, 0), readlane_f64(a, 16)),
-                max2(readlane_f64(a, 32), readlane_f64(a, 48)));
+    a = max2(a, dpp_rows_f64<0x142, 0xA>(a));   // row_bcast:15
+    a = max2(a, dpp_rows_f64<0x143, 0xC>(a));   // row_bcast:31
+    return readlane_f64(a, 63);
 }
 
 // Smallest integer over the wavefront, uniform across lanes (same pattern).
@@ -145,12 +155,16 @@ struct BlockW {
     static constexpr int value = (64 / RPT) < 32 ? (64 / RPT) : 32;
 };
 
+struct __attribute__((aligned(16))) Slot {
+    double a;   // best score of the wave (-1: no candidate)
+    int g;      // smallest global row with that score
+    int p;      // its physical row in the node
+};
+
 template <int BW, int NWV>
 struct Lds {
     double cand[2][NWV][8];     // each wave's best row: its current sub-panel values
-    double slot_a[2][NWV];      // each wave's best score
-    int slot_g[2][NWV];         // ... the smallest global row holding it
-    int slot_p[2][NWV];         // ... and that row's physical index in the node
+    Slot slot[2][NWV];          // each wave's best score, row and physical row
     double RT[BW][BW + 8];      // RT[l][i] = multiplier of block pivot i on pivot l
     double PR[8][BW + 2];       // the current sub-panel's pivot rows
     union {
@@ -249,9 +263,11 @@ __global__ __launch_bounds__(NT) void tslu_panel_kernel(NodeArgs p)
     }
     for (int i = tid; i < r; i += NT) s.rowsel[i] = rselg[i];
     __syncthreads();
-    if (jb > 0) {
+    if (jb > 0 && p.root) {
         // the previous block's U rows (computed by the update launch) go
-        // into their pivot rows of the scratch block
+        // into their pivot rows of the scratch block; only the root's
+        // factored block is an output (other nodes hand on their selection
+        // alone, and a selected row is never read again by its node)
         const int pj0 = jb - BW, ncp = nsel - jb;
         for (int e = tid; e < BW * ncp; e += NT) {
             const int i = e / ncp, c = e - i * ncp;
@@ -297,8 +313,7 @@ __global__ __launch_bounds__(NT) void tslu_panel_kernel(NodeArgs p)
                 constexpr int j = decltype(JC)::value;
                 if (j < spc) {
                     const int par = j & 1;
-                    // this thread's scores, the wave's best score, then the
-                    // smallest global row holding it (exact, no branches)
+                    // this thread's scores and the wave's best score (exact)
                     double sc[RPT];
                     double m = -1.0;
                     static_for<RPT>([&](auto QC) {
@@ -307,43 +322,50 @@ __global__ __launch_bounds__(NT) void tslu_panel_kernel(NodeArgs p)
                         m = max2(m, sc[q]);
                     });
                     m = wave_max(m);
-                    int c = INT_MAX;
+                    // the smallest global row of this lane scoring m; one
+                    // lane holding m (the usual case) needs no reduction
+                    int lg = INT_MAX;
                     static_for<RPT>([&](auto QC) {
                         constexpr int q = decltype(QC)::value;
-                        c = sc[q] == m ? min(c, gid[q]) : c;
+                        lg = sc[q] == m ? min(lg, gid[q]) : lg;
                     });
-                    const int wg = wave_min(c);
-                    if (lane == 0) {
-                        s.slot_a[par][wave] = m;
-                        s.slot_g[par][wave] = wg;
-                    }
+                    const unsigned long long hits = __ballot(lg != INT_MAX);
+                    const int wg = __popcll(hits) == 1 ? __builtin_amdgcn_readlane(lg, __ffsll((long long)hits) - 1)
+                                                       : wave_min(lg);
                     // the row (unique: global rows are distinct) publishes its
-                    // sub-panel values from column j on
+                    // sub-panel values from column j on; a wave without
+                    // candidates publishes an empty slot
                     if (wg != INT_MAX) {
                         static_for<RPT>([&](auto QC) {
                             constexpr int q = decltype(QC)::value;
                             if (gid[q] == wg) {
-                                s.slot_p[par][wave] = tid + q * NT;
+                                s.slot[par][wave] = Slot{m, wg, tid + q * NT};
 #pragma unroll
                                 for (int cc = j; cc < SP; ++cc) s.cand[par][wave][cc] = x[q][cc];
                             }
                         });
+                    } else if (lane == 0) {
+                        s.slot[par][wave] = Slot{-1.0, INT_MAX, 0};
                     }
                     __syncthreads();
                     // the node's winner: best score, ties to the smallest
                     // global row (some row is live at every step, so the
-                    // best score is at least -0.5 and its wave published)
-                    double M = s.slot_a[par][0];
+                    // best score is at least -0.5)
+                    Slot sl[NW];
 #pragma unroll
-                    for (int w = 1; w < NW; ++w) M = max2(M, s.slot_a[par][w]);
+                    for (int w = 0; w < NW; ++w) sl[w] = s.slot[par][w];
+                    double M = sl[0].a;
+#pragma unroll
+                    for (int w = 1; w < NW; ++w) M = max2(M, sl[w].a);
                     int Gw = INT_MAX;
 #pragma unroll
-                    for (int w = 0; w < NW; ++w)
-                        Gw = s.slot_a[par][w] == M ? min(Gw, s.slot_g[par][w]) : Gw;
-                    int mw = 0;
+                    for (int w = 0; w < NW; ++w) Gw = sl[w].a == M ? min(Gw, sl[w].g) : Gw;
+                    int mw = 0, pw = sl[0].p;
 #pragma unroll
-                    for (int w = 1; w < NW; ++w) mw = s.slot_g[par][w] == Gw ? w : mw;
-                    const int pw = s.slot_p[par][mw];
+                    for (int w = 1; w < NW; ++w) {
+                        mw = sl[w].g == Gw ? w : mw;
+                        pw = sl[w].g == Gw ? sl[w].p : pw;
+                    }
                     const double *prow = &s.cand[par][mw][0];
                     if (tid == 0) {
                         s.sel[jb + sp0 + j] = Gw;
@@ -565,7 +587,7 @@ __global__ __launch_bounds__(256) void tslu_update_kernel(NodeArgs p, int tiles_
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
                     Ut[h + i][tid] = (h + i < bwc) ? -u[i] : 0.0;
-                    if (trow == 0 && h + i < bwc) utg[(size_t)(h + i) * UTLD + cc] = u[i];
+                    if (p.root && trow == 0 && h + i < bwc) utg[(size_t)(h + i) * UTLD + cc] = u[i];
                 }
             }
         } else {
