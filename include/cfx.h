@@ -81,6 +81,20 @@ typedef struct cfx_handle cfx_handle;
 int cfx_create(cfx_handle **h);
 int cfx_destroy(cfx_handle *h);
 
+/* Overlap tuning of cfx_getrf with lookahead = 1 (host-side settings of the
+ * handle; they change scheduling only, never a result bit).  While the next
+ * panel's tournament runs on the second stream, the rest of the Schur update
+ * is issued in launches of `chunk_cols` columns whose grid is bounded by
+ * `schur_workgroups` workgroups that walk the tiles persistently, so that
+ * the tournament's launches find free compute units at once.
+ *   schur_workgroups : 0 = one workgroup per tile (no bound; the default),
+ *                      else >= 8.
+ *   chunk_cols       : >= 1; default 512.
+ * Get: host int32 pointers (either may be NULL).  Set returns -2 / -3 for
+ * an invalid value. */
+int cfx_overlap_tuning(cfx_handle *h, int32_t *schur_workgroups, int32_t *chunk_cols);
+int cfx_set_overlap_tuning(cfx_handle *h, int32_t schur_workgroups, int32_t chunk_cols);
+
 /* Static description of the library build (host memory, NUL-terminated). */
 const char *cfx_version(void);
 

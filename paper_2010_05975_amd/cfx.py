@@ -112,6 +112,8 @@ def lib():
         L.cfx_batched_tune.argtypes = [vp, vp]
         L.cfx_batched_tuning.argtypes = [vp, vp]
         L.cfx_batched_set_tuning.argtypes = [vp, vp]
+        L.cfx_overlap_tuning.argtypes = [vp, vp, vp]
+        L.cfx_set_overlap_tuning.argtypes = [vp, i32, i32]
         L.cfx_serve_create.argtypes = [C.POINTER(ServeCfg), C.POINTER(vp)]
         L.cfx_serve_submit.argtypes = [vp, C.POINTER(Request), C.POINTER(C.c_uint64)]
         L.cfx_serve_poll.argtypes = [vp, C.c_uint64, C.POINTER(Result)]
@@ -353,6 +355,19 @@ def batched_set_tuning(vb, handle=None):
     h = handle or default_handle()
     t = (C.c_int32 * 5)(*vb)
     _check("cfx_batched_set_tuning", lib().cfx_batched_set_tuning(h.h, t))
+
+
+def overlap_tuning(handle=None):
+    """(schur_workgroups, chunk_cols) of cfx_getrf's lookahead overlap."""
+    h = handle or default_handle()
+    w, c = C.c_int32(), C.c_int32()
+    _check("cfx_overlap_tuning", lib().cfx_overlap_tuning(h.h, C.byref(w), C.byref(c)))
+    return w.value, c.value
+
+
+def set_overlap_tuning(schur_workgroups, chunk_cols, handle=None):
+    h = handle or default_handle()
+    _check("cfx_set_overlap_tuning", lib().cfx_set_overlap_tuning(h.h, int(schur_workgroups), int(chunk_cols)))
 
 
 SOLVE, RESOLVE = 0, 1

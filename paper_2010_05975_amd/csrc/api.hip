@@ -57,6 +57,10 @@ struct cfx_handle {
     size_t scratch_bytes = 0;
     cfx::Profiler prof;
     int cu_count = 256;
+    // grid bound of the Schur updates that overlap the next tournament
+    // (0: one workgroup per tile)
+    int schur_wgs = 0;
+    int64_t la_chunk = 512;         // columns per overlapped Schur launch
     // batched: panel width per size class (the tuner's table) and the graph
     // of the last batched call, replayed when the arguments repeat
     int32_t bvb[cfx::kBatchClasses] = {8, 16, 16, 32, 32};
@@ -74,10 +78,6 @@ namespace cfx {
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-#ifndef CFX_LOOKAHEAD_CHUNK
-#define CFX_LOOKAHEAD_CHUNK 512
-#endif
-constexpr int64_t kLookaheadChunk = CFX_LOOKAHEAD_CHUNK;   // columns per Schur launch with lookahead
 
 struct Layout {
     int64_t max_nodes, node_rows;
@@ -202,10 +202,10 @@ static IrLayout ir_layout(int64_t n, const cfx_ir_opts *o)
 // mixed-precision path the operands were packed once for the panel.
 static int schur_update(int precision, const Workspace &ws, const double *L21, const double *U12,
                         double *C, int64_t lda, int64_t m, int64_t col0, int64_t ncols, int vb,
-                        hipStream_t st)
+                        int max_wgs, hipStream_t st)
 {
     if (precision == CFX_PREC_FP64)
-        return launch_schur_f64(L21, lda, U12 + col0, lda, C + col0, lda, m, ncols, vb, st);
+        return launch_schur_f64(L21, lda, U12 + col0, lda, C + col0, lda, m, ncols, vb, max_wgs, st);
     return launch_schur_lp(precision, ws.scratch, m, vb, col0, ncols, C, lda, st);
 }
 
@@ -350,7 +350,7 @@ int cfx_getrf(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *ipiv, i
                 e = pf.begin(st);
                 if (prec != CFX_PREC_FP64 && (rc = launch_pack_lp(prec, L21, U12, lda, m, vb, ws.scratch, st)))
                     return rc;
-                if ((rc = schur_update(prec, ws, L21, U12, C, lda, m, 0, m, vb, st))) return rc;
+                if ((rc = schur_update(prec, ws, L21, U12, C, lda, m, 0, m, vb, 0, st))) return rc;
                 pf.end(PH_SCHUR, e, st, 2.0 * (double)m * (double)m * vb);
             }
             if (pf.on) ++pf.panels;
@@ -389,7 +389,7 @@ int cfx_getrf(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *ipiv, i
             e = pf.begin(st);
             if (prec != CFX_PREC_FP64 && (rc = launch_pack_lp(prec, L21, U12, lda, m, vb, ws.scratch, st)))
                 return rc;
-            if ((rc = schur_update(prec, ws, L21, U12, C, lda, m, 0, vbn, vb, st))) return rc;
+            if ((rc = schur_update(prec, ws, L21, U12, C, lda, m, 0, vbn, vb, 0, st))) return rc;
             pf.end(PH_SCHUR, e, st, 2.0 * (double)m * vbn * vb);
             // next panel's tournament on the side stream
             hipStream_t ts = side, us = st;
@@ -405,10 +405,11 @@ int cfx_getrf(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *ipiv, i
             // the rest of the update, in column chunks: between two chunks
             // the dispatcher can start the tournament's launches queued on
             // the side stream instead of leaving them behind one huge grid
-            for (int64_t c0 = vbn; c0 < m; c0 += kLookaheadChunk) {
-                const int64_t cw = (m - c0) < kLookaheadChunk ? (m - c0) : kLookaheadChunk;
+            const int64_t chunk = h->la_chunk;
+            for (int64_t c0 = vbn; c0 < m; c0 += chunk) {
+                const int64_t cw = (m - c0) < chunk ? (m - c0) : chunk;
                 e = pf.begin(us);
-                if ((rc = schur_update(prec, ws, L21, U12, C, lda, m, c0, cw, vb, us))) return rc;
+                if ((rc = schur_update(prec, ws, L21, U12, C, lda, m, c0, cw, vb, h->schur_wgs, us))) return rc;
                 pf.end(PH_SCHUR, e, us, 2.0 * (double)m * (double)cw * vb);
             }
 
@@ -654,6 +655,24 @@ int cfx_batched_tuning(cfx_handle *h, int32_t *vb)
     if (!h) return -1;
     if (!vb) return -2;
     for (int c = 0; c < kBatchClasses; ++c) vb[c] = h->bvb[c];
+    return CFX_OK;
+}
+
+int cfx_overlap_tuning(cfx_handle *h, int32_t *schur_workgroups, int32_t *chunk_cols)
+{
+    if (!h) return -1;
+    if (schur_workgroups) *schur_workgroups = h->schur_wgs;
+    if (chunk_cols) *chunk_cols = (int32_t)h->la_chunk;
+    return CFX_OK;
+}
+
+int cfx_set_overlap_tuning(cfx_handle *h, int32_t schur_workgroups, int32_t chunk_cols)
+{
+    if (!h) return -1;
+    if (schur_workgroups < 0 || (schur_workgroups > 0 && schur_workgroups < 8)) return -2;
+    if (chunk_cols < 1) return -3;
+    h->schur_wgs = schur_workgroups;
+    h->la_chunk = chunk_cols;
     return CFX_OK;
 }
 

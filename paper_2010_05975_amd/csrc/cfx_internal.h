@@ -79,9 +79,10 @@ int launch_trsm(double *A, int64_t lda, int64_t k, int vb, int64_t m,
                 hipStream_t st);
 
 // FactorizeA11: C[0:mr, 0:nc] -= L[0:mr, 0:K] * U[0:K, 0:nc]  (FP64 MFMA).
+// max_wgs > 0 bounds the grid (persistent workgroups walk the tiles)
 int launch_schur_f64(const double *L, int64_t ldl, const double *U, int64_t ldu,
                      double *C, int64_t ldc, int64_t mr, int64_t nc, int K,
-                     hipStream_t st);
+                     int max_wgs, hipStream_t st);
 
 // Mixed-precision FactorizeA11.  launch_pack_lp rounds L21 (m x K at L21)
 // and U12 (K x m at U12, both stride lda) to the working precision into

@@ -28,17 +28,15 @@ constexpr int LDB_S = BN + 16;
 constexpr int GROUP_M = 8;
 constexpr int NXCD = 8;
 
-__device__ __forceinline__ void tile_of(int bid, int nb, int tm, int tn, int &ti, int &tj)
+// Position `pos` of the regrouped order -> tile (ti, tj): grouped row-major,
+// GROUP_M tile rows at a time, so that consecutive positions share L21 and
+// U12 strips.
+__device__ __forceinline__ void tile_at(int pos, int tm, int tn, int &ti, int &tj)
 {
-    // XCD regrouping: hardware sends id b to XCD b % 8.
-    const int per = nb / NXCD;
-    int t = bid;
-    if (bid < per * NXCD) t = (bid % NXCD) * per + bid / NXCD;
-    // grouped row-major order inside the range
-    const int group = t / (GROUP_M * tn);
+    const int group = pos / (GROUP_M * tn);
     const int first = group * GROUP_M;
     const int gsz = (tm - first) < GROUP_M ? (tm - first) : GROUP_M;
-    const int r = t - group * GROUP_M * tn;
+    const int r = pos - group * GROUP_M * tn;
     ti = first + r % gsz;
     tj = r / gsz;
 }
@@ -55,8 +53,21 @@ __global__ __launch_bounds__(256, 2) void schur_f64_kernel(const double *__restr
     __shared__ double As[2][BK * LDA_S];
     __shared__ double Bs[2][BK * LDB_S];
 
+    // XCD-aware persistent schedule: the hardware sends workgroup b to XCD
+    // b % 8.  XCD x owns the contiguous positions [x*per, (x+1)*per) (plus
+    // position 8*per + x of the ragged end), and its workgroups walk them
+    // with a stride of their count, so the tiles that share operand strips
+    // stay in one L2.  With one workgroup per tile every workgroup takes
+    // exactly one position.
+    const int nb = tm * tn;
+    const int xcd = blockIdx.x % NXCD, slot = blockIdx.x / NXCD;
+    const int nsl = ((int)gridDim.x - xcd + NXCD - 1) / NXCD;   // workgroups on this XCD
+    const int per = nb / NXCD;
+    const int cnt = per + (xcd < nb - per * NXCD ? 1 : 0);
+#pragma unroll 1
+    for (int it = slot; it < cnt; it += nsl) {
     int ti, tj;
-    tile_of(blockIdx.x, gridDim.x, tm, tn, ti, tj);
+    tile_at(it < per ? xcd * per + it : NXCD * per + xcd, tm, tn, ti, tj);
     const int64_t i0 = (int64_t)ti * BM, j0 = (int64_t)tj * BN;
 
     const int tid = threadIdx.x;
@@ -166,16 +177,22 @@ __global__ __launch_bounds__(256, 2) void schur_f64_kernel(const double *__restr
                 if (!EDGE || (gi < mr && gj < nc)) C[gi * ldc + gj] = acc[a][b][q];
             }
         }
+    }   // tiles of this workgroup (the last K chunk ended with a barrier, so
+        // the next tile may refill the LDS buffers)
 }
 
 }  // namespace
 
 int launch_schur_f64(const double *L, int64_t ldl, const double *U, int64_t ldu, double *C,
-                     int64_t ldc, int64_t mr, int64_t nc, int K, hipStream_t st)
+                     int64_t ldc, int64_t mr, int64_t nc, int K, int max_wgs, hipStream_t st)
 {
     if (mr <= 0 || nc <= 0 || K <= 0) return CFX_OK;
     const int tm = (int)((mr + BM - 1) / BM), tn = (int)((nc + BN - 1) / BN);
-    const int64_t nb = (int64_t)tm * tn;
+    if ((int64_t)tm * tn > INT32_MAX) return CFX_ENOTSUP;
+    int64_t nb = (int64_t)tm * tn;
+    // a bounded grid (at least one workgroup per XCD) walks the tiles
+    // persistently and leaves the rest of the device to concurrent work
+    if (max_wgs > 0 && max_wgs < nb) nb = max_wgs < NXCD ? NXCD : max_wgs;
     const bool full = (mr % BM == 0) && (nc % BN == 0) && (K % BK == 0);
     const bool vec = ((reinterpret_cast<uintptr_t>(L) | reinterpret_cast<uintptr_t>(U)) & 15) == 0 &&
                      (ldl % 2 == 0) && (ldu % 2 == 0);

@@ -172,3 +172,28 @@ def test_getrf_lookahead_bitwise_equal(cfx, n, v, L):
     b = run_getrf(cfx, A, v, L, 1)
     assert np.array_equal(a[1], b[1])
     assert np.array_equal(a[0], b[0])
+
+
+@pytest.mark.parametrize("n,wgs,chunk", [(2100, 8, 64), (2100, 12, 300), (2100, 40, 4096), (2048, 8, 256),
+                                         (2048, 24, 4096)])
+def test_getrf_bounded_schur_grid_bitwise_equal(cfx, n, wgs, chunk):
+    """The overlapped Schur launches with a bounded, persistent grid (few
+    workgroups walking many tiles, in narrow or wide column chunks, ragged
+    or whole tiles) change scheduling only: the factors are bitwise those of
+    the plain schedule."""
+    v, L = 128, 4
+    say(f"bounded schur grid wgs={wgs} chunk={chunk} n={n}")
+    A = G.normal_matrix(n, 12)
+    ref = run_getrf(cfx, A, v, L, 0)
+    h = cfx.Handle()
+    try:
+        cfx.set_overlap_tuning(wgs, chunk, handle=h)
+        assert cfx.overlap_tuning(handle=h) == (wgs, chunk)
+        dA = to_dev(A)
+        ipiv, info = cfx.getrf(dA, v=v, leaves=L, lookahead=1, handle=h)
+        torch.cuda.synchronize()
+    finally:
+        h.close()
+    assert int(info.cpu()[0]) == ref[2]
+    assert np.array_equal(ipiv.cpu().numpy(), ref[1])
+    assert np.array_equal(dA.cpu().numpy(), ref[0])
