@@ -10,12 +10,16 @@
 //
 // L21 = A21 U00^{-1} and U12 = L00^{-1} A12 are one solve shape: X U = B
 // with U upper triangular, for X = L21 (U = U00) and for X = U12^T
-// (U = L00^T, unit diagonal).  One wavefront owns a strip of 16 rows of X
-// (16 rows of L21, or 16 columns of U12 read transposed) in LDS and sweeps
-// 32-column blocks left to right: the finished blocks are applied on the
-// FP64 matrix cores (X_b -= X_{<b} U_{<b,b}), then each lane solves one row
-// against the 32 x 32 diagonal triangle by substitution with true division
-// (a zero diagonal leaves that column unscaled).
+// (U = L00^T, unit diagonal).  A workgroup of 4 wavefronts owns 64 rows of
+// X (rows of L21, or columns of U12 read transposed), 16 per wavefront,
+// kept in registers in the matrix cores' operand layout, and sweeps
+// 32-column blocks left to right.  Per block the workgroup stages the U
+// columns of the block once in LDS; each wavefront applies its finished
+// blocks on the FP64 matrix cores (X_b -= X_{<b} U_{<b,b}), then 16 lanes
+// solve their rows against the 32 x 32 diagonal triangle by substitution
+// with true division (a zero diagonal leaves that column unscaled).
+#include <utility>
+
 #include "cfx_internal.h"
 
 namespace cfx {
@@ -60,12 +64,26 @@ __global__ __launch_bounds__(256) void laswp_kernel(double *A, int64_t lda, int6
 // triangular solves
 // ---------------------------------------------------------------------------
 constexpr int TSB = 32;               // diagonal block of the solve
-constexpr int TSR = 16;               // rows of X per wavefront
-constexpr int XLD = kMaxV + 4;        // padded LDS row of the strip
+constexpr int TSW = 16;               // rows of X per wavefront
+constexpr int TSR = 4 * TSW;          // rows of X per workgroup
+constexpr int ULD = TSB + 1;          // padded LDS row of the staged U block
+constexpr int NCH = kMaxV / 4;        // 4-column chunks of a row of X
 
 typedef double d4t __attribute__((ext_vector_type(4)));
 
+template <typename F, int... J>
+__device__ __forceinline__ void sfor_impl(F &&f, std::integer_sequence<int, J...>)
+{
+    (f(std::integral_constant<int, J>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void sfor(F &&f)
+{
+    sfor_impl(f, std::make_integer_sequence<int, N>{});
+}
+
 // U(r, c) of the solve: U00 for L21 (mode 0), L00^T for U12 (mode 1).
+// Only r <= c is ever read.
 template <int MODE>
 __device__ __forceinline__ double uval(const double *P, int64_t lda, int r, int c)
 {
@@ -74,99 +92,120 @@ __device__ __forceinline__ double uval(const double *P, int64_t lda, int r, int 
 }
 
 template <int MODE>
-__global__ __launch_bounds__(64) void trsm_kernel(double *A, int64_t lda, int64_t k, int vb, int64_t m)
+__global__ __launch_bounds__(256) void trsm_kernel(double *A, int64_t lda, int64_t k, int vb, int64_t m)
 {
-    __shared__ double X[TSR][XLD];
-    __shared__ double Ub[TSB][TSB + 1];
-    const int lane = threadIdx.x;
+    __shared__ double Us[kMaxV * ULD];      // U[0 : c0+32, c0 : c0+32] of the block
+    __shared__ double Sb[4][TSW][ULD];      // per wavefront: the block's rows (inputs, then solution)
+    __shared__ double Sg[4][TSW][ULD];      // per wavefront: X_{<b} U_{<b,b} of the block
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lk = lane >> 4;
-    const int64_t r0 = (int64_t)blockIdx.x * TSR;
-    const int rows = (m - r0) < TSR ? (int)(m - r0) : TSR;
-    const double *P = A + k * lda + k;     // the panel's diagonal block
-    // X[i][c]: L21 row r0+i (mode 0) or U12 column r0+i (mode 1)
-    auto xaddr = [&](int i, int c) -> double * {
-        if constexpr (MODE == 0) return A + (k + vb + r0 + i) * lda + k + c;
-        else return A + (k + c) * lda + k + vb + r0 + i;
+    const int64_t row = (int64_t)blockIdx.x * TSR + wave * TSW + lr;   // this lane's row of X
+    const bool rok = row < m;
+    const double *P = A + k * lda + k;      // the panel's diagonal block
+    auto xaddr = [&](int c) -> double * {
+        if constexpr (MODE == 0) return A + (k + vb + row) * lda + k + c;
+        else return A + (k + c) * lda + k + vb + row;
     };
-    for (int e = lane; e < TSR * vb; e += 64) {
-        int i, c;
-        if constexpr (MODE == 0) { i = e / vb; c = e - i * vb; }
-        else { c = e / TSR; i = e - c * TSR; }      // 16 consecutive columns of A12 per row
-        X[i][c] = i < rows ? *xaddr(i, c) : 0.0;
-    }
-    __syncthreads();
-    for (int b0 = 0; b0 < vb; b0 += TSB) {
-        const int bc = (vb - b0) < TSB ? (vb - b0) : TSB;
-        // X_b -= X[:, 0:b0] U[0:b0, b0:b0+bc] (two 16 x 16 tiles)
-        if (b0 > 0) {
-            d4t acc[2];
+    // xa[s] = X[row][4s + lk]: the A operand layout of v_mfma_f64_16x16x4f64
+    // (lane l holds row l%16, column l/16 of each 16 x 4 slice)
+    double xa[NCH];
+    sfor<NCH>([&](auto SC) {
+        constexpr int sc = decltype(SC)::value;
+        const int c = 4 * sc + lk;
+        xa[sc] = (rok && c < vb) ? *xaddr(c) : 0.0;
+    });
+
+    // U[0 : c0+32, c0 : c0+32] of block b, this thread's share in registers;
+    // the next block's share is fetched while the current block computes
+    // element i of this thread: (r, c) = (e / 32, e % 32) with e = tid + 256 i
+    // for U00 (rows of 32 consecutive doubles), (tid, i) for L00^T (columns
+    // of L00 read down, consecutive threads on consecutive addresses)
+    constexpr int NPRE = kMaxV * TSB / 256;
+    auto elem = [&](int i, int &r, int &c) {
+        if constexpr (MODE == 0) { r = (tid + 256 * i) >> 5; c = tid & 31; }
+        else { r = tid; c = i; }
+    };
+    double pre[NPRE];
+    auto fetch_u = [&](int c0f) {
+        const int bcf = (vb - c0f) < TSB ? (vb - c0f) : TSB;
+        const int krf = c0f + bcf;
 #pragma unroll
-            for (int t = 0; t < 2; ++t)
+        for (int i = 0; i < NPRE; ++i) {
+            int r, c;
+            elem(i, r, c);
+            pre[i] = (r < krf && c < bcf && r <= c0f + c) ? uval<MODE>(P, lda, r, c0f + c) : 0.0;
+        }
+    };
+    fetch_u(0);
+
+    sfor<kMaxV / TSB>([&](auto BC) {
+        constexpr int b = decltype(BC)::value;
+        constexpr int c0 = TSB * b;
+        if (c0 < vb) {
+            const int bc = (vb - c0) < TSB ? (vb - c0) : TSB;
+            const int kr = c0 + bc;
+            __syncthreads();                    // the previous block's readers are done
 #pragma unroll
-                for (int q = 0; q < 4; ++q) acc[t][q] = X[lk + 4 * q][b0 + 16 * t + lr];
-            // b0 is a multiple of 32: chunks of 8 k-steps, all operand loads
-            // of a chunk issued before its matrix-core operations
-            const bool c0ok = b0 + lr < vb, c1ok = b0 + 16 + lr < vb;
-            for (int kc = 0; kc < b0; kc += 32) {
-                double av[8], bv[8][2];
+            for (int i = 0; i < NPRE; ++i) {
+                int r, c;
+                elem(i, r, c);
+                if (r < kr) Us[r * ULD + c] = pre[i];
+            }
+            if (c0 + TSB < vb) fetch_u(c0 + TSB);
+            // the block's current values, operand layout -> rows
+            sfor<TSB / 4>([&](auto SC) {
+                constexpr int sc = decltype(SC)::value;
+                Sb[wave][lr][4 * sc + lk] = xa[TSB / 4 * b + sc];
+            });
+            __syncthreads();
+            // X_{<b} U_{<b,b} on the matrix cores (two 16 x 16 tiles)
+            d4t g0 = {0.0, 0.0, 0.0, 0.0}, g1 = {0.0, 0.0, 0.0, 0.0};
+            sfor<TSB / 4 * b>([&](auto SC) {
+                constexpr int sc = decltype(SC)::value;
+                const double u0 = Us[(4 * sc + lk) * ULD + lr];
+                const double u1 = Us[(4 * sc + lk) * ULD + 16 + lr];
+                g0 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[sc], u0, g0, 0, 0, 0);
+                g1 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[sc], u1, g1, 0, 0, 0);
+            });
+            // result layout: lane l holds rows l/16 + 4q of column l%16
 #pragma unroll
-                for (int s8 = 0; s8 < 8; ++s8) {
-                    const int kr = kc + 4 * s8 + lk;
-                    av[s8] = -X[lr][kr];
-                    bv[s8][0] = c0ok ? uval<MODE>(P, lda, kr, b0 + lr) : 0.0;
-                    bv[s8][1] = c1ok ? uval<MODE>(P, lda, kr, b0 + 16 + lr) : 0.0;
-                }
-#pragma unroll
-                for (int s8 = 0; s8 < 8; ++s8)
-#pragma unroll
-                    for (int t = 0; t < 2; ++t)
-                        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s8], bv[s8][t], acc[t], 0, 0, 0);
+            for (int q = 0; q < 4; ++q) {
+                Sg[wave][lk + 4 * q][lr] = g0[q];
+                Sg[wave][lk + 4 * q][16 + lr] = g1[q];
             }
             __syncthreads();
+            if (lane < TSW) {
+                double x[TSB];
 #pragma unroll
-            for (int t = 0; t < 2; ++t)
+                for (int j = 0; j < TSB; ++j) x[j] = Sb[wave][lane][j] - Sg[wave][lane][j];
+                // substitution against the diagonal triangle, column by
+                // column (x_c -= x_j U[j][c] in increasing j for every c)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int c = b0 + 16 * t + lr;
-                    if (c < vb) X[lk + 4 * q][c] = acc[t][q];
-                }
-        }
-        // the diagonal block of U
-        for (int e = lane; e < bc * bc; e += 64) {
-            const int r = e / bc, c = e - r * bc;
-            Ub[r][c] = uval<MODE>(P, lda, b0 + r, b0 + c);
-        }
-        __syncthreads();
-        if (lane < TSR) {
-            double x[TSB];
+                for (int j = 0; j < TSB; ++j) {
+                    if (j < bc) {
+                        if constexpr (MODE == 0) {
+                            const double d = Us[(c0 + j) * ULD + j];
+                            x[j] = d != 0.0 ? x[j] / d : x[j];
+                        }
 #pragma unroll
-            for (int j = 0; j < TSB; ++j) x[j] = j < bc ? X[lane][b0 + j] : 0.0;
-#pragma unroll
-            for (int j = 0; j < TSB; ++j) {
-                if (j < bc) {
-                    double sj = x[j];
-#pragma unroll
-                    for (int l = 0; l < j; ++l) sj -= x[l] * Ub[l][j];
-                    if constexpr (MODE == 0) {
-                        const double d = Ub[j][j];
-                        x[j] = d != 0.0 ? sj / d : sj;
-                    } else {
-                        x[j] = sj;
+                        for (int c = j + 1; c < TSB; ++c) x[c] -= x[j] * Us[(c0 + j) * ULD + c];
                     }
                 }
-            }
 #pragma unroll
-            for (int j = 0; j < TSB; ++j)
-                if (j < bc) X[lane][b0 + j] = x[j];
+                for (int j = 0; j < TSB; ++j) Sb[wave][lane][j] = x[j];
+            }
+            __syncthreads();
+            sfor<TSB / 4>([&](auto SC) {
+                constexpr int sc = decltype(SC)::value;
+                xa[TSB / 4 * b + sc] = Sb[wave][lr][4 * sc + lk];
+            });
         }
-        __syncthreads();
-    }
-    for (int e = lane; e < TSR * vb; e += 64) {
-        int i, c;
-        if constexpr (MODE == 0) { i = e / vb; c = e - i * vb; }
-        else { c = e / TSR; i = e - c * TSR; }
-        if (i < rows) *xaddr(i, c) = X[i][c];
-    }
+    });
+    sfor<NCH>([&](auto SC) {
+        constexpr int sc = decltype(SC)::value;
+        const int c = 4 * sc + lk;
+        if (rok && c < vb) *xaddr(c) = xa[sc];
+    });
 }
 
 __global__ void set_int_kernel(int32_t *p, int32_t v) { *p = v; }
@@ -187,9 +226,9 @@ int launch_trsm(double *A, int64_t lda, int64_t k, int vb, int64_t m, hipStream_
 {
     if (m <= 0) return CFX_OK;
     const unsigned g = (unsigned)((m + TSR - 1) / TSR);
-    hipLaunchKernelGGL(trsm_kernel<0>, dim3(g), dim3(64), 0, st, A, lda, k, vb, m);
+    hipLaunchKernelGGL(trsm_kernel<0>, dim3(g), dim3(256), 0, st, A, lda, k, vb, m);
     CFX_HIP(hipGetLastError());
-    hipLaunchKernelGGL(trsm_kernel<1>, dim3(g), dim3(64), 0, st, A, lda, k, vb, m);
+    hipLaunchKernelGGL(trsm_kernel<1>, dim3(g), dim3(256), 0, st, A, lda, k, vb, m);
     CFX_HIP(hipGetLastError());
     return CFX_OK;
 }
