@@ -217,7 +217,8 @@ def serve_leg(cfx, G, torch, rate, duration, seed, arena_gb, slots, nmax):
     sides, 30 % re-solves of an earlier request's factors (kept resident).
     The inputs are built on the device before the clock starts; requests are
     submitted at their arrival times from this thread.  Run once with FP64
-    factors and once with BF16 factors + GMRES-IR (target 5e-15)."""
+    factors and once with BF16 factors + GMRES-IR (target 5e-15; a request
+    whose refinement does not reach it in 3 outer steps refactors in FP64)."""
     dev = torch.device("cuda:0")
     reqs = G.serving_stream(rate, duration, seed, nmax=nmax)
     built = []
@@ -235,8 +236,8 @@ def serve_leg(cfx, G, torch, rate, duration, seed, arena_gb, slots, nmax):
     out = {"rate_per_s": rate, "duration_s": duration, "requests": len(reqs), "n_range": [64, nmax],
            "arena_gb": arena_gb, "slots": slots}
     for prec in ("fp64", "bf16"):
-        kw = dict(precision=prec, v=256 if prec == "fp64" else 256, leaves=8, tol=5e-15,
-                  max_outer=4 if prec == "fp64" else 30, gmres_restart=30, gmres_tol=1e-6)
+        kw = dict(precision=prec, v=256, leaves=8, tol=5e-15,
+                  max_outer=4 if prec == "fp64" else 3, gmres_restart=20, gmres_tol=1e-6)
         srv = cfx.Server(int(arena_gb * (1 << 30)), max_slots=slots, **kw)
         tickets = [None] * len(reqs)
         xs = [torch.zeros_like(b) for _, b in built]
@@ -291,6 +292,7 @@ def serve_leg(cfx, G, torch, rate, duration, seed, arena_gb, slots, nmax):
                      "eta_max": float(etas.max()) if len(etas) else None,
                      "eta_le_5e-15": int(np.sum(etas <= 5e-15)),
                      "resolves": len(resolves), "resident_hits": hits,
+                     "fp64_fallbacks": sum(1 for r in ok if r.get("fallback", 0)),
                      "batched_requests": st["batched_requests"], "evictions": st["evictions"],
                      "bytes_peak_gb": round(st["bytes_peak"] / 2**30, 2)}
         log(f"serve {prec}: {out[prec]}")

@@ -251,7 +251,9 @@ int cfx_batched_set_tuning(cfx_handle *h, const int32_t *vb);
  * cfx_gesv_batched launch (FP64; their factors may be kept resident too).
  * Larger systems are factored by cfx_getrf with the configured precision
  * and solved with cfx_getrs semantics (FP64), refined by GMRES-IR
- * (BF16/FP16).  Every result reports its eta (as cfx_gesv_ir), and its
+ * (BF16/FP16); when refinement from low-precision factors does not reach
+ * ir.tol within ir.max_outer steps, the request refactors in FP64 and
+ * solves again.  Every result reports its eta (as cfx_gesv_ir), and its
  * arithmetic does not depend on what else runs: a request gives the same
  * bits alone and in a mix.
  * ------------------------------------------------------------------------ */
@@ -305,6 +307,9 @@ typedef struct {
     double eta;          /* backward error of X (max over right-hand sides) */
     double t_submit, t_admit, t_start, t_done; /* seconds, steady clock,
                             from server creation                           */
+    int32_t fallback;    /* 1: the low-precision factors did not reach the
+                            refinement target, so the request refactored A
+                            in FP64 (the resident factors are FP64 since)  */
 } cfx_result;
 
 typedef struct {

@@ -55,7 +55,8 @@ class Result(C.Structure):
     _fields_ = [("status", C.c_int32), ("info", C.c_int32), ("factor_id", C.c_uint64),
                 ("resident_hit", C.c_int32), ("batched", C.c_int32), ("outer", C.c_int32),
                 ("inner", C.c_int32), ("eta", C.c_double), ("t_submit", C.c_double),
-                ("t_admit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double)]
+                ("t_admit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double),
+                ("fallback", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

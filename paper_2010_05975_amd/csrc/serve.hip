@@ -88,6 +88,7 @@ struct Resident {
     int32_t *ipiv = nullptr, *perm = nullptr;
     int refs = 0;
     int32_t info = 0;
+    int32_t prec = CFX_PREC_FP64;   // precision the factors were computed in
     bool keep = false;
     uint64_t last_use = 0;
 };
@@ -345,24 +346,42 @@ int run_single(cfx_server *S, cfx_handle *h, hipStream_t st, Job *j)
     int rc = CFX_OK;
     int32_t info = 0;
     j->res.t_start = S->now();
-    if (!j->hit) {
-        SRV_HIP(hipMemcpy2DAsync(f->F, (size_t)n * 8, r.A, (size_t)r.lda * 8, (size_t)n * 8, (size_t)n,
-                                 hipMemcpyDeviceToDevice, st));
-        SRV_CHECK(cfx_getrf(h, n, f->F, n, f->ipiv, dinfo, &S->cfg.ir.lu, wk, wbytes, st));
-        SRV_CHECK(launch_perm(n, f->ipiv, f->perm, st));
-        SRV_HIP(hipMemcpyAsync(&info, dinfo, 4, hipMemcpyDeviceToHost, st));
-        SRV_HIP(hipStreamSynchronize(st));
+    // factor A into f (FP64 or the configured precision)
+    auto factor = [&](const cfx_lu_opts &o) -> int {
+        int rc2 = CFX_OK;
+        if (hipMemcpy2DAsync(f->F, (size_t)n * 8, r.A, (size_t)r.lda * 8, (size_t)n * 8, (size_t)n,
+                             hipMemcpyDeviceToDevice, st) != hipSuccess)
+            return CFX_EHIP;
+        if ((rc2 = cfx_getrf(h, n, f->F, n, f->ipiv, dinfo, &o, wk, wbytes, st))) return rc2;
+        if ((rc2 = launch_perm(n, f->ipiv, f->perm, st))) return rc2;
+        if (hipMemcpyAsync(&info, dinfo, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return CFX_EHIP;
         f->info = info;
-    }
-    j->res.info = f->info;
+        f->prec = o.precision;
+        return CFX_OK;
+    };
+    if (!j->hit) SRV_CHECK(factor(S->cfg.ir.lu));
     j->res.eta = 0.0;
     for (int64_t c = 0; c < r.nrhs; ++c) {
-        SRV_CHECK(launch_copy_rows(n, 1, r.B + c, r.ldb, v.b, 1, st));
-        SRV_CHECK(launch_gather_rows(n, 1, v.b, 1, f->perm, v.x, 1, st));
-        SRV_CHECK(launch_trsv(n, 1, f->F, n, v.x, 1, st));
         IrResult ir{};
-        SRV_CHECK(ir_refine(r.A, r.lda, f->F, n, f->perm, v, p, &ir, st));
+        for (;;) {
+            SRV_CHECK(launch_copy_rows(n, 1, r.B + c, r.ldb, v.b, 1, st));
+            SRV_CHECK(launch_gather_rows(n, 1, v.b, 1, f->perm, v.x, 1, st));
+            SRV_CHECK(launch_trsv(n, 1, f->F, n, v.x, 1, st));
+            ir = IrResult{};
+            SRV_CHECK(ir_refine(r.A, r.lda, f->F, n, f->perm, v, p, &ir, st));
+            if (ir.converged || f->prec == CFX_PREC_FP64) break;
+            // low-precision factors that do not reach the target: refactor
+            // in FP64 (the factors stay upgraded for later re-solves) and
+            // solve this right-hand side again
+            cfx_lu_opts o64 = S->cfg.ir.lu;
+            o64.precision = CFX_PREC_FP64;
+            SRV_CHECK(factor(o64));
+            j->res.fallback = 1;
+        }
         SRV_CHECK(launch_copy_rows(n, 1, v.x, 1, r.X + c, r.ldx, st));
+        j->res.info = f->info;
         if (ir.eta > j->res.eta || ir.eta != ir.eta) j->res.eta = ir.eta;
         j->res.outer = std::max(j->res.outer, (int32_t)ir.outer);
         j->res.inner += ir.inner;

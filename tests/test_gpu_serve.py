@@ -85,6 +85,37 @@ def test_serve_alone_equals_mix_and_oracle(cfx, prec):
         assert ra["t_submit"] <= ra["t_admit"] <= ra["t_start"] <= ra["t_done"], tag
 
 
+def test_serve_lowp_falls_back_to_fp64(cfx):
+    """BF16 factors of a cond-1e12 system cannot be refined to 5e-15 in three
+    outer steps: the request refactors in FP64, reports it, still meets the
+    target, and its resident factors stay FP64 for the re-solve.  A
+    well-conditioned request of the same server needs no fallback."""
+    say("serve low-precision fallback")
+    srv = cfx.Server(4 << 30, max_slots=2, precision="bf16", v=128, leaves=4, tol=5e-15,
+                     max_outer=3, gmres_restart=20, gmres_tol=1e-6)
+    try:
+        n = 700
+        hard = G.householder_matrix(G.householder_spec(n, 1e12, 31))
+        easy = G.householder_matrix(G.householder_spec(n, 1e2, 32))
+        B = G.rhs(n, 2, 33)
+        dH, dE = to_dev(hard), to_dev(easy)
+        Xh = torch.zeros((n, 2), dtype=torch.float64, device="cuda")
+        Xe = torch.zeros((n, 2), dtype=torch.float64, device="cuda")
+        rh = srv.wait(srv.submit(dH, to_dev(B), Xh, keep_resident=True))
+        re_ = srv.wait(srv.submit(dE, to_dev(B), Xe))
+        say(f"  hard {rh}\n  easy {re_}")
+        assert rh["status"] == 0 and rh["fallback"] == 1
+        assert O.eta(hard, Xh.cpu().numpy(), B) <= 5e-15
+        assert re_["status"] == 0 and re_["fallback"] == 0
+        assert O.eta(easy, Xe.cpu().numpy(), B) <= 5e-15
+        X2 = torch.zeros((n, 2), dtype=torch.float64, device="cuda")
+        r2 = srv.wait(srv.submit(dH, to_dev(B), X2, kind=cfx.RESOLVE, factor_id=rh["factor_id"]))
+        assert r2["resident_hit"] == 1 and r2["fallback"] == 0 and r2["status"] == 0
+        assert O.eta(hard, X2.cpu().numpy(), B) <= 5e-15
+    finally:
+        srv.close()
+
+
 def test_serve_resident_resolve_and_release(cfx):
     say("serve resident factors")
     srv = cfx.Server(4 << 30, max_slots=2, precision="fp64", v=64, leaves=4, max_outer=4)
