@@ -476,7 +476,7 @@ int cfx_gesv_ir(cfx_handle *h, int64_t n, int64_t nrhs, const double *A, int64_t
     for (int64_t c = 0; c < nrhs; ++c) {
         if ((rc = launch_copy_rows(n, 1, B + c, ldb, v.b, 1, st))) return rc;
         if ((rc = launch_gather_rows(n, 1, v.b, 1, perm, v.x, 1, st))) return rc;
-        if ((rc = launch_trsv(n, 1, F, n, v.x, 1, st))) return rc;
+        if ((rc = launch_trsv(n, 1, F, n, v.x, 1, v.sync, st))) return rc;
         IrResult res{};
         if ((rc = ir_refine(A, lda, F, n, perm, v, p, &res, st))) return rc;
         if ((rc = launch_copy_rows(n, 1, v.x, 1, X + c, ldx, st))) return rc;
@@ -718,13 +718,14 @@ int cfx_getrs(cfx_handle *h, int64_t n, int64_t nrhs, const double *LU, int64_t 
     if (!B && n > 0 && nrhs > 0) return -7;
     if (ldb < (nrhs > 1 ? nrhs : 1)) return -8;
     if (n == 0 || nrhs == 0) return CFX_OK;
-    const size_t need = align_up((size_t)n * sizeof(int32_t)) + (size_t)n * nrhs * sizeof(double);
+    const size_t need = kTrsvSyncBytes + align_up((size_t)n * sizeof(int32_t)) + (size_t)n * nrhs * sizeof(double);
     int rc = ensure_scratch(h, need);
     if (rc) return rc;
-    int32_t *perm = static_cast<int32_t *>(h->scratch);
-    double *tmp = reinterpret_cast<double *>(static_cast<char *>(h->scratch) +
+    int32_t *sync = static_cast<int32_t *>(h->scratch);
+    int32_t *perm = reinterpret_cast<int32_t *>(static_cast<char *>(h->scratch) + kTrsvSyncBytes);
+    double *tmp = reinterpret_cast<double *>(static_cast<char *>(h->scratch) + kTrsvSyncBytes +
                                              align_up((size_t)n * sizeof(int32_t)));
-    return launch_getrs(n, nrhs, LU, lda, ipiv, B, ldb, perm, tmp, static_cast<hipStream_t>(stream));
+    return launch_getrs(n, nrhs, LU, lda, ipiv, B, ldb, perm, tmp, sync, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

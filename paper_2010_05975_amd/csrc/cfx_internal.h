@@ -56,7 +56,7 @@ int launch_tslu(const double *W, int64_t ldw, int64_t row0, int64_t rows, int vb
 // getrs pieces: permutation of ipiv, and the blocked triangular solves.
 int launch_getrs(int64_t n, int64_t nrhs, const double *LU, int64_t lda,
                  const int32_t *ipiv, double *B, int64_t ldb, int32_t *perm,
-                 double *tmp, hipStream_t st);
+                 double *tmp, int32_t *sync, hipStream_t st);
 // perm[i] = source row of row i of P B (ipiv interchanges composed).
 int launch_perm(int64_t n, const int32_t *ipiv, int32_t *perm, hipStream_t st);
 // T[i, :] = B[perm[i], :]  /  B[i, :] = T[i, :]   (n x nrhs).
@@ -64,9 +64,13 @@ int launch_gather_rows(int64_t n, int64_t nrhs, const double *B, int64_t ldb,
                        const int32_t *perm, double *T, int64_t ldt, hipStream_t st);
 int launch_copy_rows(int64_t n, int64_t nrhs, const double *T, int64_t ldt,
                      double *B, int64_t ldb, hipStream_t st);
-// X <- U^{-1} L^{-1} X in place (X n x nrhs, stride ldx).
+// X <- U^{-1} L^{-1} X in place (X n x nrhs, stride ldx).  `sync` (device,
+// kTrsvSyncBytes, may be null) lets one contiguous right-hand side take the
+// one-launch-per-triangle solve; calls sharing a sync buffer must be
+// stream-ordered.
+constexpr size_t kTrsvSyncBytes = 256;
 int launch_trsv(int64_t n, int64_t nrhs, const double *LU, int64_t lda, double *X,
-                int64_t ldx, hipStream_t st);
+                int64_t ldx, int32_t *sync, hipStream_t st);
 
 // Apply the row-move plan to all n columns of A; the diagonal block of the
 // panel (rows k..k+vb, columns k..k+vb) is written from ws.lu00.
@@ -132,6 +136,7 @@ struct IrVectors {
     int64_t ldv;
     double *partial;    // block partial sums
     double *out;        // small reduction results
+    int32_t *sync;      // counters of the triangular solves (kTrsvSyncBytes)
 };
 struct IrParams {
     double tol;

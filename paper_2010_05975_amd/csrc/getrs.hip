@@ -308,6 +308,156 @@ __global__ __launch_bounds__(256) void bwd_step_kernel(const double *__restrict_
     diag_upper<NRC>(LU, lda, X, ldx, cc, nc, r0, bsn, yh);
 }
 
+// ---------------------------------------------------------------------------
+// One right-hand side: one launch per triangle.  Blocks of TB rows take
+// tickets in solve order (top down for L, bottom up for U); a block applies
+// the solved blocks as they appear (a release counter of solved blocks,
+// bumped in order), then solves its diagonal block in one wavefront and
+// publishes it.  A block only waits for blocks with smaller tickets, which
+// were taken by running workgroups, so every wait ends; each factor element
+// is still read once.  Per row the sum runs over the blocks in solve order,
+// 16 columns per lane, then a fixed quad reduction: the result does not
+// depend on timing.
+// ---------------------------------------------------------------------------
+constexpr int TB = 64;
+constexpr int kSpinLimit = 1 << 22;   // polls before a block gives up (sets sync[4])
+
+__global__ void trsv_sync_reset_kernel(int32_t *sync)
+{
+    if (threadIdx.x < 8) sync[threadIdx.x] = 0;
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double a)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(a), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(a), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// LOWER: L y = x with unit L (forward); else U x = y (backward).
+// sync[0..1] forward ticket / solved count, sync[2..3] backward, sync[4]
+// set when a wait gave up (never, when the tickets order the blocks).
+template <bool LOWER>
+__global__ __launch_bounds__(256) void trsv_sf_kernel(const double *__restrict__ LU, int64_t lda, double *x,
+                                                      int64_t n, int nb, int32_t *sync)
+{
+    __shared__ double part[TB];
+    __shared__ int sh_t, sh_avail;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int32_t *ticket = sync + (LOWER ? 0 : 2);
+    int32_t *solved = sync + (LOWER ? 1 : 3);
+    if (tid == 0) sh_t = atomicAdd(ticket, 1);
+    __syncthreads();
+    const int t = sh_t;
+    const int J = LOWER ? t : nb - 1 - t;
+    const int64_t r0 = (int64_t)J * TB;
+    const int rows = (n - r0) < TB ? (int)(n - r0) : TB;
+    const int rr = 16 * wave + (lane >> 2);     // this lane's row of the block
+    const int cq = (lane & 3) * 16;              // its 16 columns of a block
+    const bool rok = rr < rows;
+    const double *lrow = LU + (r0 + (rok ? rr : 0)) * lda;
+    const int nk = t;                            // blocks to apply, in solve order
+    auto kcol = [&](int i) -> int64_t { return (int64_t)(LOWER ? i : nb - 1 - i) * TB + cq; };
+    auto load_l = [&](int i, double *lv) {
+        const int64_t c0 = kcol(i);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) lv[e] = (rok && c0 + e < n) ? lrow[c0 + e] : 0.0;
+    };
+    // the diagonal block's row and right-hand side of wave 0's lanes, fetched
+    // before any wait (they do not depend on other blocks)
+    const bool ok = wave == 0 && lane < rows;
+    const int64_t gi = r0 + (ok ? lane : 0);
+    const double *drow = LU + gi * lda + r0;
+    double Tr[TB];      // L: columns j < lane; U: columns j > lane
+#pragma unroll
+    for (int j = 0; j < TB; ++j) Tr[j] = (ok && (LOWER ? j < lane : (j > lane && j < rows))) ? drow[j] : 0.0;
+    const double dg = (!LOWER && ok) ? drow[lane] : 1.0;
+    const double rhs = ok ? x[gi] : 0.0;
+
+    // per row: block sums (16 products each, one lane) accumulated over the
+    // blocks with Neumaier's compensation
+    double acc = 0.0, cmp = 0.0;
+    double lv[16];
+    if (nk > 0) load_l(0, lv);
+    int i = 0;
+    while (i < nk) {
+        if (tid == 0) {
+            int sv = __hip_atomic_load(solved, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int spins = 0; sv <= i && spins < kSpinLimit; ++spins) {
+                __builtin_amdgcn_s_sleep(2);
+                sv = __hip_atomic_load(solved, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            // the solved blocks' values become visible to this workgroup
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            if (sv <= i) {
+                atomicOr(sync + 4, 1);
+                sv = nk;
+            }
+            sh_avail = sv < nk ? sv : nk;
+        }
+        __syncthreads();
+        const int avail = sh_avail;
+        for (; i < avail; ++i) {
+            double ln[16];
+            if (i + 1 < nk) load_l(i + 1, ln);
+            const int64_t c0 = kcol(i);
+            double bsum = 0.0;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) bsum += lv[e] * (c0 + e < n ? x[c0 + e] : 0.0);
+            const double tsum = acc + bsum;
+            cmp += fabs(acc) >= fabs(bsum) ? (acc - tsum) + bsum : (bsum - tsum) + acc;
+            acc = tsum;
+            if (i + 1 < nk) {
+#pragma unroll
+                for (int e = 0; e < 16; ++e) lv[e] = ln[e];
+            }
+        }
+        __syncthreads();                          // sh_avail is written again
+    }
+    acc += cmp;
+    acc += dpp_d<0xB1>(acc);                      // quad_perm [1,0,3,2]
+    acc += dpp_d<0x4E>(acc);                      // quad_perm [2,3,0,1]
+    if ((lane & 3) == 0) part[rr] = acc;
+    __syncthreads();
+    if (wave != 0) return;
+    double v = ok ? rhs - part[lane] : 0.0;
+    if constexpr (LOWER) {
+#pragma unroll
+        for (int j = 0; j < TB; ++j) {
+            if (j < rows) {
+                const double xj = bcast(v, j);
+                v = lane > j ? v - Tr[j] * xj : v;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int j = TB - 1; j >= 0; --j) {
+            if (j < rows) {
+                if (lane == j) v = v / dg;
+                const double xj = bcast(v, j);
+                v = lane < j ? v - Tr[j] * xj : v;
+            }
+        }
+    }
+    if (ok) x[gi] = v;
+    // the wavefront's stores complete before the count moves on
+    if (lane == 0) __hip_atomic_store(solved, t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+int trsv_one(int64_t n, const double *LU, int64_t lda, double *x, int32_t *sync, hipStream_t st)
+{
+    const int64_t nb = (n + TB - 1) / TB;
+    if (nb > INT32_MAX) return CFX_ENOTSUP;
+    hipLaunchKernelGGL(trsv_sync_reset_kernel, dim3(1), dim3(64), 0, st, sync);
+    CFX_HIP(hipGetLastError());
+    hipLaunchKernelGGL(trsv_sf_kernel<true>, dim3((unsigned)nb), dim3(256), 0, st, LU, lda, x, n, (int)nb, sync);
+    CFX_HIP(hipGetLastError());
+    hipLaunchKernelGGL(trsv_sf_kernel<false>, dim3((unsigned)nb), dim3(256), 0, st, LU, lda, x, n, (int)nb, sync);
+    CFX_HIP(hipGetLastError());
+    return CFX_OK;
+}
+
 template <int NRC>
 int trsv_impl(int64_t n, int nrhs, const double *LU, int64_t lda, double *X, int64_t ldx, hipStream_t st)
 {
@@ -377,21 +527,23 @@ int launch_copy_rows(int64_t n, int64_t nrhs, const double *T, int64_t ldt, doub
     return CFX_OK;
 }
 
-int launch_trsv(int64_t n, int64_t nrhs, const double *LU, int64_t lda, double *X, int64_t ldx, hipStream_t st)
+int launch_trsv(int64_t n, int64_t nrhs, const double *LU, int64_t lda, double *X, int64_t ldx, int32_t *sync,
+                hipStream_t st)
 {
     if (n <= 0 || nrhs <= 0) return CFX_OK;
+    if (nrhs == 1 && sync && (ldx == 1 || n == 1)) return trsv_one(n, LU, lda, X, sync, st);
     if (nrhs == 1) return trsv_impl<1>(n, 1, LU, lda, X, ldx, st);
     return trsv_impl<16>(n, (int)nrhs, LU, lda, X, ldx, st);
 }
 
 int launch_getrs(int64_t n, int64_t nrhs, const double *LU, int64_t lda, const int32_t *ipiv, double *B,
-                 int64_t ldb, int32_t *perm, double *tmp, hipStream_t st)
+                 int64_t ldb, int32_t *perm, double *tmp, int32_t *sync, hipStream_t st)
 {
     if (n == 0 || nrhs == 0) return CFX_OK;
     int rc;
     if ((rc = launch_perm(n, ipiv, perm, st))) return rc;
     if ((rc = launch_gather_rows(n, nrhs, B, ldb, perm, tmp, nrhs, st))) return rc;
-    if ((rc = launch_trsv(n, nrhs, LU, lda, tmp, nrhs, st))) return rc;
+    if ((rc = launch_trsv(n, nrhs, LU, lda, tmp, nrhs, sync, st))) return rc;
     return launch_copy_rows(n, nrhs, tmp, nrhs, B, ldb, st);
 }
 

@@ -143,7 +143,7 @@ def test_getrf_empty(cfx):
                                         (600, 1, 256, 2), (1, 1, 32, 4), (63, 2, 16, 2),
                                         (64, 1, 16, 2), (65, 17, 16, 2), (127, 16, 32, 3),
                                         (128, 1, 32, 3), (129, 64, 32, 3), (257, 3, 64, 2),
-                                        (2000, 1, 128, 8)])
+                                        (2000, 1, 128, 8), (4097, 1, 256, 4), (1, 1, 1, 1)])
 def test_getrs_matches_oracle(cfx, n, nrhs, v, L):
     say(f"getrs n={n} nrhs={nrhs}")
     A = G.normal_matrix(n, 3)
@@ -197,3 +197,27 @@ def test_getrf_bounded_schur_grid_bitwise_equal(cfx, n, wgs, chunk):
     assert int(info.cpu()[0]) == ref[2]
     assert np.array_equal(ipiv.cpu().numpy(), ref[1])
     assert np.array_equal(dA.cpu().numpy(), ref[0])
+
+
+def test_getrs_one_rhs_repeat_is_deterministic(cfx):
+    """The one-launch-per-triangle solve (blocks applying each other's
+    results as they appear) gives the same bits on every call, and a column
+    of a multi-column solve (a different code path) agrees to rounding."""
+    n, v, L = 3000, 128, 4
+    say(f"getrs determinism n={n}")
+    A = G.normal_matrix(n, 14)
+    dA = to_dev(A)
+    ipiv, info = cfx.getrf(dA, v=v, leaves=L)
+    B = G.rhs(n, 2, 15)
+    outs = []
+    for rep in range(3):
+        dB = to_dev(B[:, :1].copy())
+        cfx.getrs(dA, ipiv, dB)
+        torch.cuda.synchronize()
+        outs.append(dB.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    dB2 = to_dev(B)
+    cfx.getrs(dA, ipiv, dB2)
+    X2 = dB2.cpu().numpy()
+    np.testing.assert_allclose(outs[0][:, 0], X2[:, 0], rtol=0, atol=1e-10 * np.abs(X2).max())
+    assert O.eta(A, outs[0], B[:, :1]) <= 1e-14
