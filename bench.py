@@ -41,11 +41,12 @@ def lu_flops_of_columns(n, k0, k1):
     return float(np.sum(2.0 * r * r + r))
 
 
-def committed_traffic(n, v, L):
+def committed_traffic(n, v, L, key="traffic_bytes_per_launch"):
     """HBM bytes per launch of the FP64 Schur kernel from the committed
     rocprofv3 PMC summary of this workload (FETCH_SIZE and WRITE_SIZE runs,
-    calibrated by a plain copy), or None if there is none or the kernel's
-    source changed since the counters were taken."""
+    calibrated by a plain copy; `read_bytes_per_launch` alone when only the
+    FETCH_SIZE run exists), or None if there is none or the kernel's source
+    changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"schur_f64_kernel_traffic_n{n}_v{v}_L{L}.md")
     if not os.path.exists(path):
@@ -59,9 +60,9 @@ def committed_traffic(n, v, L):
     h = hashlib.sha256()
     for name in ("schur_f64.hip", "api.hip"):
         h.update(open(os.path.join(ROOT, "paper_2010_05975_amd", "csrc", name), "rb").read())
-    if fields.get("kernel_source_sha256_16") != h.hexdigest()[:16] or "traffic_bytes_per_launch" not in fields:
+    if fields.get("kernel_source_sha256_16") != h.hexdigest()[:16] or key not in fields:
         return None
-    return float(fields["traffic_bytes_per_launch"])
+    return float(fields[key])
 
 
 def cpu_baseline(A_host, n, v, L, panels):
@@ -310,6 +311,11 @@ def main():
     ap.add_argument("--v", type=int, default=256)
     ap.add_argument("--leaves", type=int, default=8)
     ap.add_argument("--lookahead", type=int, default=1)
+    ap.add_argument("--schur-wgs", type=int, default=None,
+                    help="grid bound of the overlapped Schur launches (cfx_set_overlap_tuning; 0 = none)")
+    ap.add_argument("--chunk", type=int, default=None, help="columns per overlapped Schur launch")
+    ap.add_argument("--one-stream", action="store_true",
+                    help="issue the lookahead schedule on one stream (for PMC counter runs)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-panels", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -363,6 +369,11 @@ def main():
     A = torch.empty_like(pristine)
     B = torch.empty_like(pb)
     work = cfx.workspace(n, v, L, "fp64", args.lookahead, dev)
+    if args.schur_wgs is not None or args.chunk is not None or args.one_stream:
+        w0, c0, _ = cfx.overlap_tuning()
+        cfx.set_overlap_tuning(w0 if args.schur_wgs is None else args.schur_wgs,
+                               c0 if args.chunk is None else args.chunk, 1 if args.one_stream else 0)
+        log(f"overlap tuning {cfx.overlap_tuning()}")
     ipiv = torch.empty(n, dtype=torch.int32, device=dev)
     info = torch.empty(1, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
@@ -446,7 +457,9 @@ def main():
         "roofline": {"bound": "mfma", "kernel": "schur_f64_kernel",
                      "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-                     "traffic": committed_traffic(n, v, L), "avg_launch_ms": round(schur_avg_ms, 4),
+                     "traffic": committed_traffic(n, v, L),
+                     "hbm_read_bytes_per_launch": committed_traffic(n, v, L, "read_bytes_per_launch"),
+                     "avg_launch_ms": round(schur_avg_ms, 4),
                      "avg_launch_flops": schur_avg_flops},
         "checks": {"eta": eta, "projected_residual": proj, "info": info_v},
     }

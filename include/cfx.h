@@ -90,10 +90,16 @@ int cfx_destroy(cfx_handle *h);
  *   schur_workgroups : 0 = one workgroup per tile (no bound; the default),
  *                      else >= 8.
  *   chunk_cols       : >= 1; default 512.
- * Get: host int32 pointers (either may be NULL).  Set returns -2 / -3 for
+ *   one_stream       : 1 issues the same launches, in the same order, on
+ *                      the caller's stream only (no overlap; for counter
+ *                      collection by profilers that serialize dispatches
+ *                      and cannot follow waits between streams); default 0.
+ * Get: host int32 pointers (any may be NULL).  Set returns -2 / -3 / -4 for
  * an invalid value. */
-int cfx_overlap_tuning(cfx_handle *h, int32_t *schur_workgroups, int32_t *chunk_cols);
-int cfx_set_overlap_tuning(cfx_handle *h, int32_t schur_workgroups, int32_t chunk_cols);
+int cfx_overlap_tuning(cfx_handle *h, int32_t *schur_workgroups, int32_t *chunk_cols,
+                       int32_t *one_stream);
+int cfx_set_overlap_tuning(cfx_handle *h, int32_t schur_workgroups, int32_t chunk_cols,
+                           int32_t one_stream);
 
 /* Static description of the library build (host memory, NUL-terminated). */
 const char *cfx_version(void);

@@ -113,8 +113,8 @@ def lib():
         L.cfx_batched_tune.argtypes = [vp, vp]
         L.cfx_batched_tuning.argtypes = [vp, vp]
         L.cfx_batched_set_tuning.argtypes = [vp, vp]
-        L.cfx_overlap_tuning.argtypes = [vp, vp, vp]
-        L.cfx_set_overlap_tuning.argtypes = [vp, i32, i32]
+        L.cfx_overlap_tuning.argtypes = [vp, vp, vp, vp]
+        L.cfx_set_overlap_tuning.argtypes = [vp, i32, i32, i32]
         L.cfx_serve_create.argtypes = [C.POINTER(ServeCfg), C.POINTER(vp)]
         L.cfx_serve_submit.argtypes = [vp, C.POINTER(Request), C.POINTER(C.c_uint64)]
         L.cfx_serve_poll.argtypes = [vp, C.c_uint64, C.POINTER(Result)]
@@ -359,16 +359,17 @@ def batched_set_tuning(vb, handle=None):
 
 
 def overlap_tuning(handle=None):
-    """(schur_workgroups, chunk_cols) of cfx_getrf's lookahead overlap."""
+    """(schur_workgroups, chunk_cols, one_stream) of cfx_getrf's lookahead overlap."""
     h = handle or default_handle()
-    w, c = C.c_int32(), C.c_int32()
-    _check("cfx_overlap_tuning", lib().cfx_overlap_tuning(h.h, C.byref(w), C.byref(c)))
-    return w.value, c.value
+    w, c, o = C.c_int32(), C.c_int32(), C.c_int32()
+    _check("cfx_overlap_tuning", lib().cfx_overlap_tuning(h.h, C.byref(w), C.byref(c), C.byref(o)))
+    return w.value, c.value, o.value
 
 
-def set_overlap_tuning(schur_workgroups, chunk_cols, handle=None):
+def set_overlap_tuning(schur_workgroups, chunk_cols, one_stream=0, handle=None):
     h = handle or default_handle()
-    _check("cfx_set_overlap_tuning", lib().cfx_set_overlap_tuning(h.h, int(schur_workgroups), int(chunk_cols)))
+    _check("cfx_set_overlap_tuning",
+           lib().cfx_set_overlap_tuning(h.h, int(schur_workgroups), int(chunk_cols), int(one_stream)))
 
 
 SOLVE, RESOLVE = 0, 1

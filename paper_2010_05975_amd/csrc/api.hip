@@ -61,6 +61,7 @@ struct cfx_handle {
     // (0: one workgroup per tile)
     int schur_wgs = 0;
     int64_t la_chunk = 512;         // columns per overlapped Schur launch
+    bool one_stream = false;        // lookahead launches on the caller's stream only
     // batched: panel width per size class (the tuner's table) and the graph
     // of the last batched call, replayed when the arguments repeat
     int32_t bvb[cfx::kBatchClasses] = {8, 16, 16, 32, 32};
@@ -363,7 +364,7 @@ int cfx_getrf(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *ipiv, i
     // tournament only reads those columns, so it runs on the side stream
     // while the main stream finishes the rest of the update; the next
     // interchanges wait for both.
-    hipStream_t side = h->side;
+    hipStream_t side = h->one_stream ? st : h->side;
     {
         const int vb0 = (int)(n < v ? n : v);
         hipEvent_t e = pf.begin(st);
@@ -658,21 +659,24 @@ int cfx_batched_tuning(cfx_handle *h, int32_t *vb)
     return CFX_OK;
 }
 
-int cfx_overlap_tuning(cfx_handle *h, int32_t *schur_workgroups, int32_t *chunk_cols)
+int cfx_overlap_tuning(cfx_handle *h, int32_t *schur_workgroups, int32_t *chunk_cols, int32_t *one_stream)
 {
     if (!h) return -1;
     if (schur_workgroups) *schur_workgroups = h->schur_wgs;
     if (chunk_cols) *chunk_cols = (int32_t)h->la_chunk;
+    if (one_stream) *one_stream = h->one_stream ? 1 : 0;
     return CFX_OK;
 }
 
-int cfx_set_overlap_tuning(cfx_handle *h, int32_t schur_workgroups, int32_t chunk_cols)
+int cfx_set_overlap_tuning(cfx_handle *h, int32_t schur_workgroups, int32_t chunk_cols, int32_t one_stream)
 {
     if (!h) return -1;
     if (schur_workgroups < 0 || (schur_workgroups > 0 && schur_workgroups < 8)) return -2;
     if (chunk_cols < 1) return -3;
+    if (one_stream != 0 && one_stream != 1) return -4;
     h->schur_wgs = schur_workgroups;
     h->la_chunk = chunk_cols;
+    h->one_stream = one_stream != 0;
     return CFX_OK;
 }
 
