@@ -41,7 +41,7 @@ def lu_flops_of_columns(n, k0, k1):
     return float(np.sum(2.0 * r * r + r))
 
 
-def committed_traffic(n, v, L, key="traffic_bytes_per_launch"):
+def committed_traffic(n, v, L, field="traffic_bytes_per_launch"):
     """HBM bytes per launch of the FP64 Schur kernel from the committed
     rocprofv3 PMC summary of this workload (FETCH_SIZE and WRITE_SIZE runs,
     calibrated by a plain copy; `read_bytes_per_launch` alone when only the
@@ -60,9 +60,9 @@ def committed_traffic(n, v, L, key="traffic_bytes_per_launch"):
     h = hashlib.sha256()
     for name in ("schur_f64.hip", "api.hip"):
         h.update(open(os.path.join(ROOT, "paper_2010_05975_amd", "csrc", name), "rb").read())
-    if fields.get("kernel_source_sha256_16") != h.hexdigest()[:16] or key not in fields:
+    if fields.get("kernel_source_sha256_16") != h.hexdigest()[:16] or field not in fields:
         return None
-    return float(fields[key])
+    return float(fields[field])
 
 
 def cpu_baseline(A_host, n, v, L, panels):
