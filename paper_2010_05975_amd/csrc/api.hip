@@ -382,10 +382,14 @@ int cfx_getrf(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *ipiv, i
         if ((rc = launch_laswp(A, lda, n, k, vb, ws, st))) return rc;
         pf.end(PH_LASWP, e, st);
         if (m > 0) {
-            e = pf.begin(st);
-            if ((rc = launch_trsm(A, lda, k, vb, m, st))) return rc;
-            pf.end(PH_TRSM, e, st);
             const int vbn = (int)(m < v ? m : v);          // next panel width
+            // FP64: L21 and the next panel's columns of U12 first (one
+            // launch), the rest of U12 after the next tournament has been
+            // started; the low-precision pack needs all of U12 at once
+            const int64_t n1 = prec == CFX_PREC_FP64 ? vbn : m;
+            e = pf.begin(st);
+            if ((rc = launch_trsm_first(A, lda, k, vb, m, n1, st))) return rc;
+            pf.end(PH_TRSM, e, st);
             double *L21 = panel + vb * lda, *U12 = panel + vb, *C = panel + vb * lda + vb;
             e = pf.begin(st);
             if (prec != CFX_PREC_FP64 && (rc = launch_pack_lp(prec, L21, U12, lda, m, vb, ws.scratch, st)))
@@ -403,6 +407,11 @@ int cfx_getrf(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *ipiv, i
             pf.end(PH_TSLU, e, ts);
             CFX_HIP(hipEventRecord(h->ev_tslu, ts));
             tslu_on_side = true;
+            if (n1 < m) {
+                e = pf.begin(us);
+                if ((rc = launch_trsm_rest(A, lda, k, vb, m, n1, us))) return rc;
+                pf.end(PH_TRSM, e, us);
+            }
             // the rest of the update, in column chunks: between two chunks
             // the dispatcher can start the tournament's launches queued on
             // the side stream instead of leaving them behind one huge grid

@@ -81,6 +81,12 @@ int launch_laswp(double *A, int64_t lda, int64_t n, int64_t k, int vb,
 // in place, for the trailing m rows / columns of panel k.
 int launch_trsm(double *A, int64_t lda, int64_t k, int vb, int64_t m,
                 hipStream_t st);
+// L21 and the first n1 columns of U12 in one launch; the other columns of
+// U12 (n1 .. m) separately.
+int launch_trsm_first(double *A, int64_t lda, int64_t k, int vb, int64_t m, int64_t n1,
+                      hipStream_t st);
+int launch_trsm_rest(double *A, int64_t lda, int64_t k, int vb, int64_t m, int64_t n1,
+                     hipStream_t st);
 
 // FactorizeA11: C[0:mr, 0:nc] -= L[0:mr, 0:K] * U[0:K, 0:nc]  (FP64 MFMA).
 // max_wgs > 0 bounds the grid (persistent workgroups walk the tiles)

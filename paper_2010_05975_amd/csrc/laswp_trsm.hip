@@ -91,16 +91,19 @@ __device__ __forceinline__ double uval(const double *P, int64_t lda, int r, int 
     else return r == c ? 1.0 : P[(int64_t)c * lda + r];
 }
 
+// One workgroup: rows rbase .. rbase+64 (below rend) of X.  LDS:
+//   Us  U[0 : c0+32, c0 : c0+32] of the current block (kMaxV x ULD)
+//   Sb  per wavefront: the block's rows (inputs, then the solution)
+//   Sg  per wavefront: X_{<b} U_{<b,b} of the block
 template <int MODE>
-__global__ __launch_bounds__(256) void trsm_kernel(double *A, int64_t lda, int64_t k, int vb, int64_t m)
+__device__ __forceinline__ void trsm_body(double *A, int64_t lda, int64_t k, int vb, int64_t rbase,
+                                          int64_t rend, double *Us, double (*Sb)[TSW][ULD],
+                                          double (*Sg)[TSW][ULD])
 {
-    __shared__ double Us[kMaxV * ULD];      // U[0 : c0+32, c0 : c0+32] of the block
-    __shared__ double Sb[4][TSW][ULD];      // per wavefront: the block's rows (inputs, then solution)
-    __shared__ double Sg[4][TSW][ULD];      // per wavefront: X_{<b} U_{<b,b} of the block
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lk = lane >> 4;
-    const int64_t row = (int64_t)blockIdx.x * TSR + wave * TSW + lr;   // this lane's row of X
-    const bool rok = row < m;
+    const int64_t row = rbase + wave * TSW + lr;   // this lane's row of X
+    const bool rok = row < rend;
     const double *P = A + k * lda + k;      // the panel's diagonal block
     auto xaddr = [&](int c) -> double * {
         if constexpr (MODE == 0) return A + (k + vb + row) * lda + k + c;
@@ -208,6 +211,31 @@ __global__ __launch_bounds__(256) void trsm_kernel(double *A, int64_t lda, int64
     });
 }
 
+// Rows i0 .. i1 of one solve.
+template <int MODE>
+__global__ __launch_bounds__(256) void trsm_kernel(double *A, int64_t lda, int64_t k, int vb, int64_t i0,
+                                                   int64_t i1)
+{
+    __shared__ double Us[kMaxV * ULD];
+    __shared__ double Sb[4][TSW][ULD];
+    __shared__ double Sg[4][TSW][ULD];
+    trsm_body<MODE>(A, lda, k, vb, i0 + (int64_t)blockIdx.x * TSR, i1, Us, Sb, Sg);
+}
+
+// Both solves in one launch: workgroups 0 .. g0 take the m rows of L21,
+// the others the first n1 columns of U12.
+__global__ __launch_bounds__(256) void trsm_pair_kernel(double *A, int64_t lda, int64_t k, int vb, int64_t m,
+                                                        int g0, int64_t n1)
+{
+    __shared__ double Us[kMaxV * ULD];
+    __shared__ double Sb[4][TSW][ULD];
+    __shared__ double Sg[4][TSW][ULD];
+    if ((int)blockIdx.x < g0)
+        trsm_body<0>(A, lda, k, vb, (int64_t)blockIdx.x * TSR, m, Us, Sb, Sg);
+    else
+        trsm_body<1>(A, lda, k, vb, (int64_t)(blockIdx.x - g0) * TSR, n1, Us, Sb, Sg);
+}
+
 __global__ void set_int_kernel(int32_t *p, int32_t v) { *p = v; }
 
 }  // namespace
@@ -222,15 +250,30 @@ int launch_laswp(double *A, int64_t lda, int64_t n, int64_t k, int vb, const Wor
     return CFX_OK;
 }
 
-int launch_trsm(double *A, int64_t lda, int64_t k, int vb, int64_t m, hipStream_t st)
+int launch_trsm_first(double *A, int64_t lda, int64_t k, int vb, int64_t m, int64_t n1, hipStream_t st)
 {
     if (m <= 0) return CFX_OK;
-    const unsigned g = (unsigned)((m + TSR - 1) / TSR);
-    hipLaunchKernelGGL(trsm_kernel<0>, dim3(g), dim3(256), 0, st, A, lda, k, vb, m);
-    CFX_HIP(hipGetLastError());
-    hipLaunchKernelGGL(trsm_kernel<1>, dim3(g), dim3(256), 0, st, A, lda, k, vb, m);
+    n1 = n1 < m ? n1 : m;
+    const int64_t g0 = (m + TSR - 1) / TSR, g1 = (n1 + TSR - 1) / TSR;
+    if (g0 + g1 > INT32_MAX) return CFX_ENOTSUP;
+    hipLaunchKernelGGL(trsm_pair_kernel, dim3((unsigned)(g0 + g1)), dim3(256), 0, st, A, lda, k, vb, m, (int)g0,
+                       n1);
     CFX_HIP(hipGetLastError());
     return CFX_OK;
+}
+
+int launch_trsm_rest(double *A, int64_t lda, int64_t k, int vb, int64_t m, int64_t n1, hipStream_t st)
+{
+    if (n1 >= m) return CFX_OK;
+    const unsigned g = (unsigned)((m - n1 + TSR - 1) / TSR);
+    hipLaunchKernelGGL(trsm_kernel<1>, dim3(g), dim3(256), 0, st, A, lda, k, vb, n1, m);
+    CFX_HIP(hipGetLastError());
+    return CFX_OK;
+}
+
+int launch_trsm(double *A, int64_t lda, int64_t k, int vb, int64_t m, hipStream_t st)
+{
+    return launch_trsm_first(A, lda, k, vb, m, m, st);
 }
 
 int launch_set_int(int32_t *p, int32_t value, hipStream_t st)
