@@ -141,6 +141,11 @@ __global__ __launch_bounds__(256, 2) void schur_f64_kernel(const double *__restr
     fetch(0);
     stash(0);
     __syncthreads();
+    // every load of the prologue (C into the accumulators included) lands
+    // here: otherwise the compiler may let some accumulator loads reach
+    // into the loop, and the waits it then places inside the loop body
+    // would also hold back every later chunk's prefetch
+    __builtin_amdgcn_s_waitcnt(0);
 #pragma unroll 1
     for (int kc = 0; kc < nk; ++kc) {
         const int buf = kc & 1;
