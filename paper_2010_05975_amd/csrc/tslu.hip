@@ -218,6 +218,10 @@ __device__ __forceinline__ int node_gid(const NodeArgs &p, const NodeRows &n, in
 template <int RPT, int NT>
 __global__ __launch_bounds__(NT) void tslu_panel_kernel(NodeArgs p)
 {
+    // The tournament is the critical path and runs beside the Schur update:
+    // its (latency-bound) waves go first when they share a SIMD with the
+    // update's matrix-core waves.
+    __builtin_amdgcn_s_setprio(3);
     constexpr int BW = BlockW<RPT>::value;
     constexpr int NW = NT / 64;
     using L = Lds<BW, NW>;
@@ -532,6 +536,7 @@ __global__ __launch_bounds__(NT) void tslu_panel_kernel(NodeArgs p)
 template <int BW>
 __global__ __launch_bounds__(256) void tslu_update_kernel(NodeArgs p, int tiles_r, int tiles_c)
 {
+    __builtin_amdgcn_s_setprio(3);      // critical path (see tslu_panel_kernel)
     __shared__ double Ut[BW][64 + 1];   // -U rows of the block at the tile's columns
     __shared__ double Rt[BW][BW + 8];
     __shared__ int sp[BW];
@@ -642,6 +647,7 @@ __global__ __launch_bounds__(256) void tslu_update_kernel(NodeArgs p, int tiles_
 // through LDS); also clears the node's selected-row mask.
 __global__ __launch_bounds__(256) void tslu_gather_kernel(NodeArgs p, int tiles_r, int tiles_c)
 {
+    __builtin_amdgcn_s_setprio(3);      // critical path (see tslu_panel_kernel)
     __shared__ double tile[64][65];
     const int per_node = tiles_r * tiles_c;
     const int node = blockIdx.x / per_node;
