@@ -48,10 +48,19 @@ __global__ __launch_bounds__(256) void perm_lds_kernel(const int32_t *ipiv, int 
     __shared__ int32_t p[kPermLds];
     for (int i = threadIdx.x; i < n; i += 256) p[i] = i;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int i = 0; i < n; ++i) {
-            const int r = ipiv[i];
-            if (r != i) { const int t = p[i]; p[i] = p[r]; p[r] = t; }
+    // the interchanges are sequential; the first wavefront fetches 64 of
+    // them per coalesced load and lane 0 applies them (broadcast by
+    // readlane), so that only LDS latency remains in the chain
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        for (int i0 = 0; i0 < n; i0 += 64) {
+            const int mine = i0 + lane < n ? ipiv[i0 + lane] : i0 + lane;
+            const int cnt = n - i0 < 64 ? n - i0 : 64;
+            for (int j = 0; j < cnt; ++j) {
+                const int r = __builtin_amdgcn_readlane(mine, j);
+                const int i = i0 + j;
+                if (lane == 0 && r != i) { const int t = p[i]; p[i] = p[r]; p[r] = t; }
+            }
         }
     }
     __syncthreads();

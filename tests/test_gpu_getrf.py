@@ -222,3 +222,52 @@ def test_getrs_one_rhs_repeat_is_deterministic(cfx):
     X2 = dB2.cpu().numpy()
     np.testing.assert_allclose(outs[0][:, 0], X2[:, 0], rtol=0, atol=1e-10 * np.abs(X2).max())
     assert O.eta(A, outs[0], B[:, :1]) <= 1e-14
+
+
+def test_getrf_full_size_first_panel_and_sampled_rows(cfx):
+    """The workload the bench times (N = 32768, v = 256, L = 8, lookahead,
+    A ~ N(0,1) seed 0): the first panel against the oracle (pivots bit for
+    bit, U00/U12 and, after the later interchanges, L00/L21), and sampled
+    rows of P A - L U, plus the structure of ipiv."""
+    n, v, L = 32768, 256, 8
+    say(f"full size n={n}: generating")
+    A = G.normal_matrix(n, 0)
+    dA = to_dev(A)
+    ipiv, info = cfx.getrf(dA, v=v, leaves=L, lookahead=1)
+    torch.cuda.synchronize()
+    piv = ipiv.cpu().numpy()
+    assert int(info.cpu()[0]) == 0
+    assert np.all(piv >= np.arange(n)) and np.all(piv < n)
+    say("  oracle, first panel")
+    ref = O.getrf(A, v, L, npanels=1)
+    assert ref.margins[0] > 1e-10
+    assert np.array_equal(piv[:v], ref.ipiv[:v])
+    top = dA[:v, :].cpu().numpy()
+    tol = 1e-9 * max(1.0, float(np.abs(ref.LU[:v, :]).max()))
+    np.testing.assert_allclose(np.triu(top[:, :v]), np.triu(ref.LU[:v, :v]), rtol=0, atol=tol)
+    np.testing.assert_allclose(top[:, v:], ref.LU[:v, v:], rtol=0, atol=tol)
+    # the later interchanges move whole rows, the first panel's L columns too
+    Lref = ref.LU[:, :v].copy()
+    for i in range(v, n):
+        p = piv[i]
+        if p != i:
+            Lref[[i, p]] = Lref[[p, i]]
+    left = dA[:, :v].cpu().numpy()
+    np.testing.assert_allclose(np.tril(left, -1), np.tril(Lref, -1), rtol=0, atol=tol)
+    del ref, Lref, left, top
+    say("  sampled rows of P A - L U")
+    perm = np.arange(n)
+    for i in range(n):
+        p = piv[i]
+        if p != i:
+            perm[i], perm[p] = perm[p], perm[i]
+    rows = np.random.default_rng(1).choice(n, 24, replace=False)
+    U = torch.triu(dA)
+    worst = 0.0
+    for r in rows:
+        lrow = dA[r, :].clone()
+        lrow[r + 1:] = 0.0
+        lrow[r] = 1.0
+        prod = (lrow[None, :] @ U)[0].cpu().numpy()
+        worst = max(worst, float(np.abs(prod - A[perm[r]]).max()))
+    assert worst <= 1e-12 * float(np.abs(A).max()) * np.sqrt(n), worst
