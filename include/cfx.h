@@ -156,7 +156,9 @@ int cfx_getrs(cfx_handle *h, int64_t n, int64_t nrhs, const double *LU,
  * the update x += d are FP64.  Refinement of a right-hand side stops when
  * its normwise backward error
  *     eta = |b - A x|_inf / (|A|_inf |x|_inf + |b|_inf)
- * is <= tol, or after max_outer refinement steps.
+ * is <= tol, after max_outer refinement steps, or when eta has not halved
+ * over the last two steps (stagnation: the factors are too inaccurate for
+ * this matrix; converged is then 0).
  *   lu            : factorisation options (precision CFX_PREC_BF16/FP16 for
  *                   the mixed-precision factorisation; FP64 also allowed).
  *   tol           : target eta (>= 0), e.g. 5e-15.
@@ -258,8 +260,8 @@ int cfx_batched_set_tuning(cfx_handle *h, const int32_t *vb);
  * Larger systems are factored by cfx_getrf with the configured precision
  * and solved with cfx_getrs semantics (FP64), refined by GMRES-IR
  * (BF16/FP16); when refinement from low-precision factors does not reach
- * ir.tol within ir.max_outer steps, the request refactors in FP64 and
- * solves again.  Every result reports its eta (as cfx_gesv_ir), and its
+ * ir.tol (it stops after ir.max_outer steps or on stagnation), the request
+ * refactors in FP64 and solves again.  Every result reports its eta (as cfx_gesv_ir), and its
  * arithmetic does not depend on what else runs: a request gives the same
  * bits alone and in a mix.
  * ------------------------------------------------------------------------ */

@@ -350,6 +350,7 @@ int ir_refine(const double *A, int64_t lda, const double *F, int64_t ldf, const 
     const int m = v.restart;
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), hh(2 * (m + 1) + 1);
     double anorm = -1.0, eta = 0.0;
+    double eta_hist[2] = {0.0, 0.0};   // eta one and two steps back
     int rc;
     res->outer = 0;
     res->inner = 0;
@@ -364,6 +365,10 @@ int ir_refine(const double *A, int64_t lda, const double *F, int64_t ldf, const 
             break;
         }
         if (outer >= p.max_outer || !std::isfinite(eta)) break;
+        // stagnation: eta did not halve over the last two steps
+        if (outer >= 2 && eta > 0.5 * eta_hist[1]) break;
+        eta_hist[1] = eta_hist[0];
+        eta_hist[0] = eta;
 
         // GMRES on M A d = M r from d = 0
         if ((rc = apply_m(c, v.r, v.z))) return rc;

@@ -143,6 +143,21 @@ def test_gesv_ir_householder(cfx, prec, cond):
     assert np.array_equal(dA.cpu().numpy(), A) and np.array_equal(db.cpu().numpy(), b)
 
 
+def test_gesv_ir_stagnation_stops_early(cfx):
+    """BF16 factors of a cond-1e12 system: eta cannot reach the target; the
+    refinement stops once eta fails to halve over two steps, long before
+    max_outer, and reports no convergence."""
+    n = 1024
+    say("gesv_ir stagnation")
+    A, b, xs = householder_case(n, 1e12, 9)
+    X, rep = cfx.gesv_ir(to_dev(A), to_dev(b), precision="bf16", v=128, leaves=4, tol=5e-15, max_outer=50,
+                         gmres_restart=20, gmres_tol=1e-6)
+    say(f"  {rep}")
+    assert rep["converged"] == 0
+    assert 2 <= rep["outer"] < 50
+    assert np.isfinite(rep["eta"]) and rep["eta"] > 5e-15
+
+
 def test_gesv_ir_fp64_factors(cfx):
     n = 1000
     say("gesv_ir fp64 factors")
