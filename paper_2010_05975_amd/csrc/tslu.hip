@@ -272,10 +272,16 @@ __global__ __launch_bounds__(NT) void tslu_panel_kernel(NodeArgs p)
         // into their pivot rows of the scratch block; only the root's
         // factored block is an output (other nodes hand on their selection
         // alone, and a selected row is never read again by its node)
+        // One column per thread, all its loads issued before its stores (the
+        // two arrays could alias, so a load-store loop would run one global
+        // round trip per element).
         const int pj0 = jb - BW, ncp = nsel - jb;
-        for (int e = tid; e < BW * ncp; e += NT) {
-            const int i = e / ncp, c = e - i * ncp;
-            Sn[(size_t)(jb + c) * rc + s.selp[pj0 + i]] = utg[(size_t)i * UTLD + c];
+        for (int c = tid; c < ncp; c += NT) {
+            double u[BW];
+#pragma unroll
+            for (int i = 0; i < BW; ++i) u[i] = utg[(size_t)i * UTLD + c];
+#pragma unroll
+            for (int i = 0; i < BW; ++i) Sn[(size_t)(jb + c) * rc + s.selp[pj0 + i]] = u[i];
         }
         __syncthreads();    // the copies above land before any row is loaded
     }
@@ -487,16 +493,29 @@ __global__ __launch_bounds__(NT) void tslu_panel_kernel(NodeArgs p)
     const int64_t k = p.row0;   // the panel's diagonal row
     if (p.piv_out)
         for (int j = tid; j < vb; j += NT) p.piv_out[j] = s.sel[j];
-    for (int e = tid; e < vb * vb; e += NT) {
-        const int j = e / vb, c = e - j * vb;
-        p.lu00[e] = Sn[(size_t)c * rc + s.selp[j]];
+    // the factored top block: one column per thread, loads in batches of
+    // 16 ahead of their stores (see the U-row copy)
+    for (int c = tid; c < vb; c += NT) {
+        const size_t col = (size_t)c * rc;
+        for (int j0 = 0; j0 < vb; j0 += 16) {
+            double t[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) t[q] = j0 + q < vb ? Sn[col + s.selp[j0 + q]] : 0.0;
+#pragma unroll
+            for (int q = 0; q < 16; ++q)
+                if (j0 + q < vb) p.lu00[(size_t)(j0 + q) * vb + c] = t[q];
+        }
     }
-    if (tid == 0 && p.info) {
-        for (int j = 0; j < vb; ++j)
-            if (Sn[(size_t)j * rc + s.selp[j]] == 0.0) {
-                if (*p.info == 0) *p.info = (int32_t)(k + j + 1);
-                break;
-            }
+    // first exactly zero pivot of the panel, all diagonal entries at once
+    if (p.info) {
+        int *zfirst = s.plan_tmp + 2 * kMaxV - 1;
+        if (tid == 0) *zfirst = INT_MAX;
+        __syncthreads();
+        for (int j = tid; j < vb; j += NT)
+            if (Sn[(size_t)j * rc + s.selp[j]] == 0.0) atomicMin(zfirst, j);
+        __syncthreads();
+        if (tid == 0 && *zfirst != INT_MAX && *p.info == 0) *p.info = (int32_t)(k + *zfirst + 1);
+        __syncthreads();    // zfirst is plan scratch below
     }
     if (tid == 0 && p.ipiv && p.plan) {
         // Sequential interchanges k+j <-> (current position of pivot j).
