@@ -494,15 +494,15 @@ __global__ __launch_bounds__(NT) void tslu_panel_kernel(NodeArgs p)
     if (p.piv_out)
         for (int j = tid; j < vb; j += NT) p.piv_out[j] = s.sel[j];
     // the factored top block: one column per thread, loads in batches of
-    // 16 ahead of their stores (see the U-row copy)
+    // 32 ahead of their stores (see the U-row copy)
     for (int c = tid; c < vb; c += NT) {
         const size_t col = (size_t)c * rc;
-        for (int j0 = 0; j0 < vb; j0 += 16) {
-            double t[16];
+        for (int j0 = 0; j0 < vb; j0 += 32) {
+            double t[32];
 #pragma unroll
-            for (int q = 0; q < 16; ++q) t[q] = j0 + q < vb ? Sn[col + s.selp[j0 + q]] : 0.0;
+            for (int q = 0; q < 32; ++q) t[q] = j0 + q < vb ? Sn[col + s.selp[j0 + q]] : 0.0;
 #pragma unroll
-            for (int q = 0; q < 16; ++q)
+            for (int q = 0; q < 32; ++q)
                 if (j0 + q < vb) p.lu00[(size_t)(j0 + q) * vb + c] = t[q];
         }
     }
@@ -517,32 +517,53 @@ __global__ __launch_bounds__(NT) void tslu_panel_kernel(NodeArgs p)
         if (tid == 0 && *zfirst != INT_MAX && *p.info == 0) *p.info = (int32_t)(k + *zfirst + 1);
         __syncthreads();    // zfirst is plan scratch below
     }
-    if (tid == 0 && p.ipiv && p.plan) {
-        // Sequential interchanges k+j <-> (current position of pivot j).
-        // loc[t]: current position of the row that started at k+t;
-        // at[q]:  which starting top row sits at top position k+q.
+    if (p.ipiv && p.plan) {
         int *loc = s.plan_tmp;
         int *at = loc + vb;
-        for (int t = 0; t < vb; ++t) { loc[t] = (int)(k + t); at[t] = t; }
-        for (int j = 0; j < vb; ++j) {
-            const int pj = s.sel[j];
-            const bool top = pj < k + vb;
-            const int pos = top ? loc[pj - k] : pj;
-            p.ipiv[k + j] = pos;
-            const int tcur = at[j];
-            if (pos != k + j) {
-                loc[tcur] = pos;
-                if (pos < k + vb) at[pos - k] = tcur;
+        if (tid == 0) {
+            // Sequential interchanges k+j <-> (current position of pivot j).
+            // loc[t]: current position of the row that started at k+t;
+            // at[q]:  which starting top row sits at top position k+q.
+            for (int t = 0; t < vb; ++t) { loc[t] = (int)(k + t); at[t] = t; }
+            for (int j = 0; j < vb; ++j) {
+                const int pj = s.sel[j];
+                const bool top = pj < k + vb;
+                const int pos = top ? loc[pj - k] : pj;
+                p.ipiv[k + j] = pos;
+                const int tcur = at[j];
+                if (pos != k + j) {
+                    loc[tcur] = pos;
+                    if (pos < k + vb) at[pos - k] = tcur;
+                }
+                if (top) loc[pj - k] = (int)(k + j);
             }
-            if (top) loc[pj - k] = (int)(k + j);
         }
-        int *dst = p.plan + 1, *src = p.plan + 1 + 2 * kMaxV;
-        int np = 0;
-        for (int j = 0; j < vb; ++j)
-            if (s.sel[j] != k + j) { dst[np] = (int)(k + j); src[np] = s.sel[j]; ++np; }
-        for (int t = 0; t < vb; ++t)
-            if (loc[t] >= k + vb) { dst[np] = loc[t]; src[np] = (int)(k + t); ++np; }
-        p.plan[0] = np;
+        __syncthreads();
+        // the row-move plan: selected rows into the top positions (in pivot
+        // order), then the displaced top rows (in starting order); one
+        // wavefront compacts each list with ballots
+        if (tid < 64) {
+            int *dst = p.plan + 1, *src = p.plan + 1 + 2 * kMaxV;
+            const unsigned long long below = (1ull << lane) - 1;
+            int np = 0;
+            for (int j0 = 0; j0 < vb; j0 += 64) {
+                const int j = j0 + lane;
+                const bool mv = j < vb && s.sel[j] != k + j;
+                const unsigned long long bal = __ballot(mv);
+                const int at_ = np + __popcll(bal & below);
+                if (mv) { dst[at_] = (int)(k + j); src[at_] = s.sel[j]; }
+                np += __popcll(bal);
+            }
+            for (int t0 = 0; t0 < vb; t0 += 64) {
+                const int t = t0 + lane;
+                const bool mv = t < vb && loc[t] >= k + vb;
+                const unsigned long long bal = __ballot(mv);
+                const int at_ = np + __popcll(bal & below);
+                if (mv) { dst[at_] = loc[t]; src[at_] = (int)(k + t); }
+                np += __popcll(bal);
+            }
+            if (lane == 0) p.plan[0] = np;
+        }
     }
 }
 
