@@ -141,6 +141,22 @@ __global__ __launch_bounds__(256, 2) void schur_lp_kernel(const T *__restrict__ 
         bok[b] = !EDGE || gj < nc;
         bp[b] = reinterpret_cast<const v8 *>(Ut_ + (bok[b] ? gj : 0) * Kp + 8 * lk);
     }
+    // the C tile is read first: the kernel is bound by these reads and
+    // writes, and their latency then overlaps the operand loads and the
+    // matrix-core work (f32 16x16 accumulator layout: lane l holds rows
+    // 4*(l/16) + q of column l%16)
+    // (whole tiles only; an edge tile reads C at the end, which keeps its
+    // guarded addressing within the register budget)
+    double cv[4][4][4];
+    if constexpr (!EDGE) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    cv[a][b][q] = C[(i0 + wm + a * 16 + 4 * lk + q) * ldc + j0 + wn + b * 16 + lr];
+    }
     f4 acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
@@ -158,7 +174,6 @@ __global__ __launch_bounds__(256, 2) void schur_lp_kernel(const T *__restrict__ 
 #pragma unroll
             for (int b = 0; b < 4; ++b) acc[a][b] = Lp<T>::mfma(af[a], bf[b], acc[a][b]);
     }
-    // f32 16x16 accumulator: lane l holds rows 4*(l/16) + q of column l%16
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -167,7 +182,9 @@ __global__ __launch_bounds__(256, 2) void schur_lp_kernel(const T *__restrict__ 
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int64_t gi = i0 + wm + a * 16 + 4 * lk + q;
-                if (!EDGE || (gi < mr && gj < nc)) {
+                if constexpr (!EDGE) {
+                    C[gi * ldc + gj] = cv[a][b][q] - (double)acc[a][b][q];
+                } else if (gi < mr && gj < nc) {
                     double *c = C + gi * ldc + gj;
                     *c = *c - (double)acc[a][b][q];
                 }
