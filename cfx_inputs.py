@@ -64,6 +64,31 @@ class HouseholderSpec:
     s: np.ndarray   # (n,) singular values, s_0 = 1 down to s_{n-1} = 1/cond
 
 
+def ipiv_pattern(kind: str, n: int, seed: int) -> np.ndarray:
+    """int32[n] LAPACK-style interchange vectors (row i with row ipiv[i]):
+    "chain"   ipiv[i] = i + 1 (every interchange shares a row with the next);
+    "near"    ipiv[i] in [i, i + 3);
+    "uniform" ipiv[i] uniform in [i, n);
+    "invalid" as "uniform", with every 7th entry replaced by one outside
+              [i, n) (i - 1, n, -5 or 2^31 - 1 in turn)."""
+    g = rng(seed)
+    i = np.arange(n, dtype=np.int64)
+    if kind == "chain":
+        r = i + 1
+    elif kind == "near":
+        r = i + g.integers(0, 3, n)
+    elif kind in ("uniform", "invalid"):
+        r = i + np.floor(g.random(n) * (n - i)).astype(np.int64)
+    else:
+        raise ValueError(kind)
+    r = np.minimum(r, n - 1)
+    if kind == "invalid":
+        bad = np.array([-1, n, -5, 2**31 - 1], dtype=np.int64)
+        k = np.arange(0, n, 7)
+        r[k] = np.where(bad[k % 4] == -1, k - 1, bad[k % 4])
+    return r.astype(np.int32)
+
+
 def householder_spec(n: int, cond: float, seed: int, nrefl: int = 8) -> HouseholderSpec:
     g = rng(seed)
     w1 = g.standard_normal(size=(nrefl, n))

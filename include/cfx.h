@@ -141,6 +141,8 @@ int cfx_tslu(cfx_handle *h, int64_t rows, int64_t vb, const double *W,
  * ipiv to B in order, forward substitution with unit L, back substitution
  * with U.
  *   LU   : device, n x n factors, stride lda.
+ *   ipiv : device int32[n] as written by cfx_getrf (i <= ipiv[i] < n); an
+ *          entry outside [i, n) is taken as no interchange.
  *   B    : device, n x nrhs row-major, stride ldb >= nrhs; overwritten by X.
  * Asynchronous on `stream`. */
 int cfx_getrs(cfx_handle *h, int64_t n, int64_t nrhs, const double *LU,

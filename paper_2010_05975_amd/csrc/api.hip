@@ -207,7 +207,7 @@ static int schur_update(int precision, const Workspace &ws, const double *L21, c
 {
     if (precision == CFX_PREC_FP64)
         return launch_schur_f64(L21, lda, U12 + col0, lda, C + col0, lda, m, ncols, vb, max_wgs, st);
-    return launch_schur_lp(precision, ws.scratch, m, vb, col0, ncols, C, lda, st);
+    return launch_schur_lp(precision, ws.scratch, m, vb, col0, ncols, C, lda, max_wgs, st);
 }
 
 }  // namespace cfx

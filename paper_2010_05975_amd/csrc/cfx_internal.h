@@ -103,7 +103,7 @@ size_t lp_pack_bytes(int64_t m, int K);
 int launch_pack_lp(int precision, const double *L21, const double *U12, int64_t lda,
                    int64_t m, int K, void *buf, hipStream_t st);
 int launch_schur_lp(int precision, const void *buf, int64_t m, int K, int64_t col0,
-                    int64_t ncols, double *C, int64_t ldc, hipStream_t st);
+                    int64_t ncols, double *C, int64_t ldc, int max_wgs, hipStream_t st);
 
 int launch_set_int(int32_t *p, int32_t value, hipStream_t st);
 

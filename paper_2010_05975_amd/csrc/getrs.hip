@@ -1,8 +1,9 @@
 // Solve A X = B from the factors A = P L U (the problem statement of Sec. 2.2
 // applied to right-hand sides; LAPACK getrs conventions).
 //
-// 1. perm: the ipiv interchanges composed into one gather (one workgroup,
-//    the index array in LDS).
+// 1. perm: the ipiv interchanges composed into one gather (one wavefront,
+//    the index array in LDS; runs of interchanges on disjoint rows are
+//    applied together).
 // 2. X = B[perm] into a contiguous temporary.
 // 3. Forward substitution with unit L, then back substitution with U,
 //    blocked by SB = 128 rows.  One launch per block: every workgroup
@@ -21,6 +22,7 @@ namespace cfx {
 namespace {
 
 constexpr int kPermLds = 36864;   // n up to this uses the LDS permutation (144 KiB)
+static_assert(kPermLds <= 0x10000, "row indices and the tags of perm_lds_kernel share a 32-bit entry");
 constexpr int SB = 128;           // block of the substitution
 constexpr int HB = 64;            // half block solved by one wavefront's lanes
 constexpr int RPW = 64;           // rows per updating workgroup
@@ -43,28 +45,69 @@ __device__ __forceinline__ double bcast(double x, int l)
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-__global__ __launch_bounds__(256) void perm_lds_kernel(const int32_t *ipiv, int n, int32_t *perm)
+// One wavefront; lane l holds interchange i0 + l of the current window of
+// 64.  A run of consecutive interchanges is tried at once: each of its
+// lanes tags the two rows of its interchange (an LDS add of 1 << 16; the
+// entries themselves are < 2^16).  No row tagged twice means that the run
+// touches disjoint rows, so its interchanges commute and every lane applies
+// its own; the next run is then twice as long.  Otherwise the tags are
+// removed and the run is halved; a run of at most 2 is applied in order by
+// lane 0.  An entry outside [i, n) is no interchange.
+__global__ __launch_bounds__(64) void perm_lds_kernel(const int32_t *ipiv, int n, int32_t *perm)
 {
     __shared__ int32_t p[kPermLds];
-    for (int i = threadIdx.x; i < n; i += 256) p[i] = i;
+    const int lane = threadIdx.x;
+    for (int i = lane; i < n; i += 64) p[i] = i;
     __syncthreads();
-    // the interchanges are sequential; the first wavefront fetches 64 of
-    // them per coalesced load and lane 0 applies them (broadcast by
-    // readlane), so that only LDS latency remains in the chain
-    if (threadIdx.x < 64) {
-        const int lane = threadIdx.x;
-        for (int i0 = 0; i0 < n; i0 += 64) {
-            const int mine = i0 + lane < n ? ipiv[i0 + lane] : i0 + lane;
-            const int cnt = n - i0 < 64 ? n - i0 : 64;
-            for (int j = 0; j < cnt; ++j) {
-                const int r = __builtin_amdgcn_readlane(mine, j);
-                const int i = i0 + j;
-                if (lane == 0 && r != i) { const int t = p[i]; p[i] = p[r]; p[r] = t; }
+    int nxt = lane < n ? ipiv[lane] : 0;
+    int run = 64;
+    for (int i0 = 0; i0 < n; i0 += 64) {
+        const int cnt = n - i0 < 64 ? n - i0 : 64;
+        const int i = i0 + lane;
+        const int r = nxt;
+        if (i0 + 64 + lane < n) nxt = ipiv[i0 + 64 + lane];    // the next window, ahead of its use
+        const bool valid = lane < cnt && r > i && r < n;
+        int b = 0;      // interchanges [i0, i0 + b) are applied (uniform)
+        while (b < cnt) {
+            const int e = b + run < cnt ? b + run : cnt;
+            const bool act = valid && lane >= b && lane < e;
+            int oi = 0, orr = 0;
+            if (act) {
+                oi = atomicAdd(&p[i], 0x10000);
+                orr = atomicAdd(&p[r], 0x10000);
+            }
+            const bool clash = act && (((oi | orr) >> 16) != 0);
+            if (__ballot(clash) == 0) {
+                if (act) {      // untagged old entries: the swap, tags dropped
+                    p[i] = orr;
+                    p[r] = oi;
+                }
+                b = e;
+                run = run < 32 ? 2 * run : 64;
+            } else {
+                if (act) {
+                    atomicSub(&p[i], 0x10000);
+                    atomicSub(&p[r], 0x10000);
+                }
+                if (e - b <= 2) {
+                    for (int j = b; j < e; ++j) {
+                        const int rj = __builtin_amdgcn_readlane(r, j);
+                        const int ij = i0 + j;
+                        if (lane == 0 && rj > ij && rj < n) {
+                            const int t = p[ij];
+                            p[ij] = p[rj];
+                            p[rj] = t;
+                        }
+                    }
+                    b = e;
+                } else {
+                    run = (e - b) / 2;
+                }
             }
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += 256) perm[i] = p[i];
+    for (int i = lane; i < n; i += 64) perm[i] = p[i];
 }
 
 __global__ void perm_global_kernel(const int32_t *ipiv, int64_t n, int32_t *perm)
@@ -73,7 +116,7 @@ __global__ void perm_global_kernel(const int32_t *ipiv, int64_t n, int32_t *perm
     for (int64_t i = 0; i < n; ++i) perm[i] = (int32_t)i;
     for (int64_t i = 0; i < n; ++i) {
         const int64_t r = ipiv[i];
-        if (r != i) { const int32_t t = perm[i]; perm[i] = perm[r]; perm[r] = t; }
+        if (r > i && r < n) { const int32_t t = perm[i]; perm[i] = perm[r]; perm[r] = t; }
     }
 }
 
@@ -507,7 +550,7 @@ int launch_perm(int64_t n, const int32_t *ipiv, int32_t *perm, hipStream_t st)
 {
     if (n <= 0) return CFX_OK;
     if (n <= kPermLds)
-        hipLaunchKernelGGL(perm_lds_kernel, dim3(1), dim3(256), 0, st, ipiv, (int)n, perm);
+        hipLaunchKernelGGL(perm_lds_kernel, dim3(1), dim3(64), 0, st, ipiv, (int)n, perm);
     else
         hipLaunchKernelGGL(perm_global_kernel, dim3(1), dim3(64), 0, st, ipiv, n, perm);
     CFX_HIP(hipGetLastError());

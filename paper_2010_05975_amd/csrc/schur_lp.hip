@@ -43,15 +43,14 @@ template <> struct Lp<_Float16> {
     }
 };
 
-__device__ __forceinline__ void tile_of(int bid, int nb, int tm, int tn, int &ti, int &tj)
+// Position `pos` of the regrouped order -> tile (ti, tj): grouped row-major,
+// GROUP_M tile rows at a time.
+__device__ __forceinline__ void tile_at(int pos, int tm, int tn, int &ti, int &tj)
 {
-    const int per = nb / NXCD;
-    int t = bid;
-    if (bid < per * NXCD) t = (bid % NXCD) * per + bid / NXCD;
-    const int group = t / (GROUP_M * tn);
+    const int group = pos / (GROUP_M * tn);
     const int first = group * GROUP_M;
     const int gsz = (tm - first) < GROUP_M ? (tm - first) : GROUP_M;
-    const int r = t - group * GROUP_M * tn;
+    const int r = pos - group * GROUP_M * tn;
     ti = first + r % gsz;
     tj = r / gsz;
 }
@@ -120,8 +119,18 @@ __global__ __launch_bounds__(256, 2) void schur_lp_kernel(const T *__restrict__ 
                                                           int64_t mr, int64_t nc, int tm, int tn)
 {
     typedef typename Lp<T>::v8 v8;
+    // XCD-aware persistent schedule (as the FP64 update): workgroup b runs
+    // on XCD b % 8, which owns a contiguous range of tile positions; with
+    // one workgroup per tile each takes exactly one position
+    const int nb = tm * tn;
+    const int xcd = blockIdx.x % NXCD, slot = blockIdx.x / NXCD;
+    const int nsl = ((int)gridDim.x - xcd + NXCD - 1) / NXCD;
+    const int per = nb / NXCD;
+    const int cnt = per + (xcd < nb - per * NXCD ? 1 : 0);
+#pragma unroll 1
+    for (int it = slot; it < cnt; it += nsl) {
     int ti, tj;
-    tile_of(blockIdx.x, gridDim.x, tm, tn, ti, tj);
+    tile_at(it < per ? xcd * per + it : NXCD * per + xcd, tm, tn, ti, tj);
     const int64_t i0 = (int64_t)ti * BM, j0 = (int64_t)tj * BN;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
@@ -190,6 +199,7 @@ __global__ __launch_bounds__(256, 2) void schur_lp_kernel(const T *__restrict__ 
                 }
             }
         }
+    }   // tiles of this workgroup
 }
 
 template <typename T>
@@ -211,14 +221,16 @@ int pack_impl(const double *L21, const double *U12, int64_t lda, int64_t m, int 
 
 template <typename T>
 int schur_impl(const void *buf, int64_t m, int K, int64_t col0, int64_t ncols, double *C, int64_t ldc,
-               hipStream_t st)
+               int max_wgs, hipStream_t st)
 {
     const int Kp = (K + KB - 1) / KB * KB;
     const T *Lp_ = static_cast<const T *>(buf);
     const T *Ut_ = Lp_ + (size_t)m * Kp + (size_t)col0 * Kp;
     if (m <= 0 || ncols <= 0) return CFX_OK;
     const int tm = (int)((m + BM - 1) / BM), tn = (int)((ncols + BN - 1) / BN);
-    const int64_t nb = (int64_t)tm * tn;
+    if ((int64_t)tm * tn > INT32_MAX) return CFX_ENOTSUP;
+    int64_t nb = (int64_t)tm * tn;
+    if (max_wgs > 0 && max_wgs < nb) nb = max_wgs < NXCD ? NXCD : max_wgs;
     const bool full = (m % BM == 0) && (ncols % BN == 0);
     if (full)
         hipLaunchKernelGGL((schur_lp_kernel<T, false>), dim3((unsigned)nb), dim3(256), 0, st, Lp_, Ut_, Kp,
@@ -247,10 +259,10 @@ int launch_pack_lp(int precision, const double *L21, const double *U12, int64_t 
 }
 
 int launch_schur_lp(int precision, const void *buf, int64_t m, int K, int64_t col0, int64_t ncols, double *C,
-                    int64_t ldc, hipStream_t st)
+                    int64_t ldc, int max_wgs, hipStream_t st)
 {
-    if (precision == CFX_PREC_BF16) return schur_impl<__bf16>(buf, m, K, col0, ncols, C, ldc, st);
-    return schur_impl<_Float16>(buf, m, K, col0, ncols, C, ldc, st);
+    if (precision == CFX_PREC_BF16) return schur_impl<__bf16>(buf, m, K, col0, ncols, C, ldc, max_wgs, st);
+    return schur_impl<_Float16>(buf, m, K, col0, ncols, C, ldc, max_wgs, st);
 }
 
 }  // namespace cfx

@@ -162,6 +162,29 @@ def test_getrs_matches_oracle(cfx, n, nrhs, v, L):
     np.testing.assert_allclose(X, Xref, rtol=1e-8, atol=1e-8 * np.abs(Xref).max())
 
 
+@pytest.mark.parametrize("kind", ["chain", "near", "uniform", "invalid"])
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 1000, 36864, 36865])
+def test_getrs_interchanges_exact(cfx, kind, n):
+    """With unit factors (LU = I) getrs returns P B, so the composed
+    interchanges are compared exactly with the sequential definition, for
+    interchange runs that all share rows ("chain"), often do ("near") or
+    rarely do ("uniform"); entries outside [i, n) are no interchange.
+    n = 36864 is the largest order of the LDS index array, 36865 the first
+    beyond it."""
+    nrhs = 1 if kind in ("chain", "uniform") else 2
+    say(f"getrs interchanges {kind} n={n} nrhs={nrhs}")
+    ipiv = G.ipiv_pattern(kind, n, 21)
+    i = np.arange(n)
+    perm = O.ipiv_to_perm(np.where((ipiv >= i) & (ipiv < n), ipiv, i))
+    B = G.rhs(n, nrhs, 22)
+    dLU = torch.eye(n, dtype=torch.float64, device="cuda")
+    dB = to_dev(B)
+    cfx.getrs(dLU, torch.from_numpy(ipiv).cuda(), dB)
+    X = dB.cpu().numpy()
+    del dLU
+    assert np.array_equal(X, B[perm])
+
+
 @pytest.mark.parametrize("n,v,L", [(1500, 128, 4), (3000, 256, 8)])
 def test_getrf_lookahead_bitwise_equal(cfx, n, v, L):
     """Lookahead only reorders independent launches: the factors are

@@ -120,6 +120,29 @@ def householder_case(n, cond, seed):
     return A, b, xs
 
 
+@pytest.mark.parametrize("prec,n,wgs,chunk", [("bf16", 2100, 8, 64), ("fp16", 2100, 12, 300),
+                                              ("bf16", 2048, 24, 4096), ("fp16", 2048, 8, 256)])
+def test_lowp_bounded_schur_grid_bitwise_equal(cfx, prec, n, wgs, chunk):
+    """A bounded, persistent grid for the low-precision Schur launches
+    (few workgroups walking many tiles; ragged or whole tiles) changes
+    scheduling only: the factors are bitwise those of the unbounded grid."""
+    v, L = 128, 4
+    say(f"lowp bounded schur grid {prec} wgs={wgs} chunk={chunk} n={n}")
+    A = G.normal_matrix(n, 13)
+    ref = run_getrf(cfx, A, v, L, prec, 1)
+    h = cfx.Handle()
+    try:
+        cfx.set_overlap_tuning(wgs, chunk, 0, handle=h)
+        dA = to_dev(A)
+        ipiv, info = cfx.getrf(dA, v=v, leaves=L, precision=prec, lookahead=1, handle=h)
+        torch.cuda.synchronize()
+    finally:
+        h.close()
+    assert int(info.cpu()[0]) == ref[2]
+    assert np.array_equal(ipiv.cpu().numpy(), ref[1])
+    assert np.array_equal(dA.cpu().numpy(), ref[0])
+
+
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("cond", [1e2, 1e6])
 def test_gesv_ir_householder(cfx, prec, cond):
