@@ -87,8 +87,10 @@ int cfx_destroy(cfx_handle *h);
  * is issued in launches of `chunk_cols` columns whose grid is bounded by
  * `schur_workgroups` workgroups that walk the tiles persistently, so that
  * the tournament's launches find free compute units at once.
- *   schur_workgroups : 0 = one workgroup per tile (no bound; the default),
- *                      else >= 8.
+ *   schur_workgroups : -1 = by precision (the default): no bound for FP64,
+ *                      384 for BF16/FP16 (their update is bound by HBM and
+ *                      loses little to a bound); 0 = one workgroup per tile
+ *                      (no bound); else >= 8.
  *   chunk_cols       : >= 1; default 512.
  *   one_stream       : 1 issues the same launches, in the same order, on
  *                      the caller's stream only (no overlap; for counter

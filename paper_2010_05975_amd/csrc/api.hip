@@ -47,6 +47,10 @@ struct Profiler {
 };
 }  // namespace cfx
 
+namespace cfx {
+constexpr int kLpSchurWgs = 384;
+}  // namespace cfx
+
 struct cfx_handle {
     int device = 0;
     hipStream_t side = nullptr;     // lookahead stream (default priority)
@@ -58,8 +62,10 @@ struct cfx_handle {
     cfx::Profiler prof;
     int cu_count = 256;
     // grid bound of the Schur updates that overlap the next tournament
-    // (0: one workgroup per tile)
-    int schur_wgs = 0;
+    // (0: one workgroup per tile; -1: by precision, none for FP64 and
+    // kLpSchurWgs for the HBM-bound low-precision update, which then leaves
+    // compute units to the tournament at little cost of its own)
+    int schur_wgs = -1;
     int64_t la_chunk = 512;         // columns per overlapped Schur launch
     bool one_stream = false;        // lookahead launches on the caller's stream only
     // batched: panel width per size class (the tuner's table) and the graph
@@ -416,10 +422,11 @@ int cfx_getrf(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *ipiv, i
             // the dispatcher can start the tournament's launches queued on
             // the side stream instead of leaving them behind one huge grid
             const int64_t chunk = h->la_chunk;
+            const int wgs = h->schur_wgs >= 0 ? h->schur_wgs : (prec == CFX_PREC_FP64 ? 0 : cfx::kLpSchurWgs);
             for (int64_t c0 = vbn; c0 < m; c0 += chunk) {
                 const int64_t cw = (m - c0) < chunk ? (m - c0) : chunk;
                 e = pf.begin(us);
-                if ((rc = schur_update(prec, ws, L21, U12, C, lda, m, c0, cw, vb, h->schur_wgs, us))) return rc;
+                if ((rc = schur_update(prec, ws, L21, U12, C, lda, m, c0, cw, vb, wgs, us))) return rc;
                 pf.end(PH_SCHUR, e, us, 2.0 * (double)m * (double)cw * vb);
             }
 
@@ -680,7 +687,7 @@ int cfx_overlap_tuning(cfx_handle *h, int32_t *schur_workgroups, int32_t *chunk_
 int cfx_set_overlap_tuning(cfx_handle *h, int32_t schur_workgroups, int32_t chunk_cols, int32_t one_stream)
 {
     if (!h) return -1;
-    if (schur_workgroups < 0 || (schur_workgroups > 0 && schur_workgroups < 8)) return -2;
+    if (schur_workgroups < -1 || (schur_workgroups > 0 && schur_workgroups < 8)) return -2;
     if (chunk_cols < 1) return -3;
     if (one_stream != 0 && one_stream != 1) return -4;
     h->schur_wgs = schur_workgroups;

@@ -210,6 +210,7 @@ def test_getrf_bounded_schur_grid_bitwise_equal(cfx, n, wgs, chunk):
     ref = run_getrf(cfx, A, v, L, 0)
     h = cfx.Handle()
     try:
+        assert cfx.overlap_tuning(handle=h) == (-1, 512, 0)     # the defaults
         one = 1 if wgs == 12 else 0         # one case on the caller's stream only
         cfx.set_overlap_tuning(wgs, chunk, one, handle=h)
         assert cfx.overlap_tuning(handle=h) == (wgs, chunk, one)
