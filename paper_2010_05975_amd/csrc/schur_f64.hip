@@ -9,7 +9,10 @@
 // feeds the matrix cores.  Both operand tiles are stored k-major in LDS so
 // that the 16 lanes of an MFMA operand row read 16 consecutive doubles.
 // C is read once into the accumulators before the reduction (the L tile is
-// staged negated, so the matrix cores accumulate C - L U) and written once.
+// staged negated, so the matrix cores accumulate C - L U) and written once,
+// both non-temporal: C streams through without evicting the operand strips
+// from L2, nor the data of the tournament kernels that run beside the
+// update.
 //
 // Tiles are mapped XCD-aware: consecutive workgroup ids land on different
 // XCDs (each with its own L2), so ids are regrouped to give each XCD a
@@ -133,7 +136,7 @@ __global__ __launch_bounds__(256, 2) void schur_f64_kernel(const double *__restr
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int64_t gi = i0 + wm + a * 16 + lk + 4 * q;
-                acc[a][b][q] = (!EDGE || (gi < mr && gj < nc)) ? C[gi * ldc + gj] : 0.0;
+                acc[a][b][q] = (!EDGE || (gi < mr && gj < nc)) ? __builtin_nontemporal_load(&C[gi * ldc + gj]) : 0.0;
             }
         }
 
@@ -179,7 +182,7 @@ __global__ __launch_bounds__(256, 2) void schur_f64_kernel(const double *__restr
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int64_t gi = i0 + wm + a * 16 + lk + 4 * q;
-                if (!EDGE || (gi < mr && gj < nc)) C[gi * ldc + gj] = acc[a][b][q];
+                if (!EDGE || (gi < mr && gj < nc)) __builtin_nontemporal_store(acc[a][b][q], &C[gi * ldc + gj]);
             }
         }
     }   // tiles of this workgroup (the last K chunk ended with a barrier, so

@@ -155,7 +155,8 @@ __global__ __launch_bounds__(256, 2) void schur_lp_kernel(const T *__restrict__ 
     // matrix-core work (f32 16x16 accumulator layout: lane l holds rows
     // 4*(l/16) + q of column l%16)
     // (whole tiles only; an edge tile reads C at the end, which keeps its
-    // guarded addressing within the register budget)
+    // guarded addressing within the register budget).  Whole tiles move C
+    // non-temporally, so that it does not evict the operands from L2.
     double cv[4][4][4];
     if constexpr (!EDGE) {
 #pragma unroll
@@ -164,7 +165,7 @@ __global__ __launch_bounds__(256, 2) void schur_lp_kernel(const T *__restrict__ 
             for (int b = 0; b < 4; ++b)
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    cv[a][b][q] = C[(i0 + wm + a * 16 + 4 * lk + q) * ldc + j0 + wn + b * 16 + lr];
+                    cv[a][b][q] = __builtin_nontemporal_load(&C[(i0 + wm + a * 16 + 4 * lk + q) * ldc + j0 + wn + b * 16 + lr]);
     }
     f4 acc[4][4];
 #pragma unroll
@@ -192,7 +193,7 @@ __global__ __launch_bounds__(256, 2) void schur_lp_kernel(const T *__restrict__ 
             for (int q = 0; q < 4; ++q) {
                 const int64_t gi = i0 + wm + a * 16 + 4 * lk + q;
                 if constexpr (!EDGE) {
-                    C[gi * ldc + gj] = cv[a][b][q] - (double)acc[a][b][q];
+                    __builtin_nontemporal_store(cv[a][b][q] - (double)acc[a][b][q], &C[gi * ldc + gj]);
                 } else if (gi < mr && gj < nc) {
                     double *c = C + gi * ldc + gj;
                     *c = *c - (double)acc[a][b][q];
