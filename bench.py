@@ -312,7 +312,8 @@ def main():
     ap.add_argument("--leaves", type=int, default=8)
     ap.add_argument("--lookahead", type=int, default=1)
     ap.add_argument("--schur-wgs", type=int, default=None,
-                    help="grid bound of the overlapped Schur launches (cfx_set_overlap_tuning; 0 = none)")
+                    help="grid bound of the overlapped Schur launches (cfx_set_overlap_tuning; "
+                         "-1 = by precision, the default; 0 = none)")
     ap.add_argument("--chunk", type=int, default=None, help="columns per overlapped Schur launch")
     ap.add_argument("--one-stream", action="store_true",
                     help="issue the lookahead schedule on one stream (for PMC counter runs)")

@@ -367,6 +367,8 @@ def overlap_tuning(handle=None):
 
 
 def set_overlap_tuning(schur_workgroups, chunk_cols, one_stream=0, handle=None):
+    """cfx_set_overlap_tuning: schur_workgroups -1 (by precision, the default),
+    0 (one workgroup per tile) or >= 8; chunk_cols >= 1; one_stream 0 or 1."""
     h = handle or default_handle()
     _check("cfx_set_overlap_tuning",
            lib().cfx_set_overlap_tuning(h.h, int(schur_workgroups), int(chunk_cols), int(one_stream)))
