@@ -197,6 +197,25 @@ def test_getrf_lookahead_bitwise_equal(cfx, n, v, L):
     assert np.array_equal(a[0], b[0])
 
 
+def test_overlap_tuning_rejects_invalid_values(cfx):
+    """cfx_set_overlap_tuning: -2 for a workgroup bound below -1 or in
+    1..7, -3 for chunk_cols < 1, -4 for one_stream outside {0, 1}; a
+    rejected call leaves the settings unchanged."""
+    h = cfx.Handle()
+    try:
+        cfx.set_overlap_tuning(8, 256, 1, handle=h)
+        for args, code in [((-2, 512, 0), -2), ((1, 512, 0), -2), ((7, 512, 0), -2),
+                           ((0, 0, 0), -3), ((0, 512, 2), -4)]:
+            with pytest.raises(cfx.CfxError) as e:
+                cfx.set_overlap_tuning(*args, handle=h)
+            assert e.value.code == code, args
+            assert cfx.overlap_tuning(handle=h) == (8, 256, 1)
+        cfx.set_overlap_tuning(-1, 512, 0, handle=h)
+        assert cfx.overlap_tuning(handle=h) == (-1, 512, 0)
+    finally:
+        h.close()
+
+
 @pytest.mark.parametrize("n,wgs,chunk", [(2100, 8, 64), (2100, 12, 300), (2100, 40, 4096), (2048, 8, 256),
                                          (2048, 24, 4096)])
 def test_getrf_bounded_schur_grid_bitwise_equal(cfx, n, wgs, chunk):
