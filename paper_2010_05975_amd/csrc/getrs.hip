@@ -395,6 +395,7 @@ __global__ __launch_bounds__(256) void trsv_sf_kernel(const double *__restrict__
                                                       int64_t n, int nb, int32_t *sync)
 {
     __shared__ double part[TB];
+    __shared__ double Ts[TB][TB + 1];   // the diagonal block (padded rows)
     __shared__ int sh_t, sh_avail;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int32_t *ticket = sync + (LOWER ? 0 : 2);
@@ -416,22 +417,42 @@ __global__ __launch_bounds__(256) void trsv_sf_kernel(const double *__restrict__
 #pragma unroll
         for (int e = 0; e < 16; ++e) lv[e] = (rok && c0 + e < n) ? lrow[c0 + e] : 0.0;
     };
-    // the diagonal block's row and right-hand side of wave 0's lanes, fetched
-    // before any wait (they do not depend on other blocks)
+    // one value of block i of the solution per lane (lane l: column l)
+    auto load_x = [&](int i) -> double {
+        const int64_t c = (int64_t)(LOWER ? i : nb - 1 - i) * TB + lane;
+        return c < n ? x[c] : 0.0;
+    };
+    // the diagonal block (L: strictly lower; U: upper with the diagonal) is
+    // staged in LDS before any wait; wave 0 takes it into registers only for
+    // the solve, so the registers stay free for the prefetch ring below
+#pragma unroll
+    for (int e = tid; e < TB * TB; e += 256) {
+        const int i = e / TB, j = e - i * TB;
+        const bool in = i < rows && j < rows && (LOWER ? j < i : j >= i);
+        Ts[i][j] = in ? LU[(r0 + i) * lda + r0 + j] : 0.0;
+    }
     const bool ok = wave == 0 && lane < rows;
     const int64_t gi = r0 + (ok ? lane : 0);
-    const double *drow = LU + gi * lda + r0;
-    double Tr[TB];      // L: columns j < lane; U: columns j > lane
-#pragma unroll
-    for (int j = 0; j < TB; ++j) Tr[j] = (ok && (LOWER ? j < lane : (j > lane && j < rows))) ? drow[j] : 0.0;
-    const double dg = (!LOWER && ok) ? drow[lane] : 1.0;
     const double rhs = ok ? x[gi] : 0.0;
 
     // per row: block sums (16 products each, one lane) accumulated over the
-    // blocks with Neumaier's compensation
+    // blocks with Neumaier's compensation.  The factor tiles of the next
+    // blocks are requested D ahead, and the solution values of every block
+    // already known to be solved as soon as that is known (one value per
+    // lane, spread to the lanes that need it by cross-lane moves), so a
+    // block row that runs behind the solved blocks does not pay one memory
+    // round trip per block.
+    constexpr int D = 3;
     double acc = 0.0, cmp = 0.0;
-    double lv[16];
-    if (nk > 0) load_l(0, lv);
+    double lq[D][16];
+    double xq[D];
+    bool xv[D];
+    static_for<D>([&](auto S) {
+        constexpr int q = decltype(S)::value;
+        if (q < nk) load_l(q, lq[q]);
+        xq[q] = 0.0;
+        xv[q] = false;
+    });
     int i = 0;
     while (i < nk) {
         if (tid == 0) {
@@ -451,19 +472,33 @@ __global__ __launch_bounds__(256) void trsv_sf_kernel(const double *__restrict__
         __syncthreads();
         const int avail = sh_avail;
         for (; i < avail; ++i) {
+            static_for<D>([&](auto S) {
+                constexpr int q = decltype(S)::value;
+                if (!xv[q] && i + q < avail) {
+                    xq[q] = load_x(i + q);
+                    xv[q] = true;
+                }
+            });
             double ln[16];
-            if (i + 1 < nk) load_l(i + 1, ln);
-            const int64_t c0 = kcol(i);
+            if (i + D < nk) load_l(i + D, ln);
             double bsum = 0.0;
 #pragma unroll
-            for (int e = 0; e < 16; ++e) bsum += lv[e] * (c0 + e < n ? x[c0 + e] : 0.0);
+            for (int e = 0; e < 16; ++e) bsum += lq[0][e] * __shfl(xq[0], cq + e);
             const double tsum = acc + bsum;
             cmp += fabs(acc) >= fabs(bsum) ? (acc - tsum) + bsum : (bsum - tsum) + acc;
             acc = tsum;
-            if (i + 1 < nk) {
+            static_for<D - 1>([&](auto S) {
+                constexpr int q = decltype(S)::value;
 #pragma unroll
-                for (int e = 0; e < 16; ++e) lv[e] = ln[e];
+                for (int e = 0; e < 16; ++e) lq[q][e] = lq[q + 1][e];
+                xq[q] = xq[q + 1];
+                xv[q] = xv[q + 1];
+            });
+            if (i + D < nk) {
+#pragma unroll
+                for (int e = 0; e < 16; ++e) lq[D - 1][e] = ln[e];
             }
+            xv[D - 1] = false;
         }
         __syncthreads();                          // sh_avail is written again
     }
@@ -473,6 +508,10 @@ __global__ __launch_bounds__(256) void trsv_sf_kernel(const double *__restrict__
     if ((lane & 3) == 0) part[rr] = acc;
     __syncthreads();
     if (wave != 0) return;
+    double Tr[TB];      // L: columns j < lane; U: columns j > lane
+#pragma unroll
+    for (int j = 0; j < TB; ++j) Tr[j] = (LOWER || j > lane) ? Ts[lane][j] : 0.0;
+    const double dg = (!LOWER && ok) ? Ts[lane][lane] : 1.0;
     double v = ok ? rhs - part[lane] : 0.0;
     if constexpr (LOWER) {
 #pragma unroll
