@@ -349,7 +349,9 @@ int cfx_serve_destroy(cfx_server *s);
 
 /* Per-phase device time of the factorisation steps, for measurement.
  * Between cfx_profile_begin and cfx_profile_end every cfx_getrf on the
- * handle records HIP events around each phase on the stream that runs it.
+ * handle records HIP events around each phase on the stream that runs it
+ * (the column-chunk launches of one overlapped trailing update form one
+ * timed span; schur_launches counts the launches inside the spans).
  * cfx_profile_end waits for those events (host-blocking), fills `out`
  * (host pointer) with the summed durations and stops recording.
  *   schur_flops : algorithmic flops of the Schur updates, 2 * rows * cols * K

@@ -15,7 +15,7 @@ struct Profiler {
     bool on = false;
     std::vector<hipEvent_t> pool;
     size_t used = 0;
-    struct Rec { int phase; hipEvent_t a, b; double flops; };
+    struct Rec { int phase; hipEvent_t a, b; double flops; int launches; };
     std::vector<Rec> recs;
     int64_t panels = 0;
 
@@ -36,13 +36,13 @@ struct Profiler {
         if (e) (void)hipEventRecord(e, st);
         return e;
     }
-    void end(int phase, hipEvent_t a, hipStream_t st, double flops = 0.0)
+    void end(int phase, hipEvent_t a, hipStream_t st, double flops = 0.0, int launches = 1)
     {
         if (!on || !a) return;
         hipEvent_t e = next();
         if (!e) return;
         (void)hipEventRecord(e, st);
-        recs.push_back({phase, a, e, flops});
+        recs.push_back({phase, a, e, flops, launches});
     }
 };
 }  // namespace cfx
@@ -272,7 +272,7 @@ int cfx_profile_end(cfx_handle *h, cfx_profile *out)
         ms[rec.phase] += t;
         if (rec.phase == PH_SCHUR) {
             r.schur_flops += rec.flops;
-            ++r.schur_launches;
+            r.schur_launches += rec.launches;
         }
     }
     r.tslu_ms = ms[PH_TSLU];
@@ -421,13 +421,18 @@ int cfx_getrf(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *ipiv, i
             // the rest of the update, in column chunks: between two chunks
             // the dispatcher can start the tournament's launches queued on
             // the side stream instead of leaving them behind one huge grid
+            // (one event pair around all chunks: events between the
+            // launches would cost the step about 2 %)
             const int64_t chunk = h->la_chunk;
             const int wgs = h->schur_wgs >= 0 ? h->schur_wgs : (prec == CFX_PREC_FP64 ? 0 : cfx::kLpSchurWgs);
-            for (int64_t c0 = vbn; c0 < m; c0 += chunk) {
-                const int64_t cw = (m - c0) < chunk ? (m - c0) : chunk;
+            if (vbn < m) {
                 e = pf.begin(us);
-                if ((rc = schur_update(prec, ws, L21, U12, C, lda, m, c0, cw, vb, wgs, us))) return rc;
-                pf.end(PH_SCHUR, e, us, 2.0 * (double)m * (double)cw * vb);
+                int nl = 0;
+                for (int64_t c0 = vbn; c0 < m; c0 += chunk, ++nl) {
+                    const int64_t cw = (m - c0) < chunk ? (m - c0) : chunk;
+                    if ((rc = schur_update(prec, ws, L21, U12, C, lda, m, c0, cw, vb, wgs, us))) return rc;
+                }
+                pf.end(PH_SCHUR, e, us, 2.0 * (double)m * (double)(m - vbn) * vb, nl);
             }
 
         }
