@@ -21,6 +21,8 @@
 namespace cfx {
 namespace {
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+
 constexpr int kPermLds = 36864;   // n up to this uses the LDS permutation (144 KiB)
 static_assert(kPermLds <= 0x10000, "row indices and the tags of perm_lds_kernel share a 32-bit entry");
 constexpr int SB = 128;           // block of the substitution
@@ -139,8 +141,9 @@ __global__ void copy_rows_kernel(const double *T, int64_t ldt, int64_t n, int64_
 }
 
 // x_i[c] -= sum_{k < bs} LU[i][c0 + k] * ys[k][c] for rows rbeg <= i < rend
-// and the nc right-hand sides cc .. cc+nc of this chunk.  A wavefront takes
-// 4 rows at a time, 16 lanes per row.
+// and the nc right-hand sides cc .. cc+nc of this chunk.  One right-hand
+// side: a wavefront takes 4 rows at a time, 16 lanes per row; 16 right-hand
+// sides: 16 rows at a time on the FP64 matrix cores.
 template <int NRC>
 __device__ __forceinline__ void update_rows(const double *__restrict__ LU, int64_t lda, double *X,
                                             int64_t ldx, int cc, int nc, int64_t rbeg, int64_t rend,
@@ -148,11 +151,12 @@ __device__ __forceinline__ void update_rows(const double *__restrict__ LU, int64
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int sub = lane >> 4, q = lane & 15;
-    for (int64_t i0 = rbeg + wave * 4; i0 < rend; i0 += 16) {
-        const int64_t i = i0 + sub;
-        const bool ok = i < rend;
-        const double *row = LU + (ok ? i : rbeg) * lda + c0;
+    constexpr int RW = NRC == 1 ? 4 : 16;       // rows per wavefront pass
+    for (int64_t i0 = rbeg + wave * RW; i0 < rend; i0 += 4 * RW) {
         if constexpr (NRC == 1) {
+            const int64_t i = i0 + sub;
+            const bool ok = i < rend;
+            const double *row = LU + (ok ? i : rbeg) * lda + c0;
             // lane q owns the 8 consecutive columns 8q .. 8q+7
             double s = 0.0;
 #pragma unroll
@@ -166,15 +170,30 @@ __device__ __forceinline__ void update_rows(const double *__restrict__ LU, int64
             s += __shfl_xor(s, 1, 16);
             if (ok && q == 0) X[i * ldx + cc] -= s;
         } else {
-            // lane q owns right-hand side cc + q
-            double s0 = 0.0, s1 = 0.0;
-            int k = 0;
-            for (; k + 1 < bs; k += 2) {
-                s0 += row[k] * ys[k * NRC + q];
-                s1 += row[k + 1] * ys[(k + 1) * NRC + q];
+            static_assert(NRC == 16, "the matrix-core update takes 16 right-hand sides");
+            // 16 rows x 16 right-hand sides per wavefront on the FP64 matrix
+            // cores, K = bs: A lane l = (row l%16, k l/16), B lane l =
+            // (k l/16, right-hand side l%16) from the staged block, D lane l
+            // element q = (row l/16 + 4q, right-hand side l%16).  Every factor
+            // value of the 16 rows is requested before the first product.
+            const int lr = lane & 15, lk = lane >> 4;
+            const int64_t ia = i0 + lr;
+            const double *arow = LU + (ia < rend ? ia : rbeg) * lda + c0;
+            double av[SB / 4];
+#pragma unroll
+            for (int t = 0; t < SB / 4; ++t) {
+                const int k = 4 * t + lk;
+                av[t] = (ia < rend && k < bs) ? arow[k] : 0.0;
             }
-            if (k < bs) s0 += row[k] * ys[k * NRC + q];
-            if (ok && q < nc) X[i * ldx + cc + q] -= s0 + s1;
+            d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int t = 0; t < SB / 4; ++t)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], ys[(4 * t + lk) * NRC + lr], acc, 0, 0, 0);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t ir = i0 + lk + 4 * e;
+                if (ir < rend && lr < nc) X[ir * ldx + cc + lr] -= acc[e];
+            }
         }
     }
 }
@@ -426,7 +445,8 @@ __global__ __launch_bounds__(256) void trsv_sf_kernel(const double *__restrict__
     // staged in LDS before any wait; wave 0 takes it into registers only for
     // the solve, so the registers stay free for the prefetch ring below
 #pragma unroll
-    for (int e = tid; e < TB * TB; e += 256) {
+    for (int rep = 0; rep < TB * TB / 256; ++rep) {
+        const int e = tid + 256 * rep;
         const int i = e / TB, j = e - i * TB;
         const bool in = i < rows && j < rows && (LOWER ? j < i : j >= i);
         Ts[i][j] = in ? LU[(r0 + i) * lda + r0 + j] : 0.0;
