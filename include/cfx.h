@@ -47,6 +47,8 @@ enum {
     CFX_EHIP = -1002,         /* a HIP runtime call failed                 */
     CFX_EBUSY = -1003,        /* serving: queue full                       */
     CFX_ENOTSUP = -1004,      /* shape outside the supported range         */
+    CFX_ESOLVE = -1005,       /* a one-launch triangular solve gave up a
+                                 wait (bounded spin); its result is NaN    */
 };
 
 enum {
@@ -150,6 +152,24 @@ int cfx_tslu(cfx_handle *h, int64_t rows, int64_t vb, const double *W,
 int cfx_getrs(cfx_handle *h, int64_t n, int64_t nrhs, const double *LU,
               int64_t lda, const int32_t *ipiv, double *B, int64_t ldb,
               void *stream);
+/* Scratch and ordering of cfx_getrs: the permutation and the gathered
+ * right-hand sides live in a device buffer owned by the handle, grown with
+ * hipMalloc when a call needs more (hipFree of the old one waits for the
+ * device).  Calls on one handle are ordered on the device through an event
+ * of the handle, whatever streams they are issued on.
+ *
+ * A single contiguous right-hand side takes a one-launch-per-triangle solve
+ * whose blocks wait for earlier blocks with a bounded spin.  The waits end
+ * on a working device; if one ever gives up, that block writes NaN for its
+ * rows and a sticky flag of the handle is set.  cfx_getrs_check
+ * (host-blocking: it synchronises `stream`) returns CFX_ESOLVE and clears
+ * the flag when any solve on the handle gave up since the last check, else
+ * CFX_OK.  cfx_set_solve_spin_limit sets the number of polls before a wait
+ * gives up (default 4194304; 0 gives up at once, which tests use to force
+ * the error path while every kernel still exits normally); it also applies
+ * to cfx_gesv_ir and to serving workers.  Returns -2 for polls < 0. */
+int cfx_getrs_check(cfx_handle *h, void *stream);
+int cfx_set_solve_spin_limit(cfx_handle *h, int32_t polls);
 
 /* Mixed-precision solve with iterative refinement.  The paper computes the
  * factorisation only; refinement is the standard GMRES-IR of Carson and
@@ -201,7 +221,9 @@ int cfx_gesv_ir_buffer_size(cfx_handle *h, int64_t n, int64_t nrhs,
  *   work : device, >= cfx_gesv_ir_buffer_size bytes, 256-byte aligned.
  * Host-blocking: returns when X and rep are final (it synchronises
  * `stream`, on which all of its work runs).  A singular factorisation is
- * reported through rep->info (and a non-finite eta), not the return value. */
+ * reported through rep->info (and a non-finite eta), not the return value.
+ * Returns CFX_ESOLVE (rep still filled, eta NaN) when a triangular solve of
+ * the refinement gave up a wait (see cfx_getrs_check). */
 int cfx_gesv_ir(cfx_handle *h, int64_t n, int64_t nrhs, const double *A,
                 int64_t lda, const double *B, int64_t ldb, double *X,
                 int64_t ldx, const cfx_ir_opts *opts, cfx_ir_report *rep,
@@ -309,7 +331,8 @@ typedef struct {
 } cfx_request;
 
 typedef struct {
-    int32_t status;      /* CFX_OK, or CFX_ENOMEM (does not fit the arena)
+    int32_t status;      /* CFX_OK, or CFX_ENOMEM (does not fit the arena),
+                            CFX_ESOLVE (a triangular solve gave up a wait)
                             or another error code of the solve             */
     int32_t info;        /* factorisation info                             */
     uint64_t factor_id;  /* id of the factors used (new or reused)         */

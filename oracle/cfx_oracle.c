@@ -337,12 +337,14 @@ double oracle_eta(int64_t n, const double *A, int64_t lda, const double *x,
                   int64_t incx, const double *b, int64_t incb)
 {
     double rmax = 0.0, anorm = 0.0, xnorm = 0.0, bnorm = 0.0;
+    int bad = 0;   /* some x_i, b_i or residual entry is not finite */
     for (int64_t i = 0; i < n; ++i) {
         double ax = fabs(x[i * incx]), ab = fabs(b[i * incb]);
+        if (!isfinite(ax) || !isfinite(ab)) bad = 1;
         if (ax > xnorm) xnorm = ax;
         if (ab > bnorm) bnorm = ab;
     }
-    #pragma omp parallel for schedule(static) reduction(max:rmax, anorm)
+    #pragma omp parallel for schedule(static) reduction(max:rmax, anorm) reduction(|:bad)
     for (int64_t i = 0; i < n; ++i) {
         const double *ri = A + i * lda;
         /* r_i = b_i - sum_j a_ij x_j, accumulated as s + c (Dot2). */
@@ -356,9 +358,11 @@ double oracle_eta(int64_t n, const double *A, int64_t lda, const double *x,
             rowabs += fabs(ri[j]);
         }
         double r = fabs(s + c);
+        if (!isfinite(r) || !isfinite(rowabs)) bad = 1;
         if (r > rmax) rmax = r;
         if (rowabs > anorm) anorm = rowabs;
     }
+    if (bad) return NAN;
     double den = anorm * xnorm + bnorm;
     return den > 0.0 ? rmax / den : 0.0;
 }

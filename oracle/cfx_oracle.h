@@ -61,9 +61,12 @@ int oracle_getrs(int64_t n, int64_t nrhs, const double *LU, int64_t lda,
 
 /* Normwise backward error of one solution column,
  *   eta = ||b - A x||_inf / (||A||_inf ||x||_inf + ||b||_inf),
- * with every residual entry accumulated in doubled precision (error-free
- * TwoProduct by fma and TwoSum, the "Dot2" scheme of Ogita, Rump and Oishi,
- * 2005).  x and b are strided columns (stride incx / incb). */
+ * with every residual entry accumulated in doubled precision (the "Dot2"
+ * scheme of Ogita, Rump and Oishi, 2005: Knuth's error-free TwoSum and
+ * Dekker's TwoProduct with Veltkamp's splitting, no fused multiply-add).
+ * x and b are strided columns (stride incx / incb).  Returns NaN when any
+ * x_i, b_i or residual entry (hence any entry of A met by it) is not
+ * finite, so a non-finite solution never scores as accurate. */
 double oracle_eta(int64_t n, const double *A, int64_t lda, const double *x,
                   int64_t incx, const double *b, int64_t incb);
 

@@ -126,6 +126,8 @@ def eta(A: np.ndarray, x: np.ndarray, b: np.ndarray) -> float:
         xc = np.ascontiguousarray(X[:, c])
         bc = np.ascontiguousarray(Bm[:, c])
         e = lib().oracle_eta(n, _dp(A), A.shape[1], _dp(xc), 1, _dp(bc), 1)
+        if e != e:              # a non-finite column makes the whole result NaN
+            return e
         worst = max(worst, e)
     return worst
 

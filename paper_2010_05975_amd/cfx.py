@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libcfx.so")
 
 PREC = {"fp64": 0, "bf16": 1, "fp16": 2}
 STATUS = {0: "CFX_OK", 1: "CFX_PENDING", -1001: "CFX_ENOMEM", -1002: "CFX_EHIP",
-          -1003: "CFX_EBUSY", -1004: "CFX_ENOTSUP"}
+          -1003: "CFX_EBUSY", -1004: "CFX_ENOTSUP", -1005: "CFX_ESOLVE"}
 
 _lib = None
 
@@ -123,8 +123,11 @@ def lib():
         L.cfx_serve_destroy.argtypes = [vp]
         L.cfx_profile_begin.argtypes = [vp]
         L.cfx_profile_end.argtypes = [vp, C.POINTER(Profile)]
+        L.cfx_getrs_check.argtypes = [vp, vp]
+        L.cfx_set_solve_spin_limit.argtypes = [vp, i32]
         for f in ("cfx_create", "cfx_destroy", "cfx_getrf_buffer_size", "cfx_getrf",
-                  "cfx_tslu", "cfx_getrs", "cfx_gesv_ir_buffer_size", "cfx_gesv_ir",
+                  "cfx_tslu", "cfx_getrs", "cfx_getrs_check", "cfx_set_solve_spin_limit",
+                  "cfx_gesv_ir_buffer_size", "cfx_gesv_ir",
                   "cfx_gesv_batched_buffer_size", "cfx_gesv_batched", "cfx_batched_tune",
                   "cfx_batched_tuning", "cfx_batched_set_tuning", "cfx_serve_create",
                   "cfx_serve_submit", "cfx_serve_poll", "cfx_serve_release", "cfx_serve_stats_get",
@@ -248,6 +251,19 @@ def getrs(LU, ipiv, B, stream=None, handle=None):
     _check("cfx_getrs", lib().cfx_getrs(h.h, n, nrhs, _ptr(LU), lda, _ptr(ipiv), _ptr(Bm), ldb,
                                         _stream(stream)))
     return B
+
+
+def getrs_check(stream=None, handle=None):
+    """cfx_getrs_check: synchronises the stream; returns the status code
+    (0, or CFX_ESOLVE = -1005 when a one-launch solve gave up a wait)."""
+    h = handle or default_handle()
+    return int(lib().cfx_getrs_check(h.h, _stream(stream)))
+
+
+def set_solve_spin_limit(polls, handle=None):
+    """cfx_set_solve_spin_limit: polls before a solve's wait gives up."""
+    h = handle or default_handle()
+    _check("cfx_set_solve_spin_limit", lib().cfx_set_solve_spin_limit(h.h, int(polls)))
 
 
 def ir_opts(precision="bf16", v=256, leaves=64, lookahead=0, tol=5e-15, max_outer=20,

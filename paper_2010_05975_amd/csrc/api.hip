@@ -59,6 +59,11 @@ struct cfx_handle {
 
     void *scratch = nullptr;        // getrs permutation + gather buffer
     size_t scratch_bytes = 0;
+    int32_t *gsync = nullptr;       // getrs: counters of the one-launch solves
+                                    // (kTrsvSyncBytes; [4] = a wait gave up)
+    hipEvent_t ev_getrs = nullptr;  // the last getrs on this handle (scratch reuse)
+    bool getrs_issued = false;
+    int spin_limit = cfx::kSolveSpinLimit;
     cfx::Profiler prof;
     int cu_count = 256;
     // grid bound of the Schur updates that overlap the next tournament
@@ -82,6 +87,8 @@ struct cfx_handle {
 };
 
 namespace cfx {
+
+int solve_spin_limit(const cfx_handle *h) { return h->spin_limit; }
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -164,6 +171,7 @@ static int check_opts(const cfx_lu_opts *o)
 static int ensure_scratch(cfx_handle *h, size_t bytes)
 {
     if (h->scratch_bytes >= bytes) return CFX_OK;
+    // hipFree waits for the device, so no earlier getrs still reads it
     if (h->scratch) CFX_HIP(hipFree(h->scratch));
     h->scratch = nullptr;
     h->scratch_bytes = 0;
@@ -239,10 +247,20 @@ int cfx_create(cfx_handle **h)
         delete p;
         return CFX_EHIP;
     }
+    if (hipEventCreateWithFlags(&p->ev_getrs, hipEventDisableTiming) != hipSuccess ||
+        hipMalloc(&p->gsync, kTrsvSyncBytes) != hipSuccess ||
+        hipMemset(p->gsync, 0, kTrsvSyncBytes) != hipSuccess) {
+        cfx_destroy(p);
+        return CFX_EHIP;
+    }
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess &&
         cus > 0)
         p->cu_count = cus;
+    if (int rc = init_kernel_attributes()) {
+        cfx_destroy(p);
+        return rc;
+    }
 
     *h = p;
     return CFX_OK;
@@ -292,6 +310,8 @@ int cfx_destroy(cfx_handle *h)
     if (!h) return -1;
     for (hipEvent_t e : h->prof.pool) (void)hipEventDestroy(e);
     if (h->scratch) (void)hipFree(h->scratch);
+    if (h->gsync) (void)hipFree(h->gsync);
+    if (h->ev_getrs) (void)hipEventDestroy(h->ev_getrs);
     if (h->bexec) (void)hipGraphExecDestroy(h->bexec);
     if (h->bgraph) (void)hipGraphDestroy(h->bgraph);
     if (h->ev_panel) (void)hipEventDestroy(h->ev_panel);
@@ -491,27 +511,39 @@ int cfx_gesv_ir(cfx_handle *h, int64_t n, int64_t nrhs, const double *A, int64_t
     CFX_HIP(hipMemcpyAsync(&r.info, dinfo, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     CFX_HIP(hipStreamSynchronize(st));
     const IrVectors v = carve_ir(w + lay.off_vec, n, opts->gmres_restart);
-    const IrParams p{opts->tol, opts->max_outer, opts->gmres_tol};
+    IrParams p{opts->tol, opts->max_outer, opts->gmres_tol};
+    p.spin_limit = h->spin_limit;
     r.converged = 1;
     r.eta = 0.0;
     r.eta_first = 0.0;
+    // a NaN backward error of any right-hand side makes the aggregate NaN
+    auto worst = [](double acc, double e) { return (acc != acc || e != e) ? NAN : std::fmax(acc, e); };
+    // the give-up flag of the solves (sticky; work may hold anything)
+    if ((rc = launch_set_int(v.sync + 4, 0, st))) return rc;
+    int status = CFX_OK;
     for (int64_t c = 0; c < nrhs; ++c) {
         if ((rc = launch_copy_rows(n, 1, B + c, ldb, v.b, 1, st))) return rc;
         if ((rc = launch_gather_rows(n, 1, v.b, 1, perm, v.x, 1, st))) return rc;
-        if ((rc = launch_trsv(n, 1, F, n, v.x, 1, v.sync, st))) return rc;
+        if ((rc = launch_trsv(n, 1, F, n, v.x, 1, v.sync, st, p.spin_limit))) return rc;
         IrResult res{};
-        if ((rc = ir_refine(A, lda, F, n, perm, v, p, &res, st))) return rc;
+        rc = ir_refine(A, lda, F, n, perm, v, p, &res, st);
+        if (rc == CFX_ESOLVE) {         // X is NaN: report it, go on with the others
+            status = CFX_ESOLVE;
+            res.eta = NAN;
+            res.converged = 0;
+        } else if (rc) {
+            return rc;
+        }
         if ((rc = launch_copy_rows(n, 1, v.x, 1, X + c, ldx, st))) return rc;
-        r.eta = std::fmax(r.eta, res.eta);
-        r.eta_first = std::fmax(r.eta_first, res.eta_first);
-        if (!(res.eta == res.eta)) r.eta = res.eta;
+        r.eta = worst(r.eta, res.eta);
+        r.eta_first = worst(r.eta_first, res.eta_first);
         if (res.outer > r.outer) r.outer = res.outer;
         r.inner += res.inner;
         r.converged &= res.converged;
     }
     CFX_HIP(hipStreamSynchronize(st));
     *rep = r;
-    return CFX_OK;
+    return status;
 }
 
 int cfx_gesv_batched_buffer_size(cfx_handle *h, int32_t count, size_t *bytes)
@@ -743,14 +775,38 @@ int cfx_getrs(cfx_handle *h, int64_t n, int64_t nrhs, const double *LU, int64_t 
     if (!B && n > 0 && nrhs > 0) return -7;
     if (ldb < (nrhs > 1 ? nrhs : 1)) return -8;
     if (n == 0 || nrhs == 0) return CFX_OK;
-    const size_t need = kTrsvSyncBytes + align_up((size_t)n * sizeof(int32_t)) + (size_t)n * nrhs * sizeof(double);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t need = align_up((size_t)n * sizeof(int32_t)) + (size_t)n * nrhs * sizeof(double);
     int rc = ensure_scratch(h, need);
     if (rc) return rc;
-    int32_t *sync = static_cast<int32_t *>(h->scratch);
-    int32_t *perm = reinterpret_cast<int32_t *>(static_cast<char *>(h->scratch) + kTrsvSyncBytes);
-    double *tmp = reinterpret_cast<double *>(static_cast<char *>(h->scratch) + kTrsvSyncBytes +
+    // calls on one handle share its scratch and counters: each one waits for
+    // the previous one, whatever streams they are issued on
+    if (h->getrs_issued) CFX_HIP(hipStreamWaitEvent(st, h->ev_getrs, 0));
+    int32_t *perm = static_cast<int32_t *>(h->scratch);
+    double *tmp = reinterpret_cast<double *>(static_cast<char *>(h->scratch) +
                                              align_up((size_t)n * sizeof(int32_t)));
-    return launch_getrs(n, nrhs, LU, lda, ipiv, B, ldb, perm, tmp, sync, static_cast<hipStream_t>(stream));
+    rc = launch_getrs(n, nrhs, LU, lda, ipiv, B, ldb, perm, tmp, h->gsync, st, h->spin_limit);
+    if (rc) return rc;
+    CFX_HIP(hipEventRecord(h->ev_getrs, st));
+    h->getrs_issued = true;
+    return CFX_OK;
+}
+
+int cfx_getrs_check(cfx_handle *h, void *stream)
+{
+    if (!h) return -1;
+    bool gave_up = false;
+    int rc = read_solve_flag(h->gsync, static_cast<hipStream_t>(stream), &gave_up);
+    if (rc) return rc;
+    return gave_up ? CFX_ESOLVE : CFX_OK;
+}
+
+int cfx_set_solve_spin_limit(cfx_handle *h, int32_t polls)
+{
+    if (!h) return -1;
+    if (polls < 0) return -2;
+    h->spin_limit = polls;
+    return CFX_OK;
 }
 
 }  // extern "C"

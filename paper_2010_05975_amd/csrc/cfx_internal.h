@@ -53,10 +53,21 @@ int launch_tslu(const double *W, int64_t ldw, int64_t row0, int64_t rows, int vb
                 int leaves, const Workspace &ws, int32_t *piv_out, int32_t *ipiv,
                 int32_t *info, hipStream_t st);
 
+// Kernel attributes (dynamic LDS limits) of the current device; called by
+// cfx_create, so that no launch path sets them.
+int init_kernel_attributes();
+// The handle's spin limit of the one-launch triangular solves.
+int solve_spin_limit(const cfx_handle *h);
+
+// Polls of a one-launch triangular solve's wait before the block gives up
+// (sets sync[4] and writes NaN for its rows).
+constexpr int kSolveSpinLimit = 1 << 22;
+
 // getrs pieces: permutation of ipiv, and the blocked triangular solves.
 int launch_getrs(int64_t n, int64_t nrhs, const double *LU, int64_t lda,
                  const int32_t *ipiv, double *B, int64_t ldb, int32_t *perm,
-                 double *tmp, int32_t *sync, hipStream_t st);
+                 double *tmp, int32_t *sync, hipStream_t st,
+                 int spin_limit = kSolveSpinLimit);
 // perm[i] = source row of row i of P B (ipiv interchanges composed).
 int launch_perm(int64_t n, const int32_t *ipiv, int32_t *perm, hipStream_t st);
 // T[i, :] = B[perm[i], :]  /  B[i, :] = T[i, :]   (n x nrhs).
@@ -67,10 +78,14 @@ int launch_copy_rows(int64_t n, int64_t nrhs, const double *T, int64_t ldt,
 // X <- U^{-1} L^{-1} X in place (X n x nrhs, stride ldx).  `sync` (device,
 // kTrsvSyncBytes, may be null) lets one contiguous right-hand side take the
 // one-launch-per-triangle solve; calls sharing a sync buffer must be
-// stream-ordered.
+// stream-ordered.  sync[4] is set (and stays set until the host clears it)
+// when a wait of that solve gave up after spin_limit polls.
 constexpr size_t kTrsvSyncBytes = 256;
 int launch_trsv(int64_t n, int64_t nrhs, const double *LU, int64_t lda, double *X,
-                int64_t ldx, int32_t *sync, hipStream_t st);
+                int64_t ldx, int32_t *sync, hipStream_t st,
+                int spin_limit = kSolveSpinLimit);
+// Host-blocking: *gave_up = sync[4] after `st` drains; sync[4] is cleared.
+int read_solve_flag(int32_t *sync, hipStream_t st, bool *gave_up);
 
 // Apply the row-move plan to all n columns of A; the diagonal block of the
 // panel (rows k..k+vb, columns k..k+vb) is written from ws.lu00.
@@ -148,6 +163,7 @@ struct IrParams {
     double tol;
     int max_outer;
     double gmres_tol;
+    int spin_limit = kSolveSpinLimit;   // of the one-launch triangular solves
 };
 struct IrResult {
     double eta, eta_first;

@@ -391,11 +391,12 @@ __global__ __launch_bounds__(256) void bwd_step_kernel(const double *__restrict_
 // depend on timing.
 // ---------------------------------------------------------------------------
 constexpr int TB = 64;
-constexpr int kSpinLimit = 1 << 22;   // polls before a block gives up (sets sync[4])
 
+// Clears the tickets and solved counts; sync[4] (a wait gave up) is sticky
+// until the host reads and clears it.
 __global__ void trsv_sync_reset_kernel(int32_t *sync)
 {
-    if (threadIdx.x < 8) sync[threadIdx.x] = 0;
+    if (threadIdx.x < 4) sync[threadIdx.x] = 0;
 }
 
 template <int CTRL>
@@ -408,18 +409,24 @@ __device__ __forceinline__ double dpp_d(double a)
 
 // LOWER: L y = x with unit L (forward); else U x = y (backward).
 // sync[0..1] forward ticket / solved count, sync[2..3] backward, sync[4]
-// set when a wait gave up (never, when the tickets order the blocks).
+// set when a wait gave up after spin_limit polls (never, when the tickets
+// order the blocks and the device runs every resident workgroup; the bound
+// only guarantees that every workgroup exits).  A block that gave up writes
+// NaN for its rows, so an invalid solution is never mistaken for a result.
 template <bool LOWER>
 __global__ __launch_bounds__(256) void trsv_sf_kernel(const double *__restrict__ LU, int64_t lda, double *x,
-                                                      int64_t n, int nb, int32_t *sync)
+                                                      int64_t n, int nb, int32_t *sync, int spin_limit)
 {
     __shared__ double part[TB];
     __shared__ double Ts[TB][TB + 1];   // the diagonal block (padded rows)
-    __shared__ int sh_t, sh_avail;
+    __shared__ int sh_t, sh_avail, sh_gaveup;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int32_t *ticket = sync + (LOWER ? 0 : 2);
     int32_t *solved = sync + (LOWER ? 1 : 3);
-    if (tid == 0) sh_t = atomicAdd(ticket, 1);
+    if (tid == 0) {
+        sh_t = atomicAdd(ticket, 1);
+        sh_gaveup = 0;
+    }
     __syncthreads();
     const int t = sh_t;
     const int J = LOWER ? t : nb - 1 - t;
@@ -477,7 +484,7 @@ __global__ __launch_bounds__(256) void trsv_sf_kernel(const double *__restrict__
     while (i < nk) {
         if (tid == 0) {
             int sv = __hip_atomic_load(solved, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            for (int spins = 0; sv <= i && spins < kSpinLimit; ++spins) {
+            for (int spins = 0; sv <= i && spins < spin_limit; ++spins) {
                 __builtin_amdgcn_s_sleep(2);
                 sv = __hip_atomic_load(solved, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
@@ -485,6 +492,7 @@ __global__ __launch_bounds__(256) void trsv_sf_kernel(const double *__restrict__
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             if (sv <= i) {
                 atomicOr(sync + 4, 1);
+                sh_gaveup = 1;
                 sv = nk;
             }
             sh_avail = sv < nk ? sv : nk;
@@ -551,20 +559,23 @@ __global__ __launch_bounds__(256) void trsv_sf_kernel(const double *__restrict__
             }
         }
     }
-    if (ok) x[gi] = v;
+    if (ok) x[gi] = sh_gaveup ? __builtin_nan("") : v;
     // the wavefront's stores complete before the count moves on
     if (lane == 0) __hip_atomic_store(solved, t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-int trsv_one(int64_t n, const double *LU, int64_t lda, double *x, int32_t *sync, hipStream_t st)
+int trsv_one(int64_t n, const double *LU, int64_t lda, double *x, int32_t *sync, int spin_limit,
+             hipStream_t st)
 {
     const int64_t nb = (n + TB - 1) / TB;
     if (nb > INT32_MAX) return CFX_ENOTSUP;
     hipLaunchKernelGGL(trsv_sync_reset_kernel, dim3(1), dim3(64), 0, st, sync);
     CFX_HIP(hipGetLastError());
-    hipLaunchKernelGGL(trsv_sf_kernel<true>, dim3((unsigned)nb), dim3(256), 0, st, LU, lda, x, n, (int)nb, sync);
+    hipLaunchKernelGGL(trsv_sf_kernel<true>, dim3((unsigned)nb), dim3(256), 0, st, LU, lda, x, n, (int)nb, sync,
+                       spin_limit);
     CFX_HIP(hipGetLastError());
-    hipLaunchKernelGGL(trsv_sf_kernel<false>, dim3((unsigned)nb), dim3(256), 0, st, LU, lda, x, n, (int)nb, sync);
+    hipLaunchKernelGGL(trsv_sf_kernel<false>, dim3((unsigned)nb), dim3(256), 0, st, LU, lda, x, n, (int)nb, sync,
+                       spin_limit);
     CFX_HIP(hipGetLastError());
     return CFX_OK;
 }
@@ -605,6 +616,19 @@ int trsv_impl(int64_t n, int nrhs, const double *LU, int64_t lda, double *X, int
 
 }  // namespace
 
+int read_solve_flag(int32_t *sync, hipStream_t st, bool *gave_up)
+{
+    int32_t f = 0;
+    CFX_HIP(hipMemcpyAsync(&f, sync + 4, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    CFX_HIP(hipStreamSynchronize(st));
+    *gave_up = f != 0;
+    if (f) {
+        int rc = launch_set_int(sync + 4, 0, st);
+        if (rc) return rc;
+    }
+    return CFX_OK;
+}
+
 int launch_perm(int64_t n, const int32_t *ipiv, int32_t *perm, hipStream_t st)
 {
     if (n <= 0) return CFX_OK;
@@ -639,22 +663,22 @@ int launch_copy_rows(int64_t n, int64_t nrhs, const double *T, int64_t ldt, doub
 }
 
 int launch_trsv(int64_t n, int64_t nrhs, const double *LU, int64_t lda, double *X, int64_t ldx, int32_t *sync,
-                hipStream_t st)
+                hipStream_t st, int spin_limit)
 {
     if (n <= 0 || nrhs <= 0) return CFX_OK;
-    if (nrhs == 1 && sync && (ldx == 1 || n == 1)) return trsv_one(n, LU, lda, X, sync, st);
+    if (nrhs == 1 && sync && (ldx == 1 || n == 1)) return trsv_one(n, LU, lda, X, sync, spin_limit, st);
     if (nrhs == 1) return trsv_impl<1>(n, 1, LU, lda, X, ldx, st);
     return trsv_impl<16>(n, (int)nrhs, LU, lda, X, ldx, st);
 }
 
 int launch_getrs(int64_t n, int64_t nrhs, const double *LU, int64_t lda, const int32_t *ipiv, double *B,
-                 int64_t ldb, int32_t *perm, double *tmp, int32_t *sync, hipStream_t st)
+                 int64_t ldb, int32_t *perm, double *tmp, int32_t *sync, hipStream_t st, int spin_limit)
 {
     if (n == 0 || nrhs == 0) return CFX_OK;
     int rc;
     if ((rc = launch_perm(n, ipiv, perm, st))) return rc;
     if ((rc = launch_gather_rows(n, nrhs, B, ldb, perm, tmp, nrhs, st))) return rc;
-    if ((rc = launch_trsv(n, nrhs, LU, lda, tmp, nrhs, sync, st))) return rc;
+    if ((rc = launch_trsv(n, nrhs, LU, lda, tmp, nrhs, sync, st, spin_limit))) return rc;
     return launch_copy_rows(n, nrhs, tmp, nrhs, B, ldb, st);
 }
 

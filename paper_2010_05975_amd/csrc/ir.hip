@@ -257,6 +257,7 @@ struct Ctx {
     const int32_t *perm;
     IrVectors v;
     hipStream_t st;
+    int spin_limit;
 };
 
 // dst = M src = U^{-1} L^{-1} P src
@@ -264,7 +265,7 @@ int apply_m(const Ctx &c, const double *src, double *dst)
 {
     int rc = launch_gather_rows(c.v.n, 1, src, 1, c.perm, dst, 1, c.st);
     if (rc) return rc;
-    return launch_trsv(c.v.n, 1, c.F, c.ldf, dst, 1, c.v.sync, c.st);
+    return launch_trsv(c.v.n, 1, c.F, c.ldf, dst, 1, c.v.sync, c.st, c.spin_limit);
 }
 
 // out[0..nv) = V_k . w, k < nv (device result at `out`)
@@ -346,7 +347,7 @@ int backward_error(const Ctx &c, double &anorm, double &eta)
 int ir_refine(const double *A, int64_t lda, const double *F, int64_t ldf, const int32_t *perm,
               const IrVectors &v, const IrParams &p, IrResult *res, hipStream_t st)
 {
-    Ctx c{A, lda, F, ldf, perm, v, st};
+    Ctx c{A, lda, F, ldf, perm, v, st, p.spin_limit};
     const int m = v.restart;
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), hh(2 * (m + 1) + 1);
     double anorm = -1.0, eta = 0.0;
@@ -424,8 +425,11 @@ int ir_refine(const double *A, int64_t lda, const double *F, int64_t ldf, const 
         CFX_HIP(hipMemcpyAsync(v.out, y.data(), (size_t)jend * sizeof(double), hipMemcpyHostToDevice, st));
         if ((rc = vcomb(c, v.x, v.V, v.ldv, jend, v.out, 1.0))) return rc;
     }
-    CFX_HIP(hipStreamSynchronize(st));
-    return CFX_OK;
+    // a triangular solve of this refinement (or of the initial solve, whose
+    // flag is sticky too) that gave up waiting leaves NaN behind: an error
+    bool gave_up = false;
+    if ((rc = read_solve_flag(v.sync, st, &gave_up))) return rc;
+    return gave_up ? CFX_ESOLVE : CFX_OK;
 }
 
 }  // namespace cfx

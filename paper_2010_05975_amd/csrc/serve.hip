@@ -343,6 +343,7 @@ int run_single(cfx_server *S, cfx_handle *h, hipStream_t st, Job *j)
     const size_t wbytes = workspace_bytes(n, S->cfg.ir.lu.v, S->cfg.ir.lu.leaves, S->cfg.ir.lu.precision);
     IrVectors v = carve_ir(wk + al(wbytes), n, S->cfg.ir.gmres_restart);
     IrParams p{S->cfg.ir.tol, S->cfg.ir.max_outer, S->cfg.ir.gmres_tol};
+    p.spin_limit = solve_spin_limit(h);
     int rc = CFX_OK;
     int32_t info = 0;
     j->res.t_start = S->now();
@@ -362,13 +363,14 @@ int run_single(cfx_server *S, cfx_handle *h, hipStream_t st, Job *j)
         return CFX_OK;
     };
     if (!j->hit) SRV_CHECK(factor(S->cfg.ir.lu));
+    SRV_CHECK(launch_set_int(v.sync + 4, 0, st));   // give-up flag of the solves
     j->res.eta = 0.0;
     for (int64_t c = 0; c < r.nrhs; ++c) {
         IrResult ir{};
         for (;;) {
             SRV_CHECK(launch_copy_rows(n, 1, r.B + c, r.ldb, v.b, 1, st));
             SRV_CHECK(launch_gather_rows(n, 1, v.b, 1, f->perm, v.x, 1, st));
-            SRV_CHECK(launch_trsv(n, 1, f->F, n, v.x, 1, v.sync, st));
+            SRV_CHECK(launch_trsv(n, 1, f->F, n, v.x, 1, v.sync, st, p.spin_limit));
             ir = IrResult{};
             SRV_CHECK(ir_refine(r.A, r.lda, f->F, n, f->perm, v, p, &ir, st));
             if (ir.converged || f->prec == CFX_PREC_FP64) break;

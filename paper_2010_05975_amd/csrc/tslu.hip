@@ -721,17 +721,24 @@ __global__ __launch_bounds__(256) void tslu_gather_kernel(NodeArgs p, int tiles_
     if (tcol == 0 && tid < 64 && r0 + tid < r) p.rsel[(size_t)node * p.rs_node + r0 + tid] = 0;
 }
 
+// The node kernels' dynamic LDS exceeds the default limit; the attribute is
+// set once per device at handle creation (init_kernel_attributes), never on
+// the launch path, so concurrent launches from several host threads never
+// race on it.
+template <int RPT, int NT>
+int set_panel_attr()
+{
+    constexpr int BW = BlockW<RPT>::value;
+    CFX_HIP(hipFuncSetAttribute((const void *)tslu_panel_kernel<RPT, NT>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(Lds<BW, NT / 64>)));
+    return CFX_OK;
+}
+
 template <int RPT, int NT>
 int launch_level(NodeArgs a, int grid, int rows_cap, hipStream_t st)
 {
     constexpr int BW = BlockW<RPT>::value;
-    static bool attr_set = false;
     const size_t lds = sizeof(Lds<BW, NT / 64>);
-    if (!attr_set) {
-        CFX_HIP(hipFuncSetAttribute((const void *)tslu_panel_kernel<RPT, NT>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        attr_set = true;
-    }
     const int nsel_max = rows_cap < a.vb ? rows_cap : a.vb;
     const int tiles_r = (rows_cap + 63) / 64;
     {
@@ -771,6 +778,17 @@ int launch_node_level(const NodeArgs &a, int grid, int rows_cap, hipStream_t st)
 }
 
 }  // namespace
+
+int init_kernel_attributes()
+{
+    int rc;
+    if ((rc = set_panel_attr<1, 256>())) return rc;
+    if ((rc = set_panel_attr<2, 256>())) return rc;
+    if ((rc = set_panel_attr<2, 512>())) return rc;
+    if ((rc = set_panel_attr<4, 512>())) return rc;
+    if ((rc = set_panel_attr<8, 512>())) return rc;
+    return set_panel_attr<16, 512>();
+}
 
 int launch_tslu(const double *W, int64_t ldw, int64_t row0, int64_t rows, int vb, int leaves,
                 const Workspace &ws, int32_t *piv_out, int32_t *ipiv, int32_t *info, hipStream_t st)

@@ -29,6 +29,8 @@ MUTATIONS = {
     "leaf_height_unclamped": ("if (h < vb) h = vb;", ";"),
     "ipiv_relative_index": ("ipiv[k + j] = (int32_t)(k + r);", "ipiv[k + j] = (int32_t)(r);"),
     "gepp_no_elimination": ("blk[i * vb + c] -= l * blk[j * vb + c];", "(void)l;"),
+    "eta_no_compensation": ("c += te + pe;", "(void)te; (void)pe;"),
+    "eta_ignores_non_finite": ("if (bad) return NAN;", "(void)bad;"),
     "merge_uses_partial_values": ("gather_rows(W, ldw, row0, gid, cl + cr, vb, blk);",
                                   "gather_rows(W, ldw, row0, gid, cl + cr, vb, blk); "
                                   "for (int64_t q = cl; q < cl + cr; ++q) for (int64_t c = 0; c < vb; ++c) "

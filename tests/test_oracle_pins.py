@@ -436,6 +436,59 @@ def test_eta_catches_cancellation():
     assert O.eta(A, x, b) == 0.0
 
 
+def test_eta_compensation_recovers_lost_residual():
+    """The opposite case: the exact residual is nonzero but plain summation
+    loses it.  Row 0 gives r0 = 0 - (1e16 + 1 - 1e16) = -1 exactly, while
+    left-to-right summation from b0 = 0 rounds -1e16 - 1 back to -1e16 (the
+    spacing of doubles there is 2) and returns r0 = 0.  Exact eta =
+    1 / (||A||_inf ||x||_inf + ||b||_inf) = 1 / (2e16 + 1 + 1)."""
+    A = np.array([[1e16, 1.0, -1e16], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]])
+    x = np.ones(3)
+    b = np.array([0.0, 1.0, 1.0])
+    exact = float(Fraction(1) / (Fraction(2 * 10**16 + 1) + 1))
+    assert O.eta(A, x, b) == pytest.approx(exact, rel=1e-15)
+    assert O.eta(A, x, b) > 0.0
+
+
+@pytest.mark.parametrize("bad", [np.nan, np.inf, -np.inf])
+@pytest.mark.parametrize("where", ["x_one", "x_all", "b_one"])
+def test_eta_non_finite_is_never_accurate(bad, where):
+    """A non-finite solution (or right-hand side) must not score as a small
+    backward error: eta is then NaN, so every "eta <= tol" check fails."""
+    rng = np.random.default_rng(3)
+    n = 16
+    A = rng.standard_normal((n, n))
+    x = rng.standard_normal(n)
+    b = A @ x
+    if where == "x_one":
+        x[5] = bad
+    elif where == "x_all":
+        x[:] = bad
+    else:
+        b[7] = bad
+    e = O.eta(A, x, b)
+    assert not np.isfinite(e)
+    assert not (e <= 5e-15)
+
+
+def test_eta_non_finite_matrix_entry():
+    """An infinite entry of A met by the residual makes eta NaN as well."""
+    A = np.eye(4)
+    A[2, 1] = np.inf
+    x = np.ones(4)
+    b = np.ones(4)
+    assert not np.isfinite(O.eta(A, x, b))
+
+
+def test_eta_max_over_columns_keeps_nan():
+    """Several right-hand sides: a NaN column is not hidden by a later finite one."""
+    A = np.eye(3)
+    X = np.ones((3, 2))
+    B = np.ones((3, 2))
+    X[0, 0] = np.nan
+    assert not np.isfinite(O.eta(A, X, B))
+
+
 # ---------------------------------------------------------------------------
 # Generators with closed forms
 # ---------------------------------------------------------------------------
