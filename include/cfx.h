@@ -55,6 +55,10 @@ enum {
     CFX_PREC_FP64 = 0,        /* every step in FP64                        */
     CFX_PREC_BF16 = 1,        /* Schur update with BF16 operands, FP32 acc */
     CFX_PREC_FP16 = 2,        /* Schur update with FP16 operands, FP32 acc */
+    CFX_PREC_FP8 = 3,         /* Schur update with FP8 (OCP E4M3) operands,
+                                 each row of L21 and column of U12 scaled by
+                                 a power of two first, FP32 acc (an
+                                 experiment: 3 fraction bits)              */
 };
 
 /* Options of the tournament-pivoted LU.
@@ -63,10 +67,14 @@ enum {
  *               leaves of h = max(v, ceil(r / L)) rows (the last one may be
  *               shorter).  h must not exceed 8192 rows.
  *   precision : CFX_PREC_*; the pivot search, row interchanges and both
- *               triangular solves are always FP64.  With BF16/FP16 each
- *               Schur update rounds L21 and U12 to that format, multiplies
- *               on the matrix cores with FP32 accumulation and subtracts
- *               the FP32 sum from the FP64 trailing matrix.
+ *               triangular solves are always FP64.  With BF16/FP16/FP8 each
+ *               Schur update rounds L21 and U12 to that format (to nearest,
+ *               ties to even, once from FP64; FP8 after scaling each row of
+ *               L21 and each column of U12 by the power of two that brings
+ *               its largest magnitude into [128, 256)), multiplies on the
+ *               matrix cores with FP32 accumulation and subtracts the FP32
+ *               sum (FP8: scaled back exactly) from the FP64 trailing
+ *               matrix.
  *   lookahead : 0 or 1; 1 overlaps the next panel's tournament with the
  *               rest of the current Schur update on a second stream. */
 typedef struct {
@@ -141,6 +149,30 @@ int cfx_tslu(cfx_handle *h, int64_t rows, int64_t vb, const double *W,
              int64_t ldw, int64_t row0, int32_t leaves, int32_t *piv,
              void *work, size_t work_bytes, void *stream);
 
+/* The Schur-complement update alone (FactorizeA11 of Alg. 1, statement S2
+ * of Sec. 6, which carries the 2N^3/3 flops of the factorisation):
+ *     C[0:m, 0:n] -= L21[0:m, 0:K] U12[0:K, 0:n]
+ * with the arithmetic cfx_getrf uses for `precision` (FP64: FP64 matrix
+ * cores, FP64 accumulation; BF16/FP16/FP8: operands rounded as described
+ * under cfx_lu_opts, FP32 accumulation, FP64 C).
+ *   L21 : device, m x K row-major, stride ldl >= max(1, K).
+ *   U12 : device, K x n row-major, stride ldu >= max(1, n).
+ *   C   : device, m x n row-major, stride ldc >= max(1, n); must not
+ *         overlap L21 or U12.
+ *   max_workgroups : 0 = one workgroup per 128 x 128 tile; else (>= 8) a
+ *         persistent grid of that many workgroups walks the tiles.
+ *   work : device, cfx_schur_update_buffer_size bytes, 256-byte aligned
+ *         (0 bytes, and work may be NULL, for FP64; the packed operands
+ *         otherwise).
+ * Asynchronous on `stream`. */
+int cfx_schur_update_buffer_size(cfx_handle *h, int32_t precision, int64_t m,
+                                 int64_t n, int64_t K, size_t *bytes);
+int cfx_schur_update(cfx_handle *h, int32_t precision, int64_t m, int64_t n,
+                     int64_t K, const double *L21, int64_t ldl,
+                     const double *U12, int64_t ldu, double *C, int64_t ldc,
+                     int32_t max_workgroups, void *work, size_t work_bytes,
+                     void *stream);
+
 /* Solve A X = B with the factors of cfx_getrf: apply the interchanges of
  * ipiv to B in order, forward substitution with unit L, back substitution
  * with U.
@@ -170,6 +202,7 @@ int cfx_getrs(cfx_handle *h, int64_t n, int64_t nrhs, const double *LU,
  * to cfx_gesv_ir and to serving workers.  Returns -2 for polls < 0. */
 int cfx_getrs_check(cfx_handle *h, void *stream);
 int cfx_set_solve_spin_limit(cfx_handle *h, int32_t polls);
+
 
 /* Mixed-precision solve with iterative refinement.  The paper computes the
  * factorisation only; refinement is the standard GMRES-IR of Carson and

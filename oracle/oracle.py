@@ -173,30 +173,77 @@ def ipiv_sign(ipiv: np.ndarray) -> int:
 # the FP32 accumulation of the matrix cores.
 # --------------------------------------------------------------------------
 
-_FORMATS = {"bf16": (8, -126, 3.3895313892515355e38),   # precision, emin, max finite
-            "fp16": (11, -14, 65504.0)}
+# precision p (significand bits), emin, largest finite value, and whether
+# the format has infinities (OCP FP8 E4M3 has none: an overflow, an infinite
+# or a NaN input all give NaN)
+_FORMATS = {"bf16": (8, -126, 3.3895313892515355e38, True),
+            "fp16": (11, -14, 65504.0, True),
+            "fp8": (4, -6, 448.0, False)}
 
 
 def round_lowp(x, precision: str) -> np.ndarray:
-    """Round FP64 values to BF16 or FP16 (nearest, ties to even), returned as
-    FP64.  Written from the format definition: a value with exponent e
-    (2^e <= |x| < 2^(e+1), e clamped below at emin for subnormals) is rounded
-    to a multiple of 2^(e - p + 1); beyond the largest finite value (after
-    rounding) the result is infinite."""
+    """Round FP64 values to BF16, FP16 or FP8 E4M3 (nearest, ties to even),
+    returned as FP64.  Written from the format definition: a value with
+    exponent e (2^e <= |x| < 2^(e+1), e clamped below at emin for
+    subnormals) is rounded to a multiple of 2^(e - p + 1); beyond the largest
+    finite value (after rounding) the result is infinite (BF16, FP16) or NaN
+    (E4M3, which has no infinities; its infinite inputs give NaN too)."""
     if precision not in _FORMATS:
         raise ValueError(precision)
-    p, emin, vmax = _FORMATS[precision]
+    p, emin, vmax, has_inf = _FORMATS[precision]
     x = np.asarray(x, dtype=np.float64)
     out = np.array(x, dtype=np.float64, copy=True)
+    if not has_inf:
+        out[np.isinf(x)] = np.nan
     fin = np.isfinite(x) & (x != 0)
     xf = x[fin]
     _, e2 = np.frexp(np.abs(xf))                 # |x| = m 2^e2, m in [0.5, 1)
     e = np.maximum(e2 - 1, emin)
     q = np.ldexp(1.0, e - p + 1)                 # quantum, a power of two
     r = np.rint(xf / q) * q                      # exact scaling; rint ties to even
-    r[np.abs(r) > vmax] = np.inf * np.sign(r[np.abs(r) > vmax])
+    big = np.abs(r) > vmax
+    r[big] = (np.inf * np.sign(r[big])) if has_inf else np.nan
     out[fin] = r
     return out
+
+
+def fp8_scale_exponents(M: np.ndarray, axis: int) -> np.ndarray:
+    """Power-of-two scale exponents of the FP8 operands: for each row
+    (axis=1) or column (axis=0) with largest magnitude f 2^E (f in [0.5, 1)),
+    s = 8 - E, so that the scaled largest magnitude lies in [128, 256), well
+    inside the E4M3 range; s = 0 for an all-zero or non-finite vector."""
+    mx = np.max(np.abs(M), axis=axis) if M.size else np.zeros(M.shape[1 - axis])
+    _, E = np.frexp(mx)
+    s = (8 - E).astype(np.int64)
+    s[~(np.isfinite(mx) & (mx > 0))] = 0
+    return s
+
+
+def lowp_operands(L21: np.ndarray, U12: np.ndarray, precision: str):
+    """The rounded operands of one low-precision Schur update, as FP64
+    values: (Lr, Ur) with Lr Ur the product the update subtracts.  BF16 and
+    FP16 round every entry once; FP8 scales row i of L21 by 2^sL_i and column
+    j of U12 by 2^sU_j, rounds, and scales back (exact powers of two); a row
+    (column) holding a non-finite value becomes all NaN, so its row (column)
+    of the update is NaN."""
+    if precision != "fp8":
+        return round_lowp(L21, precision), round_lowp(U12, precision)
+    sL = fp8_scale_exponents(L21, 1)
+    sU = fp8_scale_exponents(U12, 0)
+    with np.errstate(invalid="ignore", over="ignore"):
+        Lr = np.ldexp(round_lowp(np.ldexp(L21, sL[:, None]), "fp8"), -sL[:, None])
+        Ur = np.ldexp(round_lowp(np.ldexp(U12, sU[None, :]), "fp8"), -sU[None, :])
+    Lr[~np.all(np.isfinite(L21), axis=1)] = np.nan
+    Ur[:, ~np.all(np.isfinite(U12), axis=0)] = np.nan
+    return Lr, Ur
+
+
+def schur_lowp(C: np.ndarray, L21: np.ndarray, U12: np.ndarray, precision: str) -> np.ndarray:
+    """FactorizeA11 with low-precision operands: C - Lr Ur, the rounded
+    operands multiplied and summed in FP64 (each product is exact)."""
+    Lr, Ur = lowp_operands(L21, U12, precision)
+    with np.errstate(invalid="ignore"):
+        return C - Lr @ Ur
 
 
 def tail_after_lowp_update(A: np.ndarray, v: int, L: int, precision: str):
@@ -211,5 +258,5 @@ def tail_after_lowp_update(A: np.ndarray, v: int, L: int, precision: str):
     PA = A[ipiv_to_perm(np.concatenate([f.ipiv[:vb], np.arange(vb, n)]).astype(np.int32))]
     L21 = f.LU[vb:, :vb]
     U12 = f.LU[:vb, vb:]
-    S = PA[vb:, vb:] - round_lowp(L21, precision) @ round_lowp(U12, precision)
+    S = schur_lowp(PA[vb:, vb:], L21, U12, precision)
     return f, S

@@ -15,7 +15,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcfx.so")
 
-PREC = {"fp64": 0, "bf16": 1, "fp16": 2}
+PREC = {"fp64": 0, "bf16": 1, "fp16": 2, "fp8": 3}
 STATUS = {0: "CFX_OK", 1: "CFX_PENDING", -1001: "CFX_ENOMEM", -1002: "CFX_EHIP",
           -1003: "CFX_EBUSY", -1004: "CFX_ENOTSUP", -1005: "CFX_ESOLVE"}
 
@@ -124,9 +124,12 @@ def lib():
         L.cfx_profile_begin.argtypes = [vp]
         L.cfx_profile_end.argtypes = [vp, C.POINTER(Profile)]
         L.cfx_getrs_check.argtypes = [vp, vp]
+        L.cfx_schur_update_buffer_size.argtypes = [vp, i32, i64, i64, i64, C.POINTER(sz)]
+        L.cfx_schur_update.argtypes = [vp, i32, i64, i64, i64, vp, i64, vp, i64, vp, i64, i32, vp, sz, vp]
         L.cfx_set_solve_spin_limit.argtypes = [vp, i32]
         for f in ("cfx_create", "cfx_destroy", "cfx_getrf_buffer_size", "cfx_getrf",
                   "cfx_tslu", "cfx_getrs", "cfx_getrs_check", "cfx_set_solve_spin_limit",
+                  "cfx_schur_update_buffer_size", "cfx_schur_update",
                   "cfx_gesv_ir_buffer_size", "cfx_gesv_ir",
                   "cfx_gesv_batched_buffer_size", "cfx_gesv_batched", "cfx_batched_tune",
                   "cfx_batched_tuning", "cfx_batched_set_tuning", "cfx_serve_create",
@@ -251,6 +254,27 @@ def getrs(LU, ipiv, B, stream=None, handle=None):
     _check("cfx_getrs", lib().cfx_getrs(h.h, n, nrhs, _ptr(LU), lda, _ptr(ipiv), _ptr(Bm), ldb,
                                         _stream(stream)))
     return B
+
+
+def schur_update(L21, U12, Cm, precision="fp64", max_workgroups=0, work=None, stream=None, handle=None):
+    """cfx_schur_update: Cm -= L21 U12 in place (Cm m x n, L21 m x K, U12 K x n,
+    row-major float64 CUDA tensors with unit column stride)."""
+    h = handle or default_handle()
+    ldl, ldu, ldc = _mat(L21, "L21"), _mat(U12, "U12"), _mat(Cm, "C")
+    m, K = L21.shape
+    n = U12.shape[1]
+    if U12.shape[0] != K or tuple(Cm.shape) != (m, n):
+        raise ValueError("shapes of L21, U12 and C do not match")
+    p = PREC[precision]
+    if work is None:
+        b = C.c_size_t()
+        _check("cfx_schur_update_buffer_size",
+               lib().cfx_schur_update_buffer_size(h.h, p, m, n, K, C.byref(b)))
+        work = torch.empty(max(b.value, 256), dtype=torch.uint8, device=Cm.device) if b.value else None
+    _check("cfx_schur_update", lib().cfx_schur_update(
+        h.h, p, m, n, K, _ptr(L21), ldl, _ptr(U12), ldu, _ptr(Cm), ldc, int(max_workgroups),
+        _ptr(work), 0 if work is None else work.numel(), _stream(stream)))
+    return Cm
 
 
 def getrs_check(stream=None, handle=None):

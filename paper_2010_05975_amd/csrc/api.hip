@@ -122,7 +122,7 @@ static Layout layout(int64_t n, int v, int leaves, int precision)
     L.off_utg = o;   o = align_up(o + (size_t)L.max_nodes * 32 * kMaxV * sizeof(double));
     L.off_rtg = o;   o = align_up(o + (size_t)L.max_nodes * 32 * 40 * sizeof(double));
     L.off_mp = o;
-    if (precision != CFX_PREC_FP64) o = align_up(o + lp_pack_bytes(n, v));
+    if (precision != CFX_PREC_FP64) o = align_up(o + lp_pack_bytes(precision, n, n, v));
     L.total = o;
     return L;
 }
@@ -162,7 +162,8 @@ static int check_opts(const cfx_lu_opts *o)
     if (!o) return 1;
     if (o->v < 1 || o->v > kMaxV) return 1;
     if (o->leaves < 1) return 1;
-    if (o->precision != CFX_PREC_FP64 && o->precision != CFX_PREC_BF16 && o->precision != CFX_PREC_FP16)
+    if (o->precision != CFX_PREC_FP64 && o->precision != CFX_PREC_BF16 && o->precision != CFX_PREC_FP16 &&
+        o->precision != CFX_PREC_FP8)
         return 2;
     if (o->lookahead < 0 || o->lookahead > 1) return 1;
     return 0;
@@ -221,7 +222,7 @@ static int schur_update(int precision, const Workspace &ws, const double *L21, c
 {
     if (precision == CFX_PREC_FP64)
         return launch_schur_f64(L21, lda, U12 + col0, lda, C + col0, lda, m, ncols, vb, max_wgs, st);
-    return launch_schur_lp(precision, ws.scratch, m, vb, col0, ncols, C, lda, max_wgs, st);
+    return launch_schur_lp(precision, ws.scratch, m, m, vb, col0, ncols, C, lda, max_wgs, st);
 }
 
 }  // namespace cfx
@@ -375,7 +376,7 @@ int cfx_getrf(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *ipiv, i
                 pf.end(PH_TRSM, e, st);
                 double *L21 = panel + vb * lda, *U12 = panel + vb, *C = panel + vb * lda + vb;
                 e = pf.begin(st);
-                if (prec != CFX_PREC_FP64 && (rc = launch_pack_lp(prec, L21, U12, lda, m, vb, ws.scratch, st)))
+                if (prec != CFX_PREC_FP64 && (rc = launch_pack_lp(prec, L21, lda, m, U12, lda, m, vb, ws.scratch, st)))
                     return rc;
                 if ((rc = schur_update(prec, ws, L21, U12, C, lda, m, 0, m, vb, 0, st))) return rc;
                 pf.end(PH_SCHUR, e, st, 2.0 * (double)m * (double)m * vb);
@@ -418,7 +419,7 @@ int cfx_getrf(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *ipiv, i
             pf.end(PH_TRSM, e, st);
             double *L21 = panel + vb * lda, *U12 = panel + vb, *C = panel + vb * lda + vb;
             e = pf.begin(st);
-            if (prec != CFX_PREC_FP64 && (rc = launch_pack_lp(prec, L21, U12, lda, m, vb, ws.scratch, st)))
+            if (prec != CFX_PREC_FP64 && (rc = launch_pack_lp(prec, L21, lda, m, U12, lda, m, vb, ws.scratch, st)))
                 return rc;
             if ((rc = schur_update(prec, ws, L21, U12, C, lda, m, 0, vbn, vb, 0, st))) return rc;
             pf.end(PH_SCHUR, e, st, 2.0 * (double)m * vbn * vb);
@@ -790,6 +791,47 @@ int cfx_getrs(cfx_handle *h, int64_t n, int64_t nrhs, const double *LU, int64_t 
     CFX_HIP(hipEventRecord(h->ev_getrs, st));
     h->getrs_issued = true;
     return CFX_OK;
+}
+
+int cfx_schur_update_buffer_size(cfx_handle *h, int32_t precision, int64_t m, int64_t n, int64_t K,
+                                 size_t *bytes)
+{
+    if (!h) return -1;
+    if (precision < CFX_PREC_FP64 || precision > CFX_PREC_FP8) return -2;
+    if (m < 0) return -3;
+    if (n < 0) return -4;
+    if (K < 0 || K > INT32_MAX / 2) return -5;
+    if (!bytes) return -6;
+    *bytes = precision == CFX_PREC_FP64 ? 0 : lp_pack_bytes(precision, m, n, (int)K);
+    return CFX_OK;
+}
+
+int cfx_schur_update(cfx_handle *h, int32_t precision, int64_t m, int64_t n, int64_t K, const double *L21,
+                     int64_t ldl, const double *U12, int64_t ldu, double *C, int64_t ldc, int32_t max_workgroups,
+                     void *work, size_t work_bytes, void *stream)
+{
+    if (!h) return -1;
+    if (precision < CFX_PREC_FP64 || precision > CFX_PREC_FP8) return -2;
+    if (m < 0 || m > INT32_MAX) return -3;
+    if (n < 0 || n > INT32_MAX) return -4;
+    if (K < 0 || K > INT32_MAX / 2) return -5;
+    const bool any = m > 0 && n > 0 && K > 0;
+    if (any && !L21) return -6;
+    if (ldl < (K > 1 ? K : 1)) return -7;
+    if (any && !U12) return -8;
+    if (ldu < (n > 1 ? n : 1)) return -9;
+    if (m > 0 && n > 0 && !C) return -10;
+    if (ldc < (n > 1 ? n : 1)) return -11;
+    if (max_workgroups < 0 || (max_workgroups > 0 && max_workgroups < 8)) return -12;
+    if (!any) return CFX_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (precision == CFX_PREC_FP64)
+        return launch_schur_f64(L21, ldl, U12, ldu, C, ldc, m, n, (int)K, max_workgroups, st);
+    if (!work || (reinterpret_cast<uintptr_t>(work) & 255)) return -13;
+    if (work_bytes < lp_pack_bytes(precision, m, n, (int)K)) return CFX_ENOMEM;
+    int rc = launch_pack_lp(precision, L21, ldl, m, U12, ldu, n, (int)K, work, st);
+    if (rc) return rc;
+    return launch_schur_lp(precision, work, m, n, (int)K, 0, n, C, ldc, max_workgroups, st);
 }
 
 int cfx_getrs_check(cfx_handle *h, void *stream)

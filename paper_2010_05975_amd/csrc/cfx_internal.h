@@ -109,15 +109,15 @@ int launch_schur_f64(const double *L, int64_t ldl, const double *U, int64_t ldu,
                      double *C, int64_t ldc, int64_t mr, int64_t nc, int K,
                      int max_wgs, hipStream_t st);
 
-// Mixed-precision FactorizeA11.  launch_pack_lp rounds L21 (m x K at L21)
-// and U12 (K x m at U12, both stride lda) to the working precision into
-// `buf` (lp_pack_bytes(m, K) bytes); launch_schur_lp then applies
-// C[0:m, col0:col0+ncols] -= L21 U12[:, col0:col0+ncols] from the packed
-// operands, FP32 accumulation, FP64 C.
-size_t lp_pack_bytes(int64_t m, int K);
-int launch_pack_lp(int precision, const double *L21, const double *U12, int64_t lda,
-                   int64_t m, int K, void *buf, hipStream_t st);
-int launch_schur_lp(int precision, const void *buf, int64_t m, int K, int64_t col0,
+// Mixed-precision FactorizeA11.  launch_pack_lp rounds L21 (m x K, stride
+// ldl) and U12 (K x n, stride ldu) to the working precision (FP8: after the
+// power-of-two row / column scaling) into `buf` (lp_pack_bytes bytes);
+// launch_schur_lp then applies C[0:m, col0:col0+ncols] -= L21 U12[:, col0:
+// col0+ncols] from the packed operands, FP32 accumulation, FP64 C.
+size_t lp_pack_bytes(int precision, int64_t m, int64_t n, int K);
+int launch_pack_lp(int precision, const double *L21, int64_t ldl, int64_t m, const double *U12,
+                   int64_t ldu, int64_t n, int K, void *buf, hipStream_t st);
+int launch_schur_lp(int precision, const void *buf, int64_t m, int64_t n, int K, int64_t col0,
                     int64_t ncols, double *C, int64_t ldc, int max_wgs, hipStream_t st);
 
 int launch_set_int(int32_t *p, int32_t value, hipStream_t st);

@@ -558,7 +558,8 @@ int cfx_serve_create(const cfx_serve_cfg *cfg, cfx_server **out)
         const cfx_ir_opts &o = cfg->ir;
         if (o.lu.v < 1 || o.lu.v > kMaxV || o.lu.leaves < 1 || o.lu.lookahead < 0 || o.lu.lookahead > 1)
             return -1;
-        if (o.lu.precision != CFX_PREC_FP64 && o.lu.precision != CFX_PREC_BF16 && o.lu.precision != CFX_PREC_FP16)
+        if (o.lu.precision != CFX_PREC_FP64 && o.lu.precision != CFX_PREC_BF16 && o.lu.precision != CFX_PREC_FP16 &&
+            o.lu.precision != CFX_PREC_FP8)
             return CFX_ENOTSUP;
         if (!(o.tol >= 0) || o.max_outer < 0 || o.gmres_restart < 1 || o.gmres_restart > 64 ||
             !(o.gmres_tol > 0 && o.gmres_tol < 1))

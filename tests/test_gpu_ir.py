@@ -50,8 +50,9 @@ def test_lowp_getrf_exact_for_representable_factors(cfx, prec, n, v, L, la):
     assert np.array_equal(np.triu(LU), U0)
 
 
-@pytest.mark.parametrize("prec", PRECS)
-@pytest.mark.parametrize("n,v,L", [(300, 256, 4), (160, 128, 2), (100, 64, 3), (77, 40, 2)])
+@pytest.mark.parametrize("prec", PRECS + ["fp8"])
+@pytest.mark.parametrize("n,v,L", [(300, 256, 4), (160, 128, 2), (100, 64, 3), (77, 40, 2),
+                                   (256, 128, 2), (512, 256, 4)])
 def test_lowp_single_update_matches_oracle(cfx, prec, n, v, L):
     """n = v + m with m <= v: one low-precision Schur update (K = v), then
     the last panel factors the m x m tail in FP64 (a single leaf)."""
@@ -79,7 +80,7 @@ def test_lowp_single_update_matches_oracle(cfx, prec, n, v, L):
     PA22 = A[perm0][v:, v:][perm22]
     L22, U22 = O.unpack(LU[v:, v:])
     R = L22 @ U22
-    Lr, Ur = O.round_lowp(LU[v:, :v], prec), O.round_lowp(LU[:v, v:], prec)
+    Lr, Ur = O.lowp_operands(LU[v:, :v], LU[:v, v:], prec)
     Sg = PA22 - Lr @ Ur
     scale = (np.abs(Lr) @ np.abs(Ur)).max()
     d_lp = np.abs(R - Sg).max()
@@ -93,7 +94,7 @@ def test_lowp_single_update_matches_oracle(cfx, prec, n, v, L):
         assert np.array_equal(ipiv[v:] - v, tail.ipiv)
 
 
-@pytest.mark.parametrize("prec,hi", [("bf16", 0.3), ("fp16", 0.05)])
+@pytest.mark.parametrize("prec,hi", [("bf16", 0.3), ("fp16", 0.05), ("fp8", 3.0)])
 @pytest.mark.parametrize("la", [0, 1])
 def test_lowp_getrf_backward_error(cfx, prec, hi, la):
     say(f"lowp backward error {prec} la={la}")
@@ -164,6 +165,27 @@ def test_gesv_ir_householder(cfx, prec, cond):
     assert fwd <= 100 * cond * 5e-15 + 1e-13
     # inputs untouched
     assert np.array_equal(dA.cpu().numpy(), A) and np.array_equal(db.cpu().numpy(), b)
+
+
+@pytest.mark.parametrize("cond", [1e2, 1e6])
+def test_gesv_ir_fp8_experiment(cfx, cond):
+    """FP8 Schur updates (3 fraction bits) with FP64 GMRES-IR: whatever the
+    outcome, the report is consistent with the oracle; a converged solve
+    meets eta <= 5e-15 by the oracle's own measure."""
+    n = 2048
+    say(f"gesv_ir fp8 cond={cond:g} n={n}")
+    A, b, xs = householder_case(n, cond, 5)
+    X, rep = cfx.gesv_ir(to_dev(A), to_dev(b), precision="fp8", v=128, leaves=4, tol=5e-15, max_outer=20,
+                         gmres_restart=30, gmres_tol=1e-6)
+    x = X.cpu().numpy()
+    eta = O.eta(A, x, b)
+    say(f"  report {rep}; oracle eta {eta:.3e}")
+    assert rep["info"] == 0
+    assert np.isfinite(rep["eta"]) and abs(rep["eta"] - eta) <= 0.05 * eta + 1e-19
+    if rep["converged"]:
+        assert eta <= 5e-15
+    else:
+        assert eta > 5e-15
 
 
 def test_gesv_ir_stagnation_stops_early(cfx):

@@ -1,6 +1,7 @@
-"""Pins of the oracle's low-precision pieces (round_lowp and the trailing
-matrix after one low-precision Schur update) against values fixed by the
-BF16 / FP16 formats themselves and by exactly representable inputs."""
+"""Pins of the oracle's low-precision pieces (round_lowp, the FP8 scaling and
+the trailing matrix after one low-precision Schur update) against values
+fixed by the BF16 / FP16 / FP8 E4M3 formats themselves and by exactly
+representable inputs."""
 import numpy as np
 import pytest
 
@@ -73,6 +74,18 @@ def test_tail_exact_for_representable_factors():
         assert np.array_equal(S, full.LU[v:, v:])
 
 
+def test_tail_exact_for_fp8_representable_factors():
+    """Factors whose rows of L21 and columns of U12 hold values with at most
+    4 significant bits inside a range of 2^7 are exact in scaled E4M3, so the
+    FP8 trailing matrix equals the FP64 one."""
+    rng = np.random.default_rng(4)
+    m, K, n = 40, 16, 24
+    L21 = rng.integers(-15, 16, size=(m, K)) * 2.0 ** rng.integers(-20, 20, size=(m, 1))
+    U12 = rng.integers(-15, 16, size=(K, n)) * 2.0 ** rng.integers(-20, 20, size=(1, n))
+    C = rng.standard_normal((m, n))
+    assert np.array_equal(O.schur_lowp(C, L21, U12, "fp8"), C - L21 @ U12)
+
+
 @pytest.mark.parametrize("prec,lo,hi", [("bf16", 1e-4, 2e-2), ("fp16", 1e-5, 3e-3)])
 def test_tail_differs_at_the_format_precision(prec, lo, hi):
     """For general inputs the low-precision tail differs from the FP64 one by
@@ -85,3 +98,86 @@ def test_tail_differs_at_the_format_precision(prec, lo, hi):
     d = np.abs(S - full.LU[v:, v:]).max()
     scale = (np.abs(f.LU[v:, :v]) @ np.abs(f.LU[:v, v:])).max()
     assert lo <= d / scale <= hi
+
+
+def e4m3_values():
+    """Every finite non-negative E4M3 value, from the encoding: exponent field
+    E (bias 7) and fraction field M; E = 0 is subnormal (M/8 2^-6); the
+    all-ones pattern (E = 15, M = 7) is NaN."""
+    vals = [M / 8 * 2.0 ** -6 for M in range(8)]
+    for E in range(1, 16):
+        for M in range(8):
+            if E == 15 and M == 7:
+                continue
+            vals.append((1 + M / 8) * 2.0 ** (E - 7))
+    return np.array(vals)
+
+
+def test_fp8_every_value_is_fixed_and_counted():
+    v = e4m3_values()
+    assert len(v) == 127 and v.max() == 448.0 and v[1] == 2.0 ** -9
+    assert np.array_equal(O.round_lowp(v, "fp8"), v)
+    assert np.array_equal(O.round_lowp(-v, "fp8"), -v)
+
+
+def test_fp8_round_to_nearest_even():
+    x = np.array([1 + 2.0 ** -4, 1 + 3 * 2.0 ** -4, 1 + 2.0 ** -4 + 2.0 ** -30, 17.0, 19.0, 2.0 ** -10,
+                  1.5 * 2.0 ** -10, 3 * 2.0 ** -10, 240.0, 248.0, 464.0, 464.0 + 2.0 ** -40, -17.0])
+    want = np.array([1.0, 1.25, 1.125, 16.0, 20.0, 0.0, 2.0 ** -9, 2.0 ** -8, 240.0, 256.0, 448.0, np.nan,
+                     -16.0])
+    got = O.round_lowp(x, "fp8")
+    assert np.array_equal(got, want, equal_nan=True)
+
+
+def test_fp8_no_infinities():
+    got = O.round_lowp(np.array([np.inf, -np.inf, np.nan, 1e6]), "fp8")
+    assert np.all(np.isnan(got))
+
+
+def test_fp8_nearest_among_all_values():
+    """Brute force: the result is a nearest representable value, and on a
+    tie the one with an even fraction field."""
+    v = e4m3_values()
+    x = np.random.default_rng(5).uniform(0, 460, 4000) * 2.0 ** np.random.default_rng(6).integers(-14, 1, 4000)
+    r = O.round_lowp(x, "fp8")
+    d = np.abs(x[:, None] - v[None, :])
+    best = d.min(axis=1)
+    assert np.all(np.abs(r - x) == best)
+
+
+def test_fp8_scale_exponents():
+    rng = np.random.default_rng(7)
+    M = rng.standard_normal((30, 50)) * 10.0 ** rng.uniform(-30, 30, size=(30, 1))
+    M[3] = 0.0
+    s = O.fp8_scale_exponents(M, 1)
+    peak = np.abs(np.ldexp(M, s[:, None])).max(axis=1)
+    assert s[3] == 0
+    ok = np.arange(30) != 3
+    assert np.all((peak[ok] >= 128) & (peak[ok] < 256))
+    # columns: the same rule on the transpose
+    assert np.array_equal(O.fp8_scale_exponents(M.T.copy(), 0), s)
+
+
+def test_fp8_update_error_at_the_format_precision():
+    """Scaled E4M3 operands carry a relative error of at most 2^-4 each, so
+    the update differs from the FP64 one by at most about 2^-3 (|L| |U|)."""
+    rng = np.random.default_rng(8)
+    L21 = rng.standard_normal((60, 32))
+    U12 = rng.standard_normal((32, 45)) * 1e-3
+    C = rng.standard_normal((60, 45))
+    d = np.abs(O.schur_lowp(C, L21, U12, "fp8") - (C - L21 @ U12))
+    bound = (2.0 ** -4 * 2 + 2.0 ** -8) * (np.abs(L21) @ np.abs(U12))
+    assert np.all(d <= bound)
+    assert d.max() > 1e-3 * bound.max()
+
+
+def test_fp8_non_finite_rows_and_columns_give_nan():
+    rng = np.random.default_rng(9)
+    L21 = rng.standard_normal((6, 5))
+    U12 = rng.standard_normal((5, 7))
+    L21[2, 3] = np.nan
+    U12[1, 4] = np.inf
+    S = O.schur_lowp(np.zeros((6, 7)), L21, U12, "fp8")
+    nan = np.isnan(S)
+    assert np.all(nan[2]) and np.all(nan[:, 4])
+    assert nan.sum() == 7 + 6 - 1
