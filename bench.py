@@ -33,6 +33,25 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def hbm_report(n, v, L, launches):
+    """Measured HBM bytes of the Schur launches (committed counter runs,
+    per launch times the launches of one factorisation) against the
+    Sec. 6 lower bound with P and M set for the XCD level and the compute
+    unit level of the MI355X."""
+    per = committed_traffic(n, v, L, launches=launches)
+    xcd = lu_io_lower_bound_bytes(n, M_XCD)
+    cu = lu_io_lower_bound_bytes(n, M_CU)
+    out = {"bound_xcd_level_gb": round(xcd / 1e9, 2), "M_xcd_elements": M_XCD, "P_xcd": 8,
+           "bound_cu_level_gb": round(cu / 1e9, 2), "M_cu_elements": M_CU, "P_cu": 256,
+           "right_looking_c_traffic_gb": round(16.0 * sum((n - k - min(v, n - k)) ** 2
+                                                          for k in range(0, n, v)) / 1e9, 2)}
+    if per is not None:
+        tot = per * launches
+        out.update({"schur_measured_gb": round(tot / 1e9, 2),
+                    "ratio_to_xcd_bound": round(tot / xcd, 3), "ratio_to_cu_bound": round(tot / cu, 3)})
+    return out
+
+
 def lu_flops_of_columns(n, k0, k1):
     """Exact LU flops of eliminating columns k0..k1-1: for column j,
     (n-j-1) divisions and 2 (n-j-1)^2 for the multiply-subtracts."""
@@ -41,12 +60,13 @@ def lu_flops_of_columns(n, k0, k1):
     return float(np.sum(2.0 * r * r + r))
 
 
-def committed_traffic(n, v, L, field="traffic_bytes_per_launch"):
+def committed_traffic(n, v, L, field="traffic_bytes_per_launch", launches=None):
     """HBM bytes per launch of the FP64 Schur kernel from the committed
-    rocprofv3 PMC summary of this workload (FETCH_SIZE and WRITE_SIZE runs,
-    calibrated by a plain copy; `read_bytes_per_launch` alone when only the
-    FETCH_SIZE run exists), or None if there is none or the kernel's source
-    changed since the counters were taken."""
+    rocprofv3 PMC summary of this workload (FETCH_SIZE and WRITE_SIZE runs
+    on the Schur-only replay of the factorisation's launches, each counter
+    calibrated by a plain copy), or None if there is none, the kernel's
+    source changed since the counters were taken, or the factorisation now
+    issues a different number of Schur launches."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"schur_f64_kernel_traffic_n{n}_v{v}_L{L}.md")
     if not os.path.exists(path):
@@ -56,13 +76,65 @@ def committed_traffic(n, v, L, field="traffic_bytes_per_launch"):
         if ":" in line and not line.startswith(("|", "#", "`")):
             key, _, val = line.partition(":")
             fields[key.strip()] = val.split()[0] if val.split() else ""
-    # the kernel and the host loop that shapes its launches
-    h = hashlib.sha256()
-    for name in ("schur_f64.hip", "api.hip"):
-        h.update(open(os.path.join(ROOT, "paper_2010_05975_amd", "csrc", name), "rb").read())
+    h = hashlib.sha256(open(os.path.join(ROOT, "paper_2010_05975_amd", "csrc", "schur_f64.hip"), "rb").read())
     if fields.get("kernel_source_sha256_16") != h.hexdigest()[:16] or field not in fields:
         return None
+    if launches is not None and fields.get("launches") != str(launches):
+        return None
     return float(fields[field])
+
+
+# Fast memory of one processor at the two levels of the MI355X hierarchy
+# (FP64 elements): an XCD (4 MiB L2 + 32 compute units x (160 KiB LDS +
+# 512 KiB registers)) and a compute unit (LDS + registers).
+M_XCD = (4 * 2**20 + 32 * (160 + 512) * 2**10) // 8
+M_CU = ((160 + 512) * 2**10) // 8
+
+
+def lu_io_lower_bound_bytes(n, M):
+    """The parallel I/O lower bound of LU (Sec. 6), summed over the P
+    processors of one level: P Q_{P,LU} >= (2N^3 - 6N^2 + 4N) / (3 sqrt(M))
+    + N (N - 1) / 2 elements, 8 bytes each (P cancels)."""
+    return 8.0 * ((2.0 * n ** 3 - 6.0 * n ** 2 + 4.0 * n) / (3.0 * np.sqrt(M)) + n * (n - 1) / 2.0)
+
+
+def schur_replay(cfx, torch, n, v, chunk, seed):
+    """Only the Schur-complement launches of one lookahead factorisation at
+    (n, v), in the library's order and shapes, on one stream: for each panel
+    k, C = A[k+vb:, k+vb:] is updated from L21 = P[k+vb:, k:k+vb] and
+    U12 = P[k:k+vb, k+vb:] (the strides and offsets of the factorisation;
+    P is a second matrix that stays unchanged), first the next panel's
+    columns, then the rest in `chunk`-column launches.  No tournament
+    kernels run, so a counter run sees these launches alone.  Returns
+    (launches, algorithmic flops, seconds)."""
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    A = torch.randn(n, n, dtype=torch.float64, device=dev, generator=g)
+    P = torch.randn(n, n, dtype=torch.float64, device=dev, generator=g) / 16.0
+    stream = torch.cuda.current_stream()
+    launches, flops = 0, 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(0, n, v):
+        vb = min(v, n - k)
+        m = n - k - vb
+        if m <= 0:
+            break
+        vbn = min(v, m)
+        L21 = P[k + vb:, k:k + vb]
+        U12 = P[k:k + vb, k + vb:]
+        C = A[k + vb:, k + vb:]
+        cols = [(0, vbn)] + [(c0, min(chunk, m - c0)) for c0 in range(vbn, m, chunk)]
+        for c0, cw in cols:
+            cfx.schur_update(L21, U12[:, c0:c0 + cw], C[:, c0:c0 + cw], stream=stream)
+            launches += 1
+            flops += 2.0 * m * cw * vb
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    del A, P
+    torch.cuda.empty_cache()
+    return launches, flops, dt
 
 
 def cpu_baseline(A_host, n, v, L, panels):
@@ -80,10 +152,52 @@ def cpu_baseline(A_host, n, v, L, panels):
                       f"solves, Schur update); flops = LU flops of those columns"}
 
 
+def masked_leg(cfx, torch, pristine, A_swapped, ipiv, n, v, L, lookahead, work, stream, reps=2):
+    """cfx_getrf_masked (row masking, Sec. 7.3) on the same matrix and
+    options as the timed steps: time per factorisation (HIP events, median
+    of `reps` after one warm-up), the row-map phase against the interchange
+    phase (the library's per-phase events), and whether the masked factors
+    read through the row map equal the interchanged ones bit for bit."""
+    dev = pristine.device
+    M = torch.empty_like(pristine)
+    rowmap = torch.empty(n, dtype=torch.int32, device=dev)
+    ipm = torch.empty(n, dtype=torch.int32, device=dev)
+    info = torch.empty(1, dtype=torch.int32, device=dev)
+    times = []
+    for it in range(reps + 1):
+        M.copy_(pristine)
+        torch.cuda.synchronize()
+        if it == reps:
+            cfx.profile_begin()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        cfx.getrf_masked(M, v=v, leaves=L, lookahead=lookahead, work=work, ipiv=ipm, rowmap=rowmap, info=info,
+                         stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if it:
+            times.append(e0.elapsed_time(e1))
+    prof = cfx.profile_end()
+    equal = bool(torch.equal(ipm, ipiv))
+    rm = rowmap.long()
+    for r0 in range(0, n, 4096):
+        r1 = min(n, r0 + 4096)
+        equal = equal and bool(torch.equal(M[rm[r0:r1]], A_swapped[r0:r1]))
+    ms = float(np.median(times))
+    out = {"getrf_ms": round(ms, 3), "getrf_tflops": round(2.0 * n ** 3 / 3.0 / (ms / 1e3) / 1e12, 3),
+           "rowmap_phase_ms": round(prof["laswp_ms"], 3),
+           "interchange_bytes_bound_gb": round(sum(2 * 2 * min(v, n - k) * n * 8 for k in range(0, n, v)) / 1e9, 2),
+           "bitwise_equal_to_interchanged": equal}
+    log(f"row masking: {out}")
+    del M
+    torch.cuda.empty_cache()
+    return out
+
+
 def ir_leg(cfx, G, torch, n, v, L, conds, precs, seed, check_oracle):
     """Time-to-solution on A = H1 diag(s) H2 (8 seeded reflectors each side,
     s log-spaced to cond), 1 RHS: plain FP64 getrf + getrs, FP64 factors +
-    GMRES-IR, and BF16 / FP16 Schur updates + GMRES-IR, all to eta <= 5e-15
+    GMRES-IR, and BF16 / FP16 / FP8 Schur updates + GMRES-IR, all to eta <= 5e-15
     (the refinement stops there; the plain solve's eta is reported)."""
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
@@ -318,6 +432,7 @@ def main():
     ap.add_argument("--one-stream", action="store_true",
                     help="issue the lookahead schedule on one stream (for PMC counter runs)")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-masked", action="store_true", help="skip the row-masking leg")
     ap.add_argument("--cpu-panels", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ir", action="store_true", help="skip the mixed-precision IR leg")
@@ -334,8 +449,11 @@ def main():
                          "used for the counter runs (no CPU baseline then)")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="end with a plain 1 GiB device copy (calibrates HBM byte counters)")
+    ap.add_argument("--schur-replay", action="store_true",
+                    help="run only the Schur-complement launches of one factorisation (one stream) "
+                         "and print their statistics; for counter runs")
     ap.add_argument("--ir-conds", default="1e2,1e6,1e10")
-    ap.add_argument("--ir-precs", default="bf16,fp16")
+    ap.add_argument("--ir-precs", default="bf16,fp16,fp8")
     ap.add_argument("--ir-oracle-check", action="store_true",
                     help="also evaluate eta of each IR result with the CPU oracle")
     args = ap.parse_args()
@@ -353,6 +471,19 @@ def main():
 
     n, v, L = args.n, args.v, args.leaves
     dev = torch.device("cuda:0")
+    if args.schur_replay:
+        chunk = args.chunk or cfx.overlap_tuning()[1]
+        launches, flops, dt = schur_replay(cfx, torch, n, v, chunk, args.seed)
+        out = {"schur_replay": {"n": n, "v": v, "chunk": chunk, "launches": launches, "flops": flops,
+                                "seconds": round(dt, 4), "tflops": round(flops / dt / 1e12, 3)}}
+        if args.calibration_copy:
+            src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+            dst = torch.empty_like(src)
+            torch.cuda.synchronize()
+            dst.copy_(src)
+            torch.cuda.synchronize()
+        print(json.dumps(out), flush=True)
+        return
     if args.device_gen:
         log(f"generating A ({n}x{n}, N(0,1), device generator seed {args.seed})")
         gen = torch.Generator(device=dev)
@@ -410,21 +541,17 @@ def main():
     ms = getrf_ms + getrs_ms
     log(f"timed {args.steps} steps: getrf {getrf_ms:.2f} ms, getrs {getrs_ms:.2f} ms")
 
-    # correctness of the last step, O(N^2): backward error of the solve and a
-    # random-projection check of P A = L U.
+    # correctness of the last step (outside the timed region): backward error
+    # of the solve and ||P A - L U||_F / ||A||_F, the products formed by
+    # torch's own FP64 matrix products (none of the library's kernels)
     with torch.no_grad():
         x = B[:, 0]
         r = pb[:, 0] - pristine @ x
         anorm = pristine.abs().sum(dim=1).max()
         eta = float(r.abs().max() / (anorm * x.abs().max() + pb.abs().max()))
-        z = torch.randn(n, dtype=torch.float64, device=dev, generator=torch.Generator(dev).manual_seed(1))
-        Uz = torch.triu(A) @ z  # n^2 work, fine at this size
-        LUz = torch.tril(A, -1) @ Uz + Uz
-        perm = torch.from_numpy(_perm_of(ipiv.cpu().numpy())).to(dev)
-        PAz = (pristine @ z)[perm]
-        proj = float((PAz - LUz).norm() / (anorm * z.norm()))
+        frob = frob_residual(torch, pristine, A, _perm_of(ipiv.cpu().numpy()))
         info_v = int(info.cpu()[0])
-    log(f"eta {eta:.3e}, projected residual {proj:.3e}, info {info_v}")
+    log(f"eta {eta:.3e}, ||PA-LU||_F/||A||_F {frob:.3e}, info {info_v}")
 
     # the 64-right-hand-side solve with the same factors (outside the timed
     # steps): median of 3 launches, HIP events on the library's stream
@@ -441,6 +568,10 @@ def main():
     getrs64_ms = sorted(t64)[1]
     del B64, Bw
     log(f"getrs with 64 right-hand sides: {getrs64_ms:.2f} ms")
+
+    masked = None
+    if not args.no_masked:
+        masked = masked_leg(cfx, torch, pristine, A, ipiv, n, v, L, args.lookahead, work, stream)
 
     flops = 2.0 * n ** 3 / 3.0 + 2.0 * n * n
     value = flops / (ms / 1e3) / 1e12
@@ -475,12 +606,17 @@ def main():
         "roofline": {"bound": "mfma", "kernel": "schur_f64_kernel",
                      "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-                     "traffic": committed_traffic(n, v, L),
-                     "hbm_read_bytes_per_launch": committed_traffic(n, v, L, "read_bytes_per_launch"),
+                     "traffic": committed_traffic(n, v, L, launches=launches),
+                     "hbm_read_bytes_per_launch": committed_traffic(n, v, L, "read_bytes_per_launch", launches),
+                     "hbm_write_bytes_per_launch": committed_traffic(n, v, L, "write_bytes_per_launch",
+                                                                     launches),
                      "avg_launch_ms": round(schur_avg_ms, 4),
                      "avg_launch_flops": schur_avg_flops},
-        "checks": {"eta": eta, "projected_residual": proj, "info": info_v},
+        "hbm_vs_lower_bound": hbm_report(n, v, L, launches),
+        "checks": {"eta": eta, "frob_residual": frob, "info": info_v},
     }
+    if masked is not None:
+        out["row_masking"] = masked
     del pristine, A, work
     torch.cuda.empty_cache()
     if not args.no_ir:
@@ -502,6 +638,24 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A_host, n, v, L, args.cpu_panels)
     print(json.dumps(out), flush=True)
+
+
+def frob_residual(torch, A0, LU, perm, block=2048):
+    """||P A - L U||_F / ||A||_F on the device, block row by block row."""
+    n = A0.shape[0]
+    dperm = torch.from_numpy(np.ascontiguousarray(perm, dtype=np.int64)).to(A0.device)
+    U = torch.triu(LU)
+    num = torch.zeros((), dtype=torch.float64, device=A0.device)
+    for r0 in range(0, n, block):
+        r1 = min(n, r0 + block)
+        Lb = torch.tril(LU[r0:r1, :r1], diagonal=r0 - 1)
+        idx = torch.arange(r1 - r0, device=A0.device)
+        Lb[idx, idx + r0] = 1.0
+        D = A0[dperm[r0:r1]] - Lb @ U[:r1]
+        num += (D * D).sum()
+        del Lb, D
+    del U
+    return float(torch.sqrt(num) / torch.linalg.norm(A0))
 
 
 def _perm_of(ipiv):

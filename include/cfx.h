@@ -139,6 +139,23 @@ int cfx_getrf(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *ipiv,
               int32_t *info, const cfx_lu_opts *opts, void *work,
               size_t work_bytes, void *stream);
 
+/* The same factorisation with row masking instead of row interchanges
+ * (Sec. 7.3, "Row Swapping vs. Row Masking"): the pivots are chosen
+ * exactly as by cfx_getrf (the same ipiv, the same arithmetic), but no row
+ * of A is moved; the library keeps, and returns, the row map
+ *   rowmap : device int32[n]: row i of the factors L\U (in the order of
+ *            cfx_getrf's output, i.e. of P A) is stored in physical row
+ *            rowmap[i] of A; equivalently (P A)[i, :] = A_input[rowmap[i], :].
+ * So A[rowmap, :] after this call equals, bit for bit, the A of cfx_getrf
+ * on the same input and options.  Every kernel reaches rows through the
+ * map (gather on read) instead of the interchange kernel moving 2 vb rows
+ * of n columns per panel.  Arguments otherwise as cfx_getrf (rowmap is
+ * argument 6; info 7, opts 8, work 9). */
+int cfx_getrf_masked(cfx_handle *h, int64_t n, double *A, int64_t lda,
+                     int32_t *ipiv, int32_t *rowmap, int32_t *info,
+                     const cfx_lu_opts *opts, void *work, size_t work_bytes,
+                     void *stream);
+
 /* Tournament pivot selection of one panel (Sec. 7.3; Sec. 7.4 Step 1): the
  * panel is W = rows x vb at device pointer W with stride ldw; row i of W is
  * global row row0 + i.  Writes the vb selected global rows, in selection
@@ -184,6 +201,14 @@ int cfx_schur_update(cfx_handle *h, int32_t precision, int64_t m, int64_t n,
 int cfx_getrs(cfx_handle *h, int64_t n, int64_t nrhs, const double *LU,
               int64_t lda, const int32_t *ipiv, double *B, int64_t ldb,
               void *stream);
+/* cfx_getrs for the factors of cfx_getrf_masked: factor row i is physical
+ * row rowmap[i] of LU, and rowmap is also the permutation of P B (so no
+ * ipiv is needed).  Same results as cfx_getrs on the interchanged factors;
+ * scratch, ordering and errors as cfx_getrs. */
+int cfx_getrs_masked(cfx_handle *h, int64_t n, int64_t nrhs, const double *LU,
+                     int64_t lda, const int32_t *rowmap, double *B, int64_t ldb,
+                     void *stream);
+
 /* Scratch and ordering of cfx_getrs: the permutation and the gathered
  * right-hand sides live in a device buffer owned by the handle, grown with
  * hipMalloc when a call needs more (hipFree of the old one waits for the

@@ -124,11 +124,14 @@ def lib():
         L.cfx_profile_begin.argtypes = [vp]
         L.cfx_profile_end.argtypes = [vp, C.POINTER(Profile)]
         L.cfx_getrs_check.argtypes = [vp, vp]
+        L.cfx_getrf_masked.argtypes = [vp, i64, vp, i64, vp, vp, vp, C.POINTER(LuOpts), vp, sz, vp]
+        L.cfx_getrs_masked.argtypes = [vp, i64, i64, vp, i64, vp, vp, i64, vp]
         L.cfx_schur_update_buffer_size.argtypes = [vp, i32, i64, i64, i64, C.POINTER(sz)]
         L.cfx_schur_update.argtypes = [vp, i32, i64, i64, i64, vp, i64, vp, i64, vp, i64, i32, vp, sz, vp]
         L.cfx_set_solve_spin_limit.argtypes = [vp, i32]
         for f in ("cfx_create", "cfx_destroy", "cfx_getrf_buffer_size", "cfx_getrf",
                   "cfx_tslu", "cfx_getrs", "cfx_getrs_check", "cfx_set_solve_spin_limit",
+                  "cfx_getrf_masked", "cfx_getrs_masked",
                   "cfx_schur_update_buffer_size", "cfx_schur_update",
                   "cfx_gesv_ir_buffer_size", "cfx_gesv_ir",
                   "cfx_gesv_batched_buffer_size", "cfx_gesv_batched", "cfx_batched_tune",
@@ -228,6 +231,41 @@ def getrf(A, v=256, leaves=64, precision="fp64", lookahead=0, work=None, ipiv=No
     _check("cfx_getrf", lib().cfx_getrf(h.h, n, _ptr(A), lda, _ptr(ipiv), _ptr(info), C.byref(o),
                                         _ptr(work), work.numel(), _stream(stream)))
     return ipiv[:n], info
+
+
+def getrf_masked(A, v=256, leaves=64, precision="fp64", lookahead=0, work=None, ipiv=None, rowmap=None,
+                 info=None, stream=None, handle=None):
+    """cfx_getrf_masked: factor A in place without moving rows; returns
+    (ipiv, rowmap, info) (int32 device tensors)."""
+    h = handle or default_handle()
+    lda = _mat(A, "A")
+    n = A.shape[0]
+    if A.shape[1] != n:
+        raise ValueError("A must be square")
+    if ipiv is None:
+        ipiv = torch.empty(max(n, 1), dtype=torch.int32, device=A.device)
+    if rowmap is None:
+        rowmap = torch.empty(max(n, 1), dtype=torch.int32, device=A.device)
+    if info is None:
+        info = torch.empty(1, dtype=torch.int32, device=A.device)
+    if work is None:
+        work = workspace(n, v, leaves, precision, lookahead, A.device, h)
+    o = LuOpts(v, leaves, PREC[precision], lookahead)
+    _check("cfx_getrf_masked", lib().cfx_getrf_masked(h.h, n, _ptr(A), lda, _ptr(ipiv), _ptr(rowmap), _ptr(info),
+                                                      C.byref(o), _ptr(work), work.numel(), _stream(stream)))
+    return ipiv, rowmap, info
+
+
+def getrs_masked(LU, rowmap, B, stream=None, handle=None):
+    """cfx_getrs_masked: solve in place in B with the factors of getrf_masked."""
+    h = handle or default_handle()
+    lda = _mat(LU, "LU")
+    Bm = B.view(-1, 1) if B.dim() == 1 else B
+    ldb = _mat(Bm, "B")
+    n, nrhs = Bm.shape
+    _check("cfx_getrs_masked", lib().cfx_getrs_masked(h.h, n, nrhs, _ptr(LU), lda, _ptr(rowmap), _ptr(Bm), ldb,
+                                                      _stream(stream)))
+    return B
 
 
 def tslu(W, vb, leaves, row0=0, work=None, stream=None, handle=None):

@@ -214,17 +214,6 @@ static IrLayout ir_layout(int64_t n, const cfx_ir_opts *o)
     return L;
 }
 
-// FactorizeA11 on C[0:m, col0:col0+ncols] of the trailing matrix.  In the
-// mixed-precision path the operands were packed once for the panel.
-static int schur_update(int precision, const Workspace &ws, const double *L21, const double *U12,
-                        double *C, int64_t lda, int64_t m, int64_t col0, int64_t ncols, int vb,
-                        int max_wgs, hipStream_t st)
-{
-    if (precision == CFX_PREC_FP64)
-        return launch_schur_f64(L21, lda, U12 + col0, lda, C + col0, lda, m, ncols, vb, max_wgs, st);
-    return launch_schur_lp(precision, ws.scratch, m, m, vb, col0, ncols, C, lda, max_wgs, st);
-}
-
 }  // namespace cfx
 
 using namespace cfx;
@@ -332,19 +321,16 @@ int cfx_getrf_buffer_size(cfx_handle *h, int64_t n, const cfx_lu_opts *opts, siz
     return CFX_OK;
 }
 
-int cfx_getrf(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *ipiv, int32_t *info,
-              const cfx_lu_opts *opts, void *work, size_t work_bytes, void *stream)
+}  // extern "C"
+
+namespace cfx {
+
+// The host loop of Alg. 1 shared by cfx_getrf (rm null: rows interchanged)
+// and cfx_getrf_masked (rm: the row map, rows never moved).  Arguments are
+// checked by the callers.
+static int getrf_run(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *ipiv, int32_t *rm,
+                     int32_t *info, const cfx_lu_opts *opts, void *work, size_t work_bytes, hipStream_t st)
 {
-    if (!h) return -1;
-    if (n < 0 || n > INT32_MAX) return -2;
-    if (!A && n > 0) return -3;
-    if (lda < (n > 1 ? n : 1)) return -4;
-    if (!ipiv && n > 0) return -5;
-    if (!info) return -6;
-    if (int c = check_opts(opts)) return c == 2 ? CFX_ENOTSUP : -7;
-    if (!work && n > 0) return -8;
-    if (reinterpret_cast<uintptr_t>(work) & 255) return -8;
-    hipStream_t st = static_cast<hipStream_t>(stream);
     int rc = launch_set_int(info, 0, st);
     if (rc || n == 0) return rc;
 
@@ -356,6 +342,37 @@ int cfx_getrf(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *ipiv, i
     }
     Workspace ws;
     if ((rc = carve_workspace(work, work_bytes, n, v, L, opts->precision, &ws))) return rc;
+    if (rm && (rc = launch_rowmap_init(rm, n, st))) return rc;
+
+    // Per panel k: the tournament's panel (W, row0 = k; with a row map W
+    // points at row 0 of column k), the interchanges (or the row-map update),
+    // and the blocks of the Schur update: L21 / C rows k+vb.., U12 rows
+    // k..k+vb; with a row map the blocks point at row 0 of their columns and
+    // their rows go through the map.
+    auto panel_w = [&](int64_t k) -> double * { return rm ? A + k : A + k * lda + k; };
+    auto swap = [&](int64_t k, int vb, hipStream_t s) -> int {
+        return rm ? launch_rowmap_apply(A, lda, rm, k, vb, ws, s) : launch_laswp(A, lda, n, k, vb, ws, s);
+    };
+    struct Blocks {
+        double *L21, *U12, *C;
+        const int32_t *rmap, *umap;
+    };
+    auto blocks = [&](int64_t k, int vb) -> Blocks {
+        if (rm) return {A + k, A + k + vb, A + k + vb, rm + k + vb, rm + k};
+        double *panel = A + k * lda + k;
+        return {panel + vb * lda, panel + vb, panel + vb * lda + vb, nullptr, nullptr};
+    };
+    auto schur = [&](const Blocks &b, int64_t m, int64_t col0, int64_t ncols, int vb, int max_wgs,
+                     hipStream_t s) -> int {
+        if (opts->precision == CFX_PREC_FP64)
+            return launch_schur_f64(b.L21, lda, b.U12 + col0, lda, b.C + col0, lda, m, ncols, vb, max_wgs, s,
+                                    b.rmap, b.umap);
+        return launch_schur_lp(opts->precision, ws.scratch, m, m, vb, col0, ncols, b.C, lda, max_wgs, s, b.rmap);
+    };
+    auto pack = [&](const Blocks &b, int64_t m, int vb, hipStream_t s) -> int {
+        if (opts->precision == CFX_PREC_FP64) return CFX_OK;
+        return launch_pack_lp(opts->precision, b.L21, lda, m, b.U12, lda, m, vb, ws.scratch, s, b.rmap, b.umap);
+    };
 
     Profiler &pf = h->prof;
     const int prec = opts->precision;
@@ -363,22 +380,20 @@ int cfx_getrf(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *ipiv, i
         for (int64_t k = 0; k < n; k += v) {
             const int vb = (int)((n - k) < v ? (n - k) : v);
             const int64_t m = n - k - vb;
-            double *panel = A + k * lda + k;
             hipEvent_t e = pf.begin(st);
-            if ((rc = launch_tslu(panel, lda, k, n - k, vb, L, ws, nullptr, ipiv, info, st))) return rc;
+            if ((rc = launch_tslu(panel_w(k), lda, k, n - k, vb, L, ws, nullptr, ipiv, info, st, rm))) return rc;
             pf.end(PH_TSLU, e, st);
             e = pf.begin(st);
-            if ((rc = launch_laswp(A, lda, n, k, vb, ws, st))) return rc;
+            if ((rc = swap(k, vb, st))) return rc;
             pf.end(PH_LASWP, e, st);
             if (m > 0) {
                 e = pf.begin(st);
-                if ((rc = launch_trsm(A, lda, k, vb, m, st))) return rc;
+                if ((rc = launch_trsm(A, lda, k, vb, m, st, rm))) return rc;
                 pf.end(PH_TRSM, e, st);
-                double *L21 = panel + vb * lda, *U12 = panel + vb, *C = panel + vb * lda + vb;
+                const Blocks b = blocks(k, vb);
                 e = pf.begin(st);
-                if (prec != CFX_PREC_FP64 && (rc = launch_pack_lp(prec, L21, lda, m, U12, lda, m, vb, ws.scratch, st)))
-                    return rc;
-                if ((rc = schur_update(prec, ws, L21, U12, C, lda, m, 0, m, vb, 0, st))) return rc;
+                if ((rc = pack(b, m, vb, st))) return rc;
+                if ((rc = schur(b, m, 0, m, vb, 0, st))) return rc;
                 pf.end(PH_SCHUR, e, st, 2.0 * (double)m * (double)m * vb);
             }
             if (pf.on) ++pf.panels;
@@ -395,18 +410,17 @@ int cfx_getrf(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *ipiv, i
     {
         const int vb0 = (int)(n < v ? n : v);
         hipEvent_t e = pf.begin(st);
-        if ((rc = launch_tslu(A, lda, 0, n, vb0, L, ws, nullptr, ipiv, info, st))) return rc;
+        if ((rc = launch_tslu(panel_w(0), lda, 0, n, vb0, L, ws, nullptr, ipiv, info, st, rm))) return rc;
         pf.end(PH_TSLU, e, st);
     }
     bool tslu_on_side = false;
     for (int64_t k = 0; k < n; k += v) {
         const int vb = (int)((n - k) < v ? (n - k) : v);
         const int64_t m = n - k - vb;
-        double *panel = A + k * lda + k;
         if (tslu_on_side) CFX_HIP(hipStreamWaitEvent(st, h->ev_tslu, 0));
         tslu_on_side = false;
         hipEvent_t e = pf.begin(st);
-        if ((rc = launch_laswp(A, lda, n, k, vb, ws, st))) return rc;
+        if ((rc = swap(k, vb, st))) return rc;
         pf.end(PH_LASWP, e, st);
         if (m > 0) {
             const int vbn = (int)(m < v ? m : v);          // next panel width
@@ -415,13 +429,12 @@ int cfx_getrf(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *ipiv, i
             // started; the low-precision pack needs all of U12 at once
             const int64_t n1 = prec == CFX_PREC_FP64 ? vbn : m;
             e = pf.begin(st);
-            if ((rc = launch_trsm_first(A, lda, k, vb, m, n1, st))) return rc;
+            if ((rc = launch_trsm_first(A, lda, k, vb, m, n1, st, rm))) return rc;
             pf.end(PH_TRSM, e, st);
-            double *L21 = panel + vb * lda, *U12 = panel + vb, *C = panel + vb * lda + vb;
+            const Blocks b = blocks(k, vb);
             e = pf.begin(st);
-            if (prec != CFX_PREC_FP64 && (rc = launch_pack_lp(prec, L21, lda, m, U12, lda, m, vb, ws.scratch, st)))
-                return rc;
-            if ((rc = schur_update(prec, ws, L21, U12, C, lda, m, 0, vbn, vb, 0, st))) return rc;
+            if ((rc = pack(b, m, vb, st))) return rc;
+            if ((rc = schur(b, m, 0, vbn, vb, 0, st))) return rc;
             pf.end(PH_SCHUR, e, st, 2.0 * (double)m * vbn * vb);
             // next panel's tournament on the side stream
             hipStream_t ts = side, us = st;
@@ -429,14 +442,14 @@ int cfx_getrf(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *ipiv, i
             CFX_HIP(hipStreamWaitEvent(ts, h->ev_panel, 0));
             const int64_t kn = k + vb;
             e = pf.begin(ts);
-            if ((rc = launch_tslu(A + kn * lda + kn, lda, kn, n - kn, vbn, L, ws, nullptr, ipiv, info, ts)))
+            if ((rc = launch_tslu(panel_w(kn), lda, kn, n - kn, vbn, L, ws, nullptr, ipiv, info, ts, rm)))
                 return rc;
             pf.end(PH_TSLU, e, ts);
             CFX_HIP(hipEventRecord(h->ev_tslu, ts));
             tslu_on_side = true;
             if (n1 < m) {
                 e = pf.begin(us);
-                if ((rc = launch_trsm_rest(A, lda, k, vb, m, n1, us))) return rc;
+                if ((rc = launch_trsm_rest(A, lda, k, vb, m, n1, us, rm))) return rc;
                 pf.end(PH_TRSM, e, us);
             }
             // the rest of the update, in column chunks: between two chunks
@@ -451,7 +464,7 @@ int cfx_getrf(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *ipiv, i
                 int nl = 0;
                 for (int64_t c0 = vbn; c0 < m; c0 += chunk, ++nl) {
                     const int64_t cw = (m - c0) < chunk ? (m - c0) : chunk;
-                    if ((rc = schur_update(prec, ws, L21, U12, C, lda, m, c0, cw, vb, wgs, us))) return rc;
+                    if ((rc = schur(b, m, c0, cw, vb, wgs, us))) return rc;
                 }
                 pf.end(PH_SCHUR, e, us, 2.0 * (double)m * (double)(m - vbn) * vb, nl);
             }
@@ -461,6 +474,41 @@ int cfx_getrf(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *ipiv, i
     }
     if (tslu_on_side) CFX_HIP(hipStreamWaitEvent(st, h->ev_tslu, 0));
     return CFX_OK;
+}
+
+}  // namespace cfx
+
+extern "C" {
+
+int cfx_getrf(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *ipiv, int32_t *info,
+              const cfx_lu_opts *opts, void *work, size_t work_bytes, void *stream)
+{
+    if (!h) return -1;
+    if (n < 0 || n > INT32_MAX) return -2;
+    if (!A && n > 0) return -3;
+    if (lda < (n > 1 ? n : 1)) return -4;
+    if (!ipiv && n > 0) return -5;
+    if (!info) return -6;
+    if (int c = check_opts(opts)) return c == 2 ? CFX_ENOTSUP : -7;
+    if (!work && n > 0) return -8;
+    if (reinterpret_cast<uintptr_t>(work) & 255) return -8;
+    return getrf_run(h, n, A, lda, ipiv, nullptr, info, opts, work, work_bytes, static_cast<hipStream_t>(stream));
+}
+
+int cfx_getrf_masked(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *ipiv, int32_t *rowmap,
+                     int32_t *info, const cfx_lu_opts *opts, void *work, size_t work_bytes, void *stream)
+{
+    if (!h) return -1;
+    if (n < 0 || n > INT32_MAX) return -2;
+    if (!A && n > 0) return -3;
+    if (lda < (n > 1 ? n : 1)) return -4;
+    if (!ipiv && n > 0) return -5;
+    if (!rowmap && n > 0) return -6;
+    if (!info) return -7;
+    if (int c = check_opts(opts)) return c == 2 ? CFX_ENOTSUP : -8;
+    if (!work && n > 0) return -9;
+    if (reinterpret_cast<uintptr_t>(work) & 255) return -9;
+    return getrf_run(h, n, A, lda, ipiv, rowmap, info, opts, work, work_bytes, static_cast<hipStream_t>(stream));
 }
 
 int cfx_gesv_ir_buffer_size(cfx_handle *h, int64_t n, int64_t nrhs, const cfx_ir_opts *opts, size_t *bytes)

@@ -51,7 +51,9 @@ int carve_workspace(void *work, size_t bytes, int64_t n, int v, int leaves,
 // receives the selected global rows.
 int launch_tslu(const double *W, int64_t ldw, int64_t row0, int64_t rows, int vb,
                 int leaves, const Workspace &ws, int32_t *piv_out, int32_t *ipiv,
-                int32_t *info, hipStream_t st);
+                int32_t *info, hipStream_t st, const int32_t *rm = nullptr);
+// (rm: row masking; panel row i, global row row0 + i, is then physical row
+// rm[row0 + i] of W, which points at row 0 of the panel's first column.)
 
 // Kernel attributes (dynamic LDS limits) of the current device; called by
 // cfx_create, so that no launch path sets them.
@@ -64,10 +66,12 @@ int solve_spin_limit(const cfx_handle *h);
 constexpr int kSolveSpinLimit = 1 << 22;
 
 // getrs pieces: permutation of ipiv, and the blocked triangular solves.
+// rm (row masking): factor row i is physical row rm[i], and rm is also the
+// permutation of P B (ipiv is then not read).
 int launch_getrs(int64_t n, int64_t nrhs, const double *LU, int64_t lda,
                  const int32_t *ipiv, double *B, int64_t ldb, int32_t *perm,
                  double *tmp, int32_t *sync, hipStream_t st,
-                 int spin_limit = kSolveSpinLimit);
+                 int spin_limit = kSolveSpinLimit, const int32_t *rm = nullptr);
 // perm[i] = source row of row i of P B (ipiv interchanges composed).
 int launch_perm(int64_t n, const int32_t *ipiv, int32_t *perm, hipStream_t st);
 // T[i, :] = B[perm[i], :]  /  B[i, :] = T[i, :]   (n x nrhs).
@@ -83,7 +87,7 @@ int launch_copy_rows(int64_t n, int64_t nrhs, const double *T, int64_t ldt,
 constexpr size_t kTrsvSyncBytes = 256;
 int launch_trsv(int64_t n, int64_t nrhs, const double *LU, int64_t lda, double *X,
                 int64_t ldx, int32_t *sync, hipStream_t st,
-                int spin_limit = kSolveSpinLimit);
+                int spin_limit = kSolveSpinLimit, const int32_t *rm = nullptr);
 // Host-blocking: *gave_up = sync[4] after `st` drains; sync[4] is cleared.
 int read_solve_flag(int32_t *sync, hipStream_t st, bool *gave_up);
 
@@ -92,33 +96,49 @@ int read_solve_flag(int32_t *sync, hipStream_t st, bool *gave_up);
 int launch_laswp(double *A, int64_t lda, int64_t n, int64_t k, int vb,
                  const Workspace &ws, hipStream_t st);
 
+// Row masking: the root's row-move plan applied to the row map rm (logical
+// row -> physical row) instead of the rows, and L00\U00 written into the
+// panel columns of the pivot rows where they are.
+int launch_rowmap_apply(double *A, int64_t lda, int32_t *rm, int64_t k, int vb,
+                        const Workspace &ws, hipStream_t st);
+// rm[i] = i for i < n.
+int launch_rowmap_init(int32_t *rm, int64_t n, hipStream_t st);
+
 // FactorizeA10 and FactorizeA01: L21 = A21 U00^{-1} and U12 = L00^{-1} A12,
-// in place, for the trailing m rows / columns of panel k.
+// in place, for the trailing m rows / columns of panel k.  rm: the row map
+// of row masking (logical row i at physical row rm[i]), or null.
 int launch_trsm(double *A, int64_t lda, int64_t k, int vb, int64_t m,
-                hipStream_t st);
+                hipStream_t st, const int32_t *rm = nullptr);
 // L21 and the first n1 columns of U12 in one launch; the other columns of
 // U12 (n1 .. m) separately.
 int launch_trsm_first(double *A, int64_t lda, int64_t k, int vb, int64_t m, int64_t n1,
-                      hipStream_t st);
+                      hipStream_t st, const int32_t *rm = nullptr);
 int launch_trsm_rest(double *A, int64_t lda, int64_t k, int vb, int64_t m, int64_t n1,
-                     hipStream_t st);
+                     hipStream_t st, const int32_t *rm = nullptr);
 
 // FactorizeA11: C[0:mr, 0:nc] -= L[0:mr, 0:K] * U[0:K, 0:nc]  (FP64 MFMA).
-// max_wgs > 0 bounds the grid (persistent workgroups walk the tiles)
+// max_wgs > 0 bounds the grid (persistent workgroups walk the tiles).
+// Row maps (null: none): row i of L and of C is physical row rmap[i] (L, C
+// then point at row 0 of their columns), row l of U physical row umap[l].
 int launch_schur_f64(const double *L, int64_t ldl, const double *U, int64_t ldu,
                      double *C, int64_t ldc, int64_t mr, int64_t nc, int K,
-                     int max_wgs, hipStream_t st);
+                     int max_wgs, hipStream_t st, const int32_t *rmap = nullptr,
+                     const int32_t *umap = nullptr);
 
 // Mixed-precision FactorizeA11.  launch_pack_lp rounds L21 (m x K, stride
 // ldl) and U12 (K x n, stride ldu) to the working precision (FP8: after the
 // power-of-two row / column scaling) into `buf` (lp_pack_bytes bytes);
 // launch_schur_lp then applies C[0:m, col0:col0+ncols] -= L21 U12[:, col0:
 // col0+ncols] from the packed operands, FP32 accumulation, FP64 C.
+// Row maps as for launch_schur_f64 (rmap: rows of L21 and C; umap: rows
+// of U12).
 size_t lp_pack_bytes(int precision, int64_t m, int64_t n, int K);
 int launch_pack_lp(int precision, const double *L21, int64_t ldl, int64_t m, const double *U12,
-                   int64_t ldu, int64_t n, int K, void *buf, hipStream_t st);
+                   int64_t ldu, int64_t n, int K, void *buf, hipStream_t st,
+                   const int32_t *rmap = nullptr, const int32_t *umap = nullptr);
 int launch_schur_lp(int precision, const void *buf, int64_t m, int64_t n, int K, int64_t col0,
-                    int64_t ncols, double *C, int64_t ldc, int max_wgs, hipStream_t st);
+                    int64_t ncols, double *C, int64_t ldc, int max_wgs, hipStream_t st,
+                    const int32_t *rmap = nullptr);
 
 int launch_set_int(int32_t *p, int32_t value, hipStream_t st);
 

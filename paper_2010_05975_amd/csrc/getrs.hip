@@ -25,6 +25,10 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int kPermLds = 36864;   // n up to this uses the LDS permutation (144 KiB)
 static_assert(kPermLds <= 0x10000, "row indices and the tags of perm_lds_kernel share a 32-bit entry");
+
+// Physical row of factor row i: rm[i] for factors stored with row masking
+// (rows never interchanged), else i.
+__device__ __forceinline__ int64_t fr(const int32_t *rm, int64_t i) { return rm ? (int64_t)rm[i] : i; }
 constexpr int SB = 128;           // block of the substitution
 constexpr int HB = 64;            // half block solved by one wavefront's lanes
 constexpr int RPW = 256;          // rows per updating workgroup (64: 34.6 ms, 256: 29.8 ms for 64 RHS at N = 32768)
@@ -145,8 +149,8 @@ __global__ void copy_rows_kernel(const double *T, int64_t ldt, int64_t n, int64_
 // side: a wavefront takes 4 rows at a time, 16 lanes per row; 16 right-hand
 // sides: 16 rows at a time on the FP64 matrix cores.
 template <int NRC>
-__device__ __forceinline__ void update_rows(const double *__restrict__ LU, int64_t lda, double *X,
-                                            int64_t ldx, int cc, int nc, int64_t rbeg, int64_t rend,
+__device__ __forceinline__ void update_rows(const double *__restrict__ LU, int64_t lda, const int32_t *rm,
+                                            double *X, int64_t ldx, int cc, int nc, int64_t rbeg, int64_t rend,
                                             int64_t c0, int bs, const double *ys)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -156,7 +160,7 @@ __device__ __forceinline__ void update_rows(const double *__restrict__ LU, int64
         if constexpr (NRC == 1) {
             const int64_t i = i0 + sub;
             const bool ok = i < rend;
-            const double *row = LU + (ok ? i : rbeg) * lda + c0;
+            const double *row = LU + fr(rm, ok ? i : rbeg) * lda + c0;
             // lane q owns the 8 consecutive columns 8q .. 8q+7
             double s = 0.0;
 #pragma unroll
@@ -178,7 +182,7 @@ __device__ __forceinline__ void update_rows(const double *__restrict__ LU, int64
             // value of the 16 rows is requested before the first product.
             const int lr = lane & 15, lk = lane >> 4;
             const int64_t ia = i0 + lr;
-            const double *arow = LU + (ia < rend ? ia : rbeg) * lda + c0;
+            const double *arow = LU + fr(rm, ia < rend ? ia : rbeg) * lda + c0;
             double av[SB / 4];
 #pragma unroll
             for (int t = 0; t < SB / 4; ++t) {
@@ -203,8 +207,8 @@ __device__ __forceinline__ void update_rows(const double *__restrict__ LU, int64
 // wavefront owns row t of the half and keeps that row of L in registers;
 // column j is eliminated by broadcasting lane j's finished value.
 template <int NRC>
-__device__ void diag_lower(const double *__restrict__ LU, int64_t lda, double *X, int64_t ldx, int cc,
-                           int nc, int64_t r0, int bs, double *yh)
+__device__ void diag_lower(const double *__restrict__ LU, int64_t lda, const int32_t *rm, double *X, int64_t ldx,
+                           int cc, int nc, int64_t r0, int bs, double *yh)
 {
     constexpr int CPW = NRC == 1 ? 1 : NRC / 4;   // right-hand sides per wavefront
     const int t = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -215,7 +219,7 @@ __device__ void diag_lower(const double *__restrict__ LU, int64_t lda, double *X
         const int64_t rb = r0 + HB * h;
         const bool okr = t < hb;
         if (active) {
-            const double *row = LU + (rb + (okr ? t : 0)) * lda;
+            const double *row = LU + fr(rm, rb + (okr ? t : 0)) * lda;
             double Lr[HB];
             static_for<HB>([&](auto J) {
                 constexpr int j = decltype(J)::value;
@@ -254,8 +258,8 @@ __device__ void diag_lower(const double *__restrict__ LU, int64_t lda, double *X
 // Upper (non-unit) triangular solve of the diagonal block rows r0 .. r0+bs
 // in place in X: the second half first, then the first.
 template <int NRC>
-__device__ void diag_upper(const double *__restrict__ LU, int64_t lda, double *X, int64_t ldx, int cc,
-                           int nc, int64_t r0, int bs, double *yh)
+__device__ void diag_upper(const double *__restrict__ LU, int64_t lda, const int32_t *rm, double *X, int64_t ldx,
+                           int cc, int nc, int64_t r0, int bs, double *yh)
 {
     constexpr int CPW = NRC == 1 ? 1 : NRC / 4;
     const int t = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -266,7 +270,7 @@ __device__ void diag_upper(const double *__restrict__ LU, int64_t lda, double *X
         const int64_t rb = r0 + HB * h;
         const bool okr = t < hb;
         if (active) {
-            const double *row = LU + (rb + (okr ? t : 0)) * lda;
+            const double *row = LU + fr(rm, rb + (okr ? t : 0)) * lda;
             double Ur[HB];
             static_for<HB>([&](auto J) {
                 constexpr int j = decltype(J)::value;
@@ -324,9 +328,9 @@ __device__ __forceinline__ void stage_block(const double *X, int64_t ldx, int cc
 // rows r0 .. r0+bsn (r0 = c0 + bs) and then solves it.  Workgroup g >= 1
 // owns rows r0 + bsn + (g-1) RPW .. + RPW.
 template <int NRC>
-__global__ __launch_bounds__(256) void fwd_step_kernel(const double *__restrict__ LU, int64_t lda, double *X,
-                                                       int64_t ldx, int64_t n, int nrhs, int64_t c0, int bs,
-                                                       int64_t r0, int bsn)
+__global__ __launch_bounds__(256) void fwd_step_kernel(const double *__restrict__ LU, int64_t lda,
+                                                       const int32_t *rm, double *X, int64_t ldx, int64_t n,
+                                                       int nrhs, int64_t c0, int bs, int64_t r0, int bsn)
 {
     __shared__ double ys[SB * NRC];
     __shared__ double yh[HB * NRC];
@@ -342,11 +346,11 @@ __global__ __launch_bounds__(256) void fwd_step_kernel(const double *__restrict_
             rbeg = r0 + bsn + (int64_t)(blockIdx.x - 1) * RPW;
             rend = rbeg + RPW < n ? rbeg + RPW : n;
         }
-        update_rows<NRC>(LU, lda, X, ldx, cc, nc, rbeg, rend, c0, bs, ys);
+        update_rows<NRC>(LU, lda, rm, X, ldx, cc, nc, rbeg, rend, c0, bs, ys);
     }
     if (blockIdx.x != 0 || bsn <= 0) return;
     __syncthreads();
-    diag_lower<NRC>(LU, lda, X, ldx, cc, nc, r0, bsn, yh);
+    diag_lower<NRC>(LU, lda, rm, X, ldx, cc, nc, r0, bsn, yh);
 }
 
 // Backward step: when c0 >= 0 the block rows c0 .. c0+bs are solved and
@@ -354,9 +358,9 @@ __global__ __launch_bounds__(256) void fwd_step_kernel(const double *__restrict_
 // r0 .. r0+bsn just above (r0 + bsn = c0) and then solves it.  Workgroup
 // g >= 1 owns rows (g-1) RPW .. + RPW below r0.
 template <int NRC>
-__global__ __launch_bounds__(256) void bwd_step_kernel(const double *__restrict__ LU, int64_t lda, double *X,
-                                                       int64_t ldx, int nrhs, int64_t c0, int bs, int64_t r0,
-                                                       int bsn)
+__global__ __launch_bounds__(256) void bwd_step_kernel(const double *__restrict__ LU, int64_t lda,
+                                                       const int32_t *rm, double *X, int64_t ldx, int nrhs,
+                                                       int64_t c0, int bs, int64_t r0, int bsn)
 {
     __shared__ double ys[SB * NRC];
     __shared__ double yh[HB * NRC];
@@ -372,11 +376,11 @@ __global__ __launch_bounds__(256) void bwd_step_kernel(const double *__restrict_
             rbeg = (int64_t)(blockIdx.x - 1) * RPW;
             rend = rbeg + RPW < r0 ? rbeg + RPW : r0;
         }
-        update_rows<NRC>(LU, lda, X, ldx, cc, nc, rbeg, rend, c0, bs, ys);
+        update_rows<NRC>(LU, lda, rm, X, ldx, cc, nc, rbeg, rend, c0, bs, ys);
     }
     if (blockIdx.x != 0 || bsn <= 0) return;
     __syncthreads();
-    diag_upper<NRC>(LU, lda, X, ldx, cc, nc, r0, bsn, yh);
+    diag_upper<NRC>(LU, lda, rm, X, ldx, cc, nc, r0, bsn, yh);
 }
 
 // ---------------------------------------------------------------------------
@@ -414,8 +418,9 @@ __device__ __forceinline__ double dpp_d(double a)
 // only guarantees that every workgroup exits).  A block that gave up writes
 // NaN for its rows, so an invalid solution is never mistaken for a result.
 template <bool LOWER>
-__global__ __launch_bounds__(256) void trsv_sf_kernel(const double *__restrict__ LU, int64_t lda, double *x,
-                                                      int64_t n, int nb, int32_t *sync, int spin_limit)
+__global__ __launch_bounds__(256) void trsv_sf_kernel(const double *__restrict__ LU, int64_t lda,
+                                                      const int32_t *rm, double *x, int64_t n, int nb,
+                                                      int32_t *sync, int spin_limit)
 {
     __shared__ double part[TB];
     __shared__ double Ts[TB][TB + 1];   // the diagonal block (padded rows)
@@ -435,7 +440,7 @@ __global__ __launch_bounds__(256) void trsv_sf_kernel(const double *__restrict__
     const int rr = 16 * wave + (lane >> 2);     // this lane's row of the block
     const int cq = (lane & 3) * 16;              // its 16 columns of a block
     const bool rok = rr < rows;
-    const double *lrow = LU + (r0 + (rok ? rr : 0)) * lda;
+    const double *lrow = LU + fr(rm, r0 + (rok ? rr : 0)) * lda;
     const int nk = t;                            // blocks to apply, in solve order
     auto kcol = [&](int i) -> int64_t { return (int64_t)(LOWER ? i : nb - 1 - i) * TB + cq; };
     auto load_l = [&](int i, double *lv) {
@@ -456,7 +461,7 @@ __global__ __launch_bounds__(256) void trsv_sf_kernel(const double *__restrict__
         const int e = tid + 256 * rep;
         const int i = e / TB, j = e - i * TB;
         const bool in = i < rows && j < rows && (LOWER ? j < i : j >= i);
-        Ts[i][j] = in ? LU[(r0 + i) * lda + r0 + j] : 0.0;
+        Ts[i][j] = in ? LU[fr(rm, r0 + i) * lda + r0 + j] : 0.0;
     }
     const bool ok = wave == 0 && lane < rows;
     const int64_t gi = r0 + (ok ? lane : 0);
@@ -564,31 +569,32 @@ __global__ __launch_bounds__(256) void trsv_sf_kernel(const double *__restrict__
     if (lane == 0) __hip_atomic_store(solved, t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-int trsv_one(int64_t n, const double *LU, int64_t lda, double *x, int32_t *sync, int spin_limit,
-             hipStream_t st)
+int trsv_one(int64_t n, const double *LU, int64_t lda, const int32_t *rm, double *x, int32_t *sync,
+             int spin_limit, hipStream_t st)
 {
     const int64_t nb = (n + TB - 1) / TB;
     if (nb > INT32_MAX) return CFX_ENOTSUP;
     hipLaunchKernelGGL(trsv_sync_reset_kernel, dim3(1), dim3(64), 0, st, sync);
     CFX_HIP(hipGetLastError());
-    hipLaunchKernelGGL(trsv_sf_kernel<true>, dim3((unsigned)nb), dim3(256), 0, st, LU, lda, x, n, (int)nb, sync,
-                       spin_limit);
+    hipLaunchKernelGGL(trsv_sf_kernel<true>, dim3((unsigned)nb), dim3(256), 0, st, LU, lda, rm, x, n, (int)nb,
+                       sync, spin_limit);
     CFX_HIP(hipGetLastError());
-    hipLaunchKernelGGL(trsv_sf_kernel<false>, dim3((unsigned)nb), dim3(256), 0, st, LU, lda, x, n, (int)nb, sync,
-                       spin_limit);
+    hipLaunchKernelGGL(trsv_sf_kernel<false>, dim3((unsigned)nb), dim3(256), 0, st, LU, lda, rm, x, n, (int)nb,
+                       sync, spin_limit);
     CFX_HIP(hipGetLastError());
     return CFX_OK;
 }
 
 template <int NRC>
-int trsv_impl(int64_t n, int nrhs, const double *LU, int64_t lda, double *X, int64_t ldx, hipStream_t st)
+int trsv_impl(int64_t n, int nrhs, const double *LU, int64_t lda, const int32_t *rm, double *X, int64_t ldx,
+              hipStream_t st)
 {
     const int64_t nb = (n + SB - 1) / SB;
     const unsigned gy = (unsigned)((nrhs + NRC - 1) / NRC);
     auto bsz = [&](int64_t J) { return (int)((n - J * SB) < SB ? (n - J * SB) : SB); };
     auto cdiv = [](int64_t a, int64_t b) { return (a + b - 1) / b; };
     // forward: L y = x
-    hipLaunchKernelGGL(fwd_step_kernel<NRC>, dim3(1, gy), dim3(256), 0, st, LU, lda, X, ldx, n, nrhs,
+    hipLaunchKernelGGL(fwd_step_kernel<NRC>, dim3(1, gy), dim3(256), 0, st, LU, lda, rm, X, ldx, n, nrhs,
                        (int64_t)-1, 0, (int64_t)0, bsz(0));
     CFX_HIP(hipGetLastError());
     for (int64_t J = 0; J + 1 < nb; ++J) {
@@ -596,18 +602,18 @@ int trsv_impl(int64_t n, int nrhs, const double *LU, int64_t lda, double *X, int
         const int bsn = bsz(J + 1);
         const int64_t below = n - r0 - bsn;
         const unsigned gx = (unsigned)(1 + cdiv(below, RPW));
-        hipLaunchKernelGGL(fwd_step_kernel<NRC>, dim3(gx, gy), dim3(256), 0, st, LU, lda, X, ldx, n, nrhs, c0,
-                           SB, r0, bsn);
+        hipLaunchKernelGGL(fwd_step_kernel<NRC>, dim3(gx, gy), dim3(256), 0, st, LU, lda, rm, X, ldx, n, nrhs,
+                           c0, SB, r0, bsn);
         CFX_HIP(hipGetLastError());
     }
     // backward: U x = y
-    hipLaunchKernelGGL(bwd_step_kernel<NRC>, dim3(1, gy), dim3(256), 0, st, LU, lda, X, ldx, nrhs,
+    hipLaunchKernelGGL(bwd_step_kernel<NRC>, dim3(1, gy), dim3(256), 0, st, LU, lda, rm, X, ldx, nrhs,
                        (int64_t)-1, 0, (nb - 1) * SB, bsz(nb - 1));
     CFX_HIP(hipGetLastError());
     for (int64_t J = nb - 1; J >= 1; --J) {
         const int64_t c0 = J * SB, r0 = c0 - SB;
         const unsigned gx = (unsigned)(1 + cdiv(r0, RPW));
-        hipLaunchKernelGGL(bwd_step_kernel<NRC>, dim3(gx, gy), dim3(256), 0, st, LU, lda, X, ldx, nrhs, c0,
+        hipLaunchKernelGGL(bwd_step_kernel<NRC>, dim3(gx, gy), dim3(256), 0, st, LU, lda, rm, X, ldx, nrhs, c0,
                            bsz(J), r0, SB);
         CFX_HIP(hipGetLastError());
     }
@@ -663,22 +669,28 @@ int launch_copy_rows(int64_t n, int64_t nrhs, const double *T, int64_t ldt, doub
 }
 
 int launch_trsv(int64_t n, int64_t nrhs, const double *LU, int64_t lda, double *X, int64_t ldx, int32_t *sync,
-                hipStream_t st, int spin_limit)
+                hipStream_t st, int spin_limit, const int32_t *rm)
 {
     if (n <= 0 || nrhs <= 0) return CFX_OK;
-    if (nrhs == 1 && sync && (ldx == 1 || n == 1)) return trsv_one(n, LU, lda, X, sync, spin_limit, st);
-    if (nrhs == 1) return trsv_impl<1>(n, 1, LU, lda, X, ldx, st);
-    return trsv_impl<16>(n, (int)nrhs, LU, lda, X, ldx, st);
+    if (nrhs == 1 && sync && (ldx == 1 || n == 1)) return trsv_one(n, LU, lda, rm, X, sync, spin_limit, st);
+    if (nrhs == 1) return trsv_impl<1>(n, 1, LU, lda, rm, X, ldx, st);
+    return trsv_impl<16>(n, (int)nrhs, LU, lda, rm, X, ldx, st);
 }
 
 int launch_getrs(int64_t n, int64_t nrhs, const double *LU, int64_t lda, const int32_t *ipiv, double *B,
-                 int64_t ldb, int32_t *perm, double *tmp, int32_t *sync, hipStream_t st, int spin_limit)
+                 int64_t ldb, int32_t *perm, double *tmp, int32_t *sync, hipStream_t st, int spin_limit,
+                 const int32_t *rm)
 {
     if (n == 0 || nrhs == 0) return CFX_OK;
     int rc;
-    if ((rc = launch_perm(n, ipiv, perm, st))) return rc;
-    if ((rc = launch_gather_rows(n, nrhs, B, ldb, perm, tmp, nrhs, st))) return rc;
-    if ((rc = launch_trsv(n, nrhs, LU, lda, tmp, nrhs, sync, st, spin_limit))) return rc;
+    // row masking: the row map is the permutation of P B itself
+    const int32_t *pb = rm;
+    if (!rm) {
+        if ((rc = launch_perm(n, ipiv, perm, st))) return rc;
+        pb = perm;
+    }
+    if ((rc = launch_gather_rows(n, nrhs, B, ldb, pb, tmp, nrhs, st))) return rc;
+    if ((rc = launch_trsv(n, nrhs, LU, lda, tmp, nrhs, sync, st, spin_limit, rm))) return rc;
     return launch_copy_rows(n, nrhs, tmp, nrhs, B, ldb, st);
 }
 

@@ -8,6 +8,12 @@
 // writes every destination, so no stripe depends on another.  The diagonal
 // block of the panel is written from the root's factored block (L00\U00).
 //
+// With row masking (Sec. 7.3, "Row Swapping vs. Row Masking") rows are not
+// moved: a row map rm (logical row -> physical row) takes the place of the
+// interchanges (rowmap_apply_kernel applies the plan to it, lu00_scatter
+// writes the root's L00\U00 into the pivot rows where they are), and every
+// kernel reaches logical row i at physical row rm[i].
+//
 // L21 = A21 U00^{-1} and U12 = L00^{-1} A12 are one solve shape: X U = B
 // with U upper triangular, for X = L21 (U = U00) and for X = U12^T
 // (U = L00^T, unit diagonal).  A workgroup of 4 wavefronts owns 64 rows of
@@ -60,6 +66,40 @@ __global__ __launch_bounds__(256) void laswp_kernel(double *A, int64_t lda, int6
             A[(k + j) * lda + c] = lu00[(int64_t)j * vb + (c - k)];
 }
 
+// Row masking: the plan's moves applied to the row map instead of the rows
+// (all sources read before any destination is written; one workgroup).
+__global__ __launch_bounds__(256) void rowmap_apply_kernel(int32_t *rm, const int32_t *plan)
+{
+    const int np = plan[0];
+    const int32_t *dst = plan + 1;
+    const int32_t *src = plan + 1 + 2 * kMaxV;
+    int v[2 * kMaxV / 256];
+#pragma unroll
+    for (int s = 0; s < 2 * kMaxV / 256; ++s) {
+        const int q = threadIdx.x + 256 * s;
+        if (q < np) v[s] = rm[src[q]];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 2 * kMaxV / 256; ++s) {
+        const int q = threadIdx.x + 256 * s;
+        if (q < np) rm[dst[q]] = v[s];
+    }
+}
+
+// Row masking: the root's factored block L00\U00 into the panel columns of
+// the pivot rows, where they are (one workgroup per pivot row).
+__global__ __launch_bounds__(256) void lu00_scatter_kernel(double *A, int64_t lda, const int32_t *rm, int64_t k,
+                                                           int vb, const double *lu00)
+{
+    const int j = blockIdx.x;
+    double *row = A + (int64_t)rm[k + j] * lda + k;
+    for (int c = threadIdx.x; c < vb; c += 256) row[c] = lu00[(int64_t)j * vb + c];
+}
+
+// Physical row of logical row i (identity without a row map).
+__device__ __forceinline__ int64_t phys(const int32_t *rm, int64_t i) { return rm ? (int64_t)rm[i] : i; }
+
 // ---------------------------------------------------------------------------
 // triangular solves
 // ---------------------------------------------------------------------------
@@ -82,13 +122,14 @@ __device__ __forceinline__ void sfor(F &&f)
     sfor_impl(f, std::make_integer_sequence<int, N>{});
 }
 
-// U(r, c) of the solve: U00 for L21 (mode 0), L00^T for U12 (mode 1).
+// U(r, c) of the solve: U00 for L21 (mode 0), L00^T for U12 (mode 1), from
+// the panel's diagonal block (rows k.. through the row map, columns k..).
 // Only r <= c is ever read.
 template <int MODE>
-__device__ __forceinline__ double uval(const double *P, int64_t lda, int r, int c)
+__device__ __forceinline__ double uval(const double *A, int64_t lda, const int32_t *rm, int64_t k, int r, int c)
 {
-    if constexpr (MODE == 0) return P[(int64_t)r * lda + c];
-    else return r == c ? 1.0 : P[(int64_t)c * lda + r];
+    if constexpr (MODE == 0) return A[phys(rm, k + r) * lda + k + c];
+    else return r == c ? 1.0 : A[phys(rm, k + c) * lda + k + r];
 }
 
 // One workgroup: rows rbase .. rbase+64 (below rend) of X.  LDS:
@@ -96,18 +137,20 @@ __device__ __forceinline__ double uval(const double *P, int64_t lda, int r, int 
 //   Sb  per wavefront: the block's rows (inputs, then the solution)
 //   Sg  per wavefront: X_{<b} U_{<b,b} of the block
 template <int MODE>
-__device__ __forceinline__ void trsm_body(double *A, int64_t lda, int64_t k, int vb, int64_t rbase,
-                                          int64_t rend, double *Us, double (*Sb)[TSW][ULD],
+__device__ __forceinline__ void trsm_body(double *A, int64_t lda, const int32_t *rm, int64_t k, int vb,
+                                          int64_t rbase, int64_t rend, double *Us, double (*Sb)[TSW][ULD],
                                           double (*Sg)[TSW][ULD])
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lk = lane >> 4;
     const int64_t row = rbase + wave * TSW + lr;   // this lane's row of X
     const bool rok = row < rend;
-    const double *P = A + k * lda + k;      // the panel's diagonal block
+    // L21: this lane's row of A21 (one physical row); U12^T: the panel
+    // rows, column k + vb + row
+    const int64_t xrow = MODE == 0 ? phys(rm, k + vb + (rok ? row : 0)) : 0;
     auto xaddr = [&](int c) -> double * {
-        if constexpr (MODE == 0) return A + (k + vb + row) * lda + k + c;
-        else return A + (k + c) * lda + k + vb + row;
+        if constexpr (MODE == 0) return A + xrow * lda + k + c;
+        else return A + phys(rm, k + c) * lda + k + vb + row;
     };
     // xa[s] = X[row][4s + lk]: the A operand layout of v_mfma_f64_16x16x4f64
     // (lane l holds row l%16, column l/16 of each 16 x 4 slice)
@@ -136,7 +179,7 @@ __device__ __forceinline__ void trsm_body(double *A, int64_t lda, int64_t k, int
         for (int i = 0; i < NPRE; ++i) {
             int r, c;
             elem(i, r, c);
-            pre[i] = (r < krf && c < bcf && r <= c0f + c) ? uval<MODE>(P, lda, r, c0f + c) : 0.0;
+            pre[i] = (r < krf && c < bcf && r <= c0f + c) ? uval<MODE>(A, lda, rm, k, r, c0f + c) : 0.0;
         }
     };
     fetch_u(0);
@@ -213,27 +256,27 @@ __device__ __forceinline__ void trsm_body(double *A, int64_t lda, int64_t k, int
 
 // Rows i0 .. i1 of one solve.
 template <int MODE>
-__global__ __launch_bounds__(256) void trsm_kernel(double *A, int64_t lda, int64_t k, int vb, int64_t i0,
-                                                   int64_t i1)
+__global__ __launch_bounds__(256) void trsm_kernel(double *A, int64_t lda, const int32_t *rm, int64_t k, int vb,
+                                                   int64_t i0, int64_t i1)
 {
     __shared__ double Us[kMaxV * ULD];
     __shared__ double Sb[4][TSW][ULD];
     __shared__ double Sg[4][TSW][ULD];
-    trsm_body<MODE>(A, lda, k, vb, i0 + (int64_t)blockIdx.x * TSR, i1, Us, Sb, Sg);
+    trsm_body<MODE>(A, lda, rm, k, vb, i0 + (int64_t)blockIdx.x * TSR, i1, Us, Sb, Sg);
 }
 
 // Both solves in one launch: workgroups 0 .. g0 take the m rows of L21,
 // the others the first n1 columns of U12.
-__global__ __launch_bounds__(256) void trsm_pair_kernel(double *A, int64_t lda, int64_t k, int vb, int64_t m,
-                                                        int g0, int64_t n1)
+__global__ __launch_bounds__(256) void trsm_pair_kernel(double *A, int64_t lda, const int32_t *rm, int64_t k,
+                                                        int vb, int64_t m, int g0, int64_t n1)
 {
     __shared__ double Us[kMaxV * ULD];
     __shared__ double Sb[4][TSW][ULD];
     __shared__ double Sg[4][TSW][ULD];
     if ((int)blockIdx.x < g0)
-        trsm_body<0>(A, lda, k, vb, (int64_t)blockIdx.x * TSR, m, Us, Sb, Sg);
+        trsm_body<0>(A, lda, rm, k, vb, (int64_t)blockIdx.x * TSR, m, Us, Sb, Sg);
     else
-        trsm_body<1>(A, lda, k, vb, (int64_t)(blockIdx.x - g0) * TSR, n1, Us, Sb, Sg);
+        trsm_body<1>(A, lda, rm, k, vb, (int64_t)(blockIdx.x - g0) * TSR, n1, Us, Sb, Sg);
 }
 
 __global__ void set_int_kernel(int32_t *p, int32_t v) { *p = v; }
@@ -250,30 +293,57 @@ int launch_laswp(double *A, int64_t lda, int64_t n, int64_t k, int vb, const Wor
     return CFX_OK;
 }
 
-int launch_trsm_first(double *A, int64_t lda, int64_t k, int vb, int64_t m, int64_t n1, hipStream_t st)
+int launch_rowmap_apply(double *A, int64_t lda, int32_t *rm, int64_t k, int vb, const Workspace &ws,
+                        hipStream_t st)
+{
+    hipLaunchKernelGGL(rowmap_apply_kernel, dim3(1), dim3(256), 0, st, rm, (const int32_t *)ws.plan);
+    CFX_HIP(hipGetLastError());
+    hipLaunchKernelGGL(lu00_scatter_kernel, dim3((unsigned)vb), dim3(256), 0, st, A, lda, (const int32_t *)rm, k,
+                       vb, (const double *)ws.lu00);
+    CFX_HIP(hipGetLastError());
+    return CFX_OK;
+}
+
+__global__ void rowmap_init_kernel(int32_t *rm, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) rm[i] = (int32_t)i;
+}
+
+int launch_rowmap_init(int32_t *rm, int64_t n, hipStream_t st)
+{
+    if (n <= 0) return CFX_OK;
+    hipLaunchKernelGGL(rowmap_init_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, rm, n);
+    CFX_HIP(hipGetLastError());
+    return CFX_OK;
+}
+
+int launch_trsm_first(double *A, int64_t lda, int64_t k, int vb, int64_t m, int64_t n1, hipStream_t st,
+                      const int32_t *rm)
 {
     if (m <= 0) return CFX_OK;
     n1 = n1 < m ? n1 : m;
     const int64_t g0 = (m + TSR - 1) / TSR, g1 = (n1 + TSR - 1) / TSR;
     if (g0 + g1 > INT32_MAX) return CFX_ENOTSUP;
-    hipLaunchKernelGGL(trsm_pair_kernel, dim3((unsigned)(g0 + g1)), dim3(256), 0, st, A, lda, k, vb, m, (int)g0,
-                       n1);
+    hipLaunchKernelGGL(trsm_pair_kernel, dim3((unsigned)(g0 + g1)), dim3(256), 0, st, A, lda, rm, k, vb, m,
+                       (int)g0, n1);
     CFX_HIP(hipGetLastError());
     return CFX_OK;
 }
 
-int launch_trsm_rest(double *A, int64_t lda, int64_t k, int vb, int64_t m, int64_t n1, hipStream_t st)
+int launch_trsm_rest(double *A, int64_t lda, int64_t k, int vb, int64_t m, int64_t n1, hipStream_t st,
+                     const int32_t *rm)
 {
     if (n1 >= m) return CFX_OK;
     const unsigned g = (unsigned)((m - n1 + TSR - 1) / TSR);
-    hipLaunchKernelGGL(trsm_kernel<1>, dim3(g), dim3(256), 0, st, A, lda, k, vb, n1, m);
+    hipLaunchKernelGGL(trsm_kernel<1>, dim3(g), dim3(256), 0, st, A, lda, rm, k, vb, n1, m);
     CFX_HIP(hipGetLastError());
     return CFX_OK;
 }
 
-int launch_trsm(double *A, int64_t lda, int64_t k, int vb, int64_t m, hipStream_t st)
+int launch_trsm(double *A, int64_t lda, int64_t k, int vb, int64_t m, hipStream_t st, const int32_t *rm)
 {
-    return launch_trsm_first(A, lda, k, vb, m, m, st);
+    return launch_trsm_first(A, lda, k, vb, m, m, st, rm);
 }
 
 int launch_set_int(int32_t *p, int32_t value, hipStream_t st)

@@ -14,6 +14,10 @@
 // from L2, nor the data of the tournament kernels that run beside the
 // update.
 //
+// With row masking (rows never interchanged) the rows of L21 and C, and of
+// U12, are reached through row maps (logical row -> physical row): the
+// MAPPED variants look up each tile row's physical row once per use.
+//
 // Tiles are mapped XCD-aware: consecutive workgroup ids land on different
 // XCDs (each with its own L2), so ids are regrouped to give each XCD a
 // contiguous, row-grouped range of tiles that share L21 and U12 strips.
@@ -47,12 +51,23 @@ __device__ __forceinline__ void tile_at(int pos, int tm, int tn, int &ti, int &t
 // EDGE: the tile may cross the matrix edge or K is not a multiple of BK
 // (every access is guarded).  VEC: operands are 16-byte aligned with even
 // strides, so a thread fetches its 8 contiguous doubles as 4 x 16 bytes.
-template <bool EDGE, bool VEC>
+template <bool EDGE, bool VEC, bool MAPPED>
 __global__ __launch_bounds__(256, 2) void schur_f64_kernel(const double *__restrict__ L, int64_t ldl,
                                                            const double *__restrict__ U, int64_t ldu,
                                                            double *__restrict__ C, int64_t ldc,
-                                                           int64_t mr, int64_t nc, int K, int tm, int tn)
+                                                           int64_t mr, int64_t nc, int K, int tm, int tn,
+                                                           const int32_t *__restrict__ rmap,
+                                                           const int32_t *__restrict__ umap)
 {
+    // physical row of tile row i of L / C, and of row l of U
+    auto crow = [&](int64_t i) -> int64_t {
+        if constexpr (MAPPED) return (int64_t)rmap[(!EDGE || i < mr) ? i : 0];
+        return i;
+    };
+    auto urow = [&](int64_t l) -> int64_t {
+        if constexpr (MAPPED) return (int64_t)umap[(!EDGE || l < K) ? l : 0];
+        return l;
+    };
     __shared__ double As[2][BK * LDA_S];
     __shared__ double Bs[2][BK * LDB_S];
 
@@ -81,7 +96,8 @@ __global__ __launch_bounds__(256, 2) void schur_f64_kernel(const double *__restr
     // global -> register staging assignment
     const int a_row = tid >> 1, a_col = (tid & 1) * 8;     // L tile: 128 rows x 16
     const int b_row = tid >> 4, b_col = (tid & 15) * 8;    // U tile: 16 rows x 128
-    const double *Lp = L + (i0 + a_row) * ldl + a_col;
+    const int64_t lrow = crow(i0 + a_row);
+    const double *Lp = L + lrow * ldl + a_col;
     const double *Up = U + (int64_t)b_row * ldu + j0 + b_col;
     double ra[8], rb[8];
 
@@ -89,7 +105,8 @@ __global__ __launch_bounds__(256, 2) void schur_f64_kernel(const double *__restr
         const int k0 = kc * BK;
         if constexpr (!EDGE && VEC) {
             const d2 *la = reinterpret_cast<const d2 *>(Lp + k0);
-            const d2 *ub = reinterpret_cast<const d2 *>(Up + (int64_t)k0 * ldu);
+            const d2 *ub = reinterpret_cast<const d2 *>(
+                MAPPED ? U + urow(k0 + b_row) * ldu + j0 + b_col : Up + (int64_t)k0 * ldu);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const d2 x = la[q], y = ub[q];
@@ -97,23 +114,25 @@ __global__ __launch_bounds__(256, 2) void schur_f64_kernel(const double *__restr
                 rb[2 * q] = y[0]; rb[2 * q + 1] = y[1];
             }
         } else if constexpr (!EDGE) {
+            const double *ub = MAPPED ? U + urow(k0 + b_row) * ldu + j0 + b_col : Up + (int64_t)k0 * ldu;
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 ra[q] = Lp[k0 + q];
-                rb[q] = Up[(int64_t)k0 * ldu + q];
+                rb[q] = ub[q];
             }
         } else {
             const int64_t gi = i0 + a_row;
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const int kk = k0 + a_col + q;
-                ra[q] = (gi < mr && kk < K) ? L[gi * ldl + kk] : 0.0;
+                ra[q] = (gi < mr && kk < K) ? L[lrow * ldl + kk] : 0.0;
             }
             const int kb = k0 + b_row;
+            const int64_t ur = urow(kb);
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const int64_t gj = j0 + b_col + q;
-                rb[q] = (kb < K && gj < nc) ? U[(int64_t)kb * ldu + gj] : 0.0;
+                rb[q] = (kb < K && gj < nc) ? U[ur * ldu + gj] : 0.0;
             }
         }
     };
@@ -136,7 +155,8 @@ __global__ __launch_bounds__(256, 2) void schur_f64_kernel(const double *__restr
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int64_t gi = i0 + wm + a * 16 + lk + 4 * q;
-                acc[a][b][q] = (!EDGE || (gi < mr && gj < nc)) ? __builtin_nontemporal_load(&C[gi * ldc + gj]) : 0.0;
+                acc[a][b][q] = (!EDGE || (gi < mr && gj < nc)) ? __builtin_nontemporal_load(&C[crow(gi) * ldc + gj])
+                                                                : 0.0;
             }
         }
 
@@ -182,7 +202,7 @@ __global__ __launch_bounds__(256, 2) void schur_f64_kernel(const double *__restr
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int64_t gi = i0 + wm + a * 16 + lk + 4 * q;
-                if (!EDGE || (gi < mr && gj < nc)) __builtin_nontemporal_store(acc[a][b][q], &C[gi * ldc + gj]);
+                if (!EDGE || (gi < mr && gj < nc)) __builtin_nontemporal_store(acc[a][b][q], &C[crow(gi) * ldc + gj]);
             }
         }
     }   // tiles of this workgroup (the last K chunk ended with a barrier, so
@@ -192,7 +212,8 @@ __global__ __launch_bounds__(256, 2) void schur_f64_kernel(const double *__restr
 }  // namespace
 
 int launch_schur_f64(const double *L, int64_t ldl, const double *U, int64_t ldu, double *C,
-                     int64_t ldc, int64_t mr, int64_t nc, int K, int max_wgs, hipStream_t st)
+                     int64_t ldc, int64_t mr, int64_t nc, int K, int max_wgs, hipStream_t st,
+                     const int32_t *rmap, const int32_t *umap)
 {
     if (mr <= 0 || nc <= 0 || K <= 0) return CFX_OK;
     const int tm = (int)((mr + BM - 1) / BM), tn = (int)((nc + BN - 1) / BN);
@@ -204,15 +225,23 @@ int launch_schur_f64(const double *L, int64_t ldl, const double *U, int64_t ldu,
     const bool full = (mr % BM == 0) && (nc % BN == 0) && (K % BK == 0);
     const bool vec = ((reinterpret_cast<uintptr_t>(L) | reinterpret_cast<uintptr_t>(U)) & 15) == 0 &&
                      (ldl % 2 == 0) && (ldu % 2 == 0);
-    if (full && vec)
-        hipLaunchKernelGGL((schur_f64_kernel<false, true>), dim3((unsigned)nb), dim3(256), 0, st, L, ldl, U,
-                           ldu, C, ldc, mr, nc, K, tm, tn);
+    if ((rmap == nullptr) != (umap == nullptr)) return CFX_ENOTSUP;   // both maps or none
+    if (rmap) {
+        if (full && vec)
+            hipLaunchKernelGGL((schur_f64_kernel<false, true, true>), dim3((unsigned)nb), dim3(256), 0, st, L,
+                               ldl, U, ldu, C, ldc, mr, nc, K, tm, tn, rmap, umap);
+        else
+            hipLaunchKernelGGL((schur_f64_kernel<true, false, true>), dim3((unsigned)nb), dim3(256), 0, st, L,
+                               ldl, U, ldu, C, ldc, mr, nc, K, tm, tn, rmap, umap);
+    } else if (full && vec)
+        hipLaunchKernelGGL((schur_f64_kernel<false, true, false>), dim3((unsigned)nb), dim3(256), 0, st, L, ldl,
+                           U, ldu, C, ldc, mr, nc, K, tm, tn, rmap, umap);
     else if (full)
-        hipLaunchKernelGGL((schur_f64_kernel<false, false>), dim3((unsigned)nb), dim3(256), 0, st, L, ldl,
-                           U, ldu, C, ldc, mr, nc, K, tm, tn);
+        hipLaunchKernelGGL((schur_f64_kernel<false, false, false>), dim3((unsigned)nb), dim3(256), 0, st, L,
+                           ldl, U, ldu, C, ldc, mr, nc, K, tm, tn, rmap, umap);
     else
-        hipLaunchKernelGGL((schur_f64_kernel<true, false>), dim3((unsigned)nb), dim3(256), 0, st, L, ldl, U,
-                           ldu, C, ldc, mr, nc, K, tm, tn);
+        hipLaunchKernelGGL((schur_f64_kernel<true, false, false>), dim3((unsigned)nb), dim3(256), 0, st, L, ldl,
+                           U, ldu, C, ldc, mr, nc, K, tm, tn, rmap, umap);
     CFX_HIP(hipGetLastError());
     return CFX_OK;
 }

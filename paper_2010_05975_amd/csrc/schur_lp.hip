@@ -172,27 +172,33 @@ __device__ __forceinline__ double absmax_nan(double m, double a)
     return (a > m || a != a) ? a : m;
 }
 
+// Physical row of logical row i (identity without a row map).
+__device__ __forceinline__ int64_t phys(const int32_t *rm, int64_t i) { return rm ? (int64_t)rm[i] : i; }
+
 // sL[i] for the rows of L (m x K, stride ldl): one wavefront per row.
 __global__ __launch_bounds__(256) void row_scale_kernel(const double *__restrict__ L, int64_t ldl, int64_t m,
-                                                        int K, int32_t *__restrict__ sL)
+                                                        int K, const int32_t *__restrict__ rmap,
+                                                        int32_t *__restrict__ sL)
 {
     const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (i >= m) return;
+    const double *row = L + phys(rmap, i) * ldl;
     double mx = 0.0;
-    for (int k = lane; k < K; k += 64) mx = absmax_nan(mx, L[i * ldl + k]);
+    for (int k = lane; k < K; k += 64) mx = absmax_nan(mx, row[k]);
     for (int off = 32; off >= 1; off >>= 1) mx = absmax_nan(mx, __shfl_xor(mx, off));
     if (lane == 0) sL[i] = scale_exp(mx);
 }
 
 // sU[j] for the columns of U (K x n, stride ldu): one thread per column.
 __global__ __launch_bounds__(256) void col_scale_kernel(const double *__restrict__ U, int64_t ldu, int64_t n,
-                                                        int K, int32_t *__restrict__ sU)
+                                                        int K, const int32_t *__restrict__ umap,
+                                                        int32_t *__restrict__ sU)
 {
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (j >= n) return;
     double mx = 0.0;
-    for (int k = 0; k < K; ++k) mx = absmax_nan(mx, U[(int64_t)k * ldu + j]);
+    for (int k = 0; k < K; ++k) mx = absmax_nan(mx, U[phys(umap, k) * ldu + j]);
     sU[j] = scale_exp(mx);
 }
 
@@ -200,13 +206,14 @@ __global__ __launch_bounds__(256) void col_scale_kernel(const double *__restrict
 // (sL null: no scaling), zero for K <= k < Kp.
 template <typename T>
 __global__ void pack_rows_kernel(const double *__restrict__ L, int64_t ldl, int64_t m, int K, int Kp,
-                                 const int32_t *__restrict__ sL, T *__restrict__ out)
+                                 const int32_t *__restrict__ rmap, const int32_t *__restrict__ sL,
+                                 T *__restrict__ out)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= m * Kp) return;
     const int64_t i = e / Kp;
     const int k = (int)(e - i * Kp);
-    double x = k < K ? L[i * ldl + k] : 0.0;
+    double x = k < K ? L[phys(rmap, i) * ldl + k] : 0.0;
     if (sL) x = sL[i] == kNonFinite ? 0.0 : ldexp(x, sL[i]);
     out[e] = to_lowp<T>(x);
 }
@@ -215,8 +222,8 @@ __global__ void pack_rows_kernel(const double *__restrict__ L, int64_t ldl, int6
 // FP64; sU null: no scaling), zero for K <= k < Kp.
 template <typename T>
 __global__ __launch_bounds__(256) void pack_cols_kernel(const double *__restrict__ U, int64_t ldu, int64_t n,
-                                                        int K, int Kp, const int32_t *__restrict__ sU,
-                                                        T *__restrict__ out)
+                                                        int K, int Kp, const int32_t *__restrict__ umap,
+                                                        const int32_t *__restrict__ sU, T *__restrict__ out)
 {
     __shared__ double tile[32][33];
     const int64_t j0 = (int64_t)blockIdx.x * 32;
@@ -225,7 +232,7 @@ __global__ __launch_bounds__(256) void pack_cols_kernel(const double *__restrict
     for (int r = ty; r < 32; r += 8) {
         const int k = k0 + r;
         const int64_t j = j0 + tx;
-        tile[r][tx] = (k < K && j < n) ? U[(int64_t)k * ldu + j] : 0.0;
+        tile[r][tx] = (k < K && j < n) ? U[phys(umap, k) * ldu + j] : 0.0;
     }
     __syncthreads();
     for (int r = ty; r < 32; r += 8) {
@@ -244,7 +251,8 @@ __global__ __launch_bounds__(256, 2) void schur_lp_kernel(const T *__restrict__ 
                                                           int Kp, const int32_t *__restrict__ sL,
                                                           const int32_t *__restrict__ sU,
                                                           double *__restrict__ C, int64_t ldc,
-                                                          int64_t mr, int64_t nc, int tm, int tn)
+                                                          int64_t mr, int64_t nc, int tm, int tn,
+                                                          const int32_t *__restrict__ rmap)
 {
     // FP8: every FP32 sum is scaled back by 2^-(sL_i + sU_j)
     constexpr bool SCALED = sizeof(T) == 1;
@@ -295,7 +303,8 @@ __global__ __launch_bounds__(256, 2) void schur_lp_kernel(const T *__restrict__ 
             for (int b = 0; b < 4; ++b)
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    cv[a][b][q] = __builtin_nontemporal_load(&C[(i0 + wm + a * 16 + 4 * lk + q) * ldc + j0 + wn + b * 16 + lr]);
+                    cv[a][b][q] = __builtin_nontemporal_load(
+                        &C[phys(rmap, i0 + wm + a * 16 + 4 * lk + q) * ldc + j0 + wn + b * 16 + lr]);
     }
     f4 acc[4][4];
 #pragma unroll
@@ -347,9 +356,9 @@ __global__ __launch_bounds__(256, 2) void schur_lp_kernel(const T *__restrict__ 
             for (int q = 0; q < 4; ++q) {
                 const int64_t gi = i0 + wm + a * 16 + 4 * lk + q;
                 if constexpr (!EDGE) {
-                    __builtin_nontemporal_store(cv[a][b][q] - sum_at(a, b, q), &C[gi * ldc + gj]);
+                    __builtin_nontemporal_store(cv[a][b][q] - sum_at(a, b, q), &C[phys(rmap, gi) * ldc + gj]);
                 } else if (gi < mr && gj < nc) {
-                    double *c = C + gi * ldc + gj;
+                    double *c = C + phys(rmap, gi) * ldc + gj;
                     *c = *c - sum_at(a, b, q);
                 }
             }
@@ -379,7 +388,7 @@ PackLayout pack_layout(int precision, int64_t m, int64_t n, int K)
 
 template <typename T>
 int pack_impl(const PackLayout &pl, const double *L21, int64_t ldl, int64_t m, const double *U12, int64_t ldu,
-              int64_t n, int K, char *buf, hipStream_t st)
+              int64_t n, int K, char *buf, hipStream_t st, const int32_t *rmap, const int32_t *umap)
 {
     const int Kp = pl.Kp;
     T *Lp_ = reinterpret_cast<T *>(buf);
@@ -390,24 +399,24 @@ int pack_impl(const PackLayout &pl, const double *L21, int64_t ldl, int64_t m, c
         sU = reinterpret_cast<int32_t *>(buf + pl.off_su);
         if (m > 0) {
             hipLaunchKernelGGL(row_scale_kernel, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, st, L21, ldl, m, K,
-                               sL);
+                               rmap, sL);
             CFX_HIP(hipGetLastError());
         }
         if (n > 0) {
             hipLaunchKernelGGL(col_scale_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, U12, ldu, n,
-                               K, sU);
+                               K, umap, sU);
             CFX_HIP(hipGetLastError());
         }
     }
     const int64_t tot = m * Kp;
     if (tot > 0) {
         hipLaunchKernelGGL(pack_rows_kernel<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, L21, ldl,
-                           m, K, Kp, sL, Lp_);
+                           m, K, Kp, rmap, sL, Lp_);
         CFX_HIP(hipGetLastError());
     }
     if (n > 0) {
         hipLaunchKernelGGL(pack_cols_kernel<T>, dim3((unsigned)((n + 31) / 32), (unsigned)(Kp / 32)), dim3(256), 0,
-                           st, U12, ldu, n, K, Kp, sU, Ut_);
+                           st, U12, ldu, n, K, Kp, umap, sU, Ut_);
         CFX_HIP(hipGetLastError());
     }
     return CFX_OK;
@@ -415,7 +424,7 @@ int pack_impl(const PackLayout &pl, const double *L21, int64_t ldl, int64_t m, c
 
 template <typename T>
 int schur_impl(const PackLayout &pl, const char *buf, int64_t m, int64_t col0, int64_t ncols, double *C,
-               int64_t ldc, int max_wgs, hipStream_t st)
+               int64_t ldc, int max_wgs, hipStream_t st, const int32_t *rmap)
 {
     const int Kp = pl.Kp;
     const T *Lp_ = reinterpret_cast<const T *>(buf);
@@ -433,10 +442,10 @@ int schur_impl(const PackLayout &pl, const char *buf, int64_t m, int64_t col0, i
     const bool full = (m % BM == 0) && (ncols % BN == 0);
     if (full)
         hipLaunchKernelGGL((schur_lp_kernel<T, false>), dim3((unsigned)nb), dim3(256), 0, st, Lp_, Ut_, Kp, sL, sU,
-                           C + col0, ldc, m, ncols, tm, tn);
+                           C + col0, ldc, m, ncols, tm, tn, rmap);
     else
         hipLaunchKernelGGL((schur_lp_kernel<T, true>), dim3((unsigned)nb), dim3(256), 0, st, Lp_, Ut_, Kp, sL, sU,
-                           C + col0, ldc, m, ncols, tm, tn);
+                           C + col0, ldc, m, ncols, tm, tn, rmap);
     CFX_HIP(hipGetLastError());
     return CFX_OK;
 }
@@ -449,24 +458,24 @@ size_t lp_pack_bytes(int precision, int64_t m, int64_t n, int K)
 }
 
 int launch_pack_lp(int precision, const double *L21, int64_t ldl, int64_t m, const double *U12, int64_t ldu,
-                   int64_t n, int K, void *buf, hipStream_t st)
+                   int64_t n, int K, void *buf, hipStream_t st, const int32_t *rmap, const int32_t *umap)
 {
     const PackLayout pl = pack_layout(precision, m, n, K);
     char *b = static_cast<char *>(buf);
-    if (precision == CFX_PREC_BF16) return pack_impl<__bf16>(pl, L21, ldl, m, U12, ldu, n, K, b, st);
-    if (precision == CFX_PREC_FP16) return pack_impl<_Float16>(pl, L21, ldl, m, U12, ldu, n, K, b, st);
-    if (precision == CFX_PREC_FP8) return pack_impl<e4m3>(pl, L21, ldl, m, U12, ldu, n, K, b, st);
+    if (precision == CFX_PREC_BF16) return pack_impl<__bf16>(pl, L21, ldl, m, U12, ldu, n, K, b, st, rmap, umap);
+    if (precision == CFX_PREC_FP16) return pack_impl<_Float16>(pl, L21, ldl, m, U12, ldu, n, K, b, st, rmap, umap);
+    if (precision == CFX_PREC_FP8) return pack_impl<e4m3>(pl, L21, ldl, m, U12, ldu, n, K, b, st, rmap, umap);
     return CFX_ENOTSUP;
 }
 
 int launch_schur_lp(int precision, const void *buf, int64_t m, int64_t n, int K, int64_t col0, int64_t ncols,
-                    double *C, int64_t ldc, int max_wgs, hipStream_t st)
+                    double *C, int64_t ldc, int max_wgs, hipStream_t st, const int32_t *rmap)
 {
     const PackLayout pl = pack_layout(precision, m, n, K);
     const char *b = static_cast<const char *>(buf);
-    if (precision == CFX_PREC_BF16) return schur_impl<__bf16>(pl, b, m, col0, ncols, C, ldc, max_wgs, st);
-    if (precision == CFX_PREC_FP16) return schur_impl<_Float16>(pl, b, m, col0, ncols, C, ldc, max_wgs, st);
-    if (precision == CFX_PREC_FP8) return schur_impl<e4m3>(pl, b, m, col0, ncols, C, ldc, max_wgs, st);
+    if (precision == CFX_PREC_BF16) return schur_impl<__bf16>(pl, b, m, col0, ncols, C, ldc, max_wgs, st, rmap);
+    if (precision == CFX_PREC_FP16) return schur_impl<_Float16>(pl, b, m, col0, ncols, C, ldc, max_wgs, st, rmap);
+    if (precision == CFX_PREC_FP8) return schur_impl<e4m3>(pl, b, m, col0, ncols, C, ldc, max_wgs, st, rmap);
     return CFX_ENOTSUP;
 }
 

@@ -68,6 +68,7 @@ struct NodeArgs {
     int32_t *ipiv;          // root: interchanges, global indexing (may be null)
     int32_t *plan;          // root: row-move plan (may be null)
     int32_t *info;          // root: first zero pivot (may be null)
+    const int32_t *rm;      // row masking: global row g is physical row rm[g] of W (else g - row0)
     int32_t *selg;          // per node: selected global rows [kMaxV], physical rows [kMaxV]
     unsigned char *rsel;    // per node: row already selected [rs_node]
     int rs_node;
@@ -704,8 +705,13 @@ __global__ __launch_bounds__(256) void tslu_gather_kernel(NodeArgs p, int tiles_
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const int e = tid + k * 256, i = e >> 6, c = e & 63;
-        v[k] = (r0 + i < r && c0 + c < p.vb)
-                   ? p.W[(int64_t)(node_gid(p, nr, r0 + i) - p.row0) * p.ldw + c0 + c] : 0.0;
+        if (r0 + i < r && c0 + c < p.vb) {
+            const int g = node_gid(p, nr, r0 + i);
+            const int64_t pr = p.rm ? (int64_t)p.rm[g] : (int64_t)(g - p.row0);
+            v[k] = p.W[pr * p.ldw + c0 + c];
+        } else {
+            v[k] = 0.0;
+        }
     }
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
@@ -791,7 +797,8 @@ int init_kernel_attributes()
 }
 
 int launch_tslu(const double *W, int64_t ldw, int64_t row0, int64_t rows, int vb, int leaves,
-                const Workspace &ws, int32_t *piv_out, int32_t *ipiv, int32_t *info, hipStream_t st)
+                const Workspace &ws, int32_t *piv_out, int32_t *ipiv, int32_t *info, hipStream_t st,
+                const int32_t *rm)
 {
     int64_t h = (rows + leaves - 1) / leaves;
     if (h < vb) h = vb;
@@ -812,6 +819,7 @@ int launch_tslu(const double *W, int64_t ldw, int64_t row0, int64_t rows, int vb
     a.ipiv = ipiv;
     a.plan = ipiv ? ws.plan : nullptr;
     a.info = info;
+    a.rm = rm;
     a.selg = ws.selg;
     a.rsel = ws.rsel;
     a.rs_node = (int)ws.rs_node;
