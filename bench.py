@@ -60,7 +60,7 @@ def lu_flops_of_columns(n, k0, k1):
     return float(np.sum(2.0 * r * r + r))
 
 
-def committed_traffic(n, v, L, field="traffic_bytes_per_launch", launches=None):
+def committed_traffic(n, v, L, field="traffic_bytes_per_launch", launches=None, delay=1):
     """HBM bytes per launch of the FP64 Schur kernel from the committed
     rocprofv3 PMC summary of this workload (FETCH_SIZE and WRITE_SIZE runs
     on the Schur-only replay of the factorisation's launches, each counter
@@ -68,7 +68,8 @@ def committed_traffic(n, v, L, field="traffic_bytes_per_launch", launches=None):
     source changed since the counters were taken, or the factorisation now
     issues a different number of Schur launches."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"schur_f64_kernel_traffic_n{n}_v{v}_L{L}.md")
+    tag = "" if delay == 1 else f"_delay{delay}"
+    path = os.path.join(ROOT, "profiles", f"schur_f64_kernel_traffic_n{n}_v{v}_L{L}{tag}.md")
     if not os.path.exists(path):
         return None
     fields = {}
@@ -98,13 +99,17 @@ def lu_io_lower_bound_bytes(n, M):
     return 8.0 * ((2.0 * n ** 3 - 6.0 * n ** 2 + 4.0 * n) / (3.0 * np.sqrt(M)) + n * (n - 1) / 2.0)
 
 
-def schur_replay(cfx, torch, n, v, chunk, seed):
+def schur_replay(cfx, torch, n, v, chunk, seed, delay=1):
     """Only the Schur-complement launches of one lookahead factorisation at
     (n, v), in the library's order and shapes, on one stream: for each panel
     k, C = A[k+vb:, k+vb:] is updated from L21 = P[k+vb:, k:k+vb] and
     U12 = P[k:k+vb, k+vb:] (the strides and offsets of the factorisation;
     P is a second matrix that stays unchanged), first the next panel's
-    columns, then the rest in `chunk`-column launches.  No tournament
+    columns, then the rest in `chunk`-column launches.  With delay d > 1
+    the launches of the tile-stationary schedule instead: inside each batch
+    of d panels the thin updates of panel k's columns and of its pivot rows
+    (K = k - K0), and at the batch end the update of the trailing matrix
+    with K = d v (the next panel's columns, then chunks).  No tournament
     kernels run, so a counter run sees these launches alone.  Returns
     (launches, algorithmic flops, seconds)."""
     dev = torch.device("cuda:0")
@@ -114,22 +119,29 @@ def schur_replay(cfx, torch, n, v, chunk, seed):
     P = torch.randn(n, n, dtype=torch.float64, device=dev, generator=g) / 16.0
     stream = torch.cuda.current_stream()
     launches, flops = 0, 0.0
+
+    def upd(r, c, m, nc, k0, K):
+        nonlocal launches, flops
+        if m <= 0 or nc <= 0 or K <= 0:
+            return
+        cfx.schur_update(P[r:r + m, k0:k0 + K], P[k0:k0 + K, c:c + nc], A[r:r + m, c:c + nc], stream=stream)
+        launches += 1
+        flops += 2.0 * m * nc * K
+
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(0, n, v):
-        vb = min(v, n - k)
-        m = n - k - vb
+    for K0 in range(0, n, delay * v):
+        kE = min(n, K0 + delay * v)
+        for k in range(K0 + v, kE, v):          # thin updates inside the batch
+            vb = min(v, n - k)
+            upd(k, k, n - k, vb, K0, k - K0)
+            upd(k, k + vb, vb, n - k - vb, K0, k - K0)
+        m = n - kE
         if m <= 0:
             break
         vbn = min(v, m)
-        L21 = P[k + vb:, k:k + vb]
-        U12 = P[k:k + vb, k + vb:]
-        C = A[k + vb:, k + vb:]
-        cols = [(0, vbn)] + [(c0, min(chunk, m - c0)) for c0 in range(vbn, m, chunk)]
-        for c0, cw in cols:
-            cfx.schur_update(L21, U12[:, c0:c0 + cw], C[:, c0:c0 + cw], stream=stream)
-            launches += 1
-            flops += 2.0 * m * cw * vb
+        for c0, cw in [(0, vbn)] + [(c0, min(chunk, m - c0)) for c0 in range(vbn, m, chunk)]:
+            upd(kE, kE + c0, m, cw, K0, kE - K0)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     del A, P
@@ -189,6 +201,52 @@ def masked_leg(cfx, torch, pristine, A_swapped, ipiv, n, v, L, lookahead, work, 
            "interchange_bytes_bound_gb": round(sum(2 * 2 * min(v, n - k) * n * 8 for k in range(0, n, v)) / 1e9, 2),
            "bitwise_equal_to_interchanged": equal}
     log(f"row masking: {out}")
+    del M
+    torch.cuda.empty_cache()
+    return out
+
+
+def delayed_leg(cfx, torch, pristine, A_ref, n, v, L, lookahead, work, stream, delays, reps=2):
+    """The tile-stationary schedule (cfx_set_schur_delay) on the same matrix
+    and options: time per factorisation (HIP events, median of `reps` after
+    a warm-up), the Schur phase, the Frobenius residual of the factors, and
+    the HBM bytes of its Schur launches from the committed counter runs of
+    the matching replay (when present)."""
+    out = {}
+    M = torch.empty_like(pristine)
+    ipiv = torch.empty(n, dtype=torch.int32, device=pristine.device)
+    info = torch.empty(1, dtype=torch.int32, device=pristine.device)
+    for d in delays:
+        cfx.set_schur_delay(d)
+        wk = cfx.workspace(n, v, L, "fp64", lookahead, pristine.device)
+        times = []
+        for it in range(reps + 1):
+            M.copy_(pristine)
+            torch.cuda.synchronize()
+            if it == reps:
+                cfx.profile_begin()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            cfx.getrf(M, v=v, leaves=L, lookahead=lookahead, work=wk, ipiv=ipiv, info=info, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            if it:
+                times.append(e0.elapsed_time(e1))
+        prof = cfx.profile_end()
+        cfx.set_schur_delay(1)
+        ms = float(np.median(times))
+        res = frob_residual(torch, pristine, M, _perm_of(ipiv.cpu().numpy()))
+        r = {"getrf_ms": round(ms, 3), "getrf_tflops": round(2.0 * n ** 3 / 3.0 / (ms / 1e3) / 1e12, 3),
+             "schur_ms": round(prof["schur_ms"], 3), "tslu_ms": round(prof["tslu_ms"], 3),
+             "schur_launches": prof["schur_launches"], "frob_residual": res, "info": int(info.cpu()[0])}
+        per = committed_traffic(n, v, L, launches=prof["schur_launches"], delay=d)
+        if per is not None:
+            tot = per * prof["schur_launches"]
+            r["schur_hbm_gb"] = round(tot / 1e9, 2)
+            r["ratio_to_xcd_bound"] = round(tot / lu_io_lower_bound_bytes(n, M_XCD), 3)
+        out[f"delay_{d}"] = r
+        log(f"tile-stationary d={d}: {r}")
+        del wk
     del M
     torch.cuda.empty_cache()
     return out
@@ -433,6 +491,10 @@ def main():
                     help="issue the lookahead schedule on one stream (for PMC counter runs)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-masked", action="store_true", help="skip the row-masking leg")
+    ap.add_argument("--delay", type=int, default=1,
+                    help="panels per trailing update of the timed factorisation (tile-stationary schedule)")
+    ap.add_argument("--delays", default="2,4",
+                    help="delays of the tile-stationary leg (empty: skip it)")
     ap.add_argument("--cpu-panels", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ir", action="store_true", help="skip the mixed-precision IR leg")
@@ -473,9 +535,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.schur_replay:
         chunk = args.chunk or cfx.overlap_tuning()[1]
-        launches, flops, dt = schur_replay(cfx, torch, n, v, chunk, args.seed)
-        out = {"schur_replay": {"n": n, "v": v, "chunk": chunk, "launches": launches, "flops": flops,
-                                "seconds": round(dt, 4), "tflops": round(flops / dt / 1e12, 3)}}
+        launches, flops, dt = schur_replay(cfx, torch, n, v, chunk, args.seed, args.delay)
+        out = {"schur_replay": {"n": n, "v": v, "chunk": chunk, "delay": args.delay, "launches": launches,
+                                "flops": flops, "seconds": round(dt, 4), "tflops": round(flops / dt / 1e12, 3)}}
         if args.calibration_copy:
             src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
             dst = torch.empty_like(src)
@@ -500,6 +562,8 @@ def main():
         pb = torch.from_numpy(b_host).to(dev)
     A = torch.empty_like(pristine)
     B = torch.empty_like(pb)
+    if args.delay != 1:
+        cfx.set_schur_delay(args.delay)
     work = cfx.workspace(n, v, L, "fp64", args.lookahead, dev)
     if args.schur_wgs is not None or args.chunk is not None or args.one_stream:
         w0, c0, _ = cfx.overlap_tuning()
@@ -570,8 +634,12 @@ def main():
     log(f"getrs with 64 right-hand sides: {getrs64_ms:.2f} ms")
 
     masked = None
-    if not args.no_masked:
+    if not args.no_masked and args.delay == 1:
         masked = masked_leg(cfx, torch, pristine, A, ipiv, n, v, L, args.lookahead, work, stream)
+    delayed = None
+    if args.delays and args.delay == 1:
+        delayed = delayed_leg(cfx, torch, pristine, A, n, v, L, args.lookahead, work, stream,
+                              [int(x) for x in args.delays.split(",") if x])
 
     flops = 2.0 * n ** 3 / 3.0 + 2.0 * n * n
     value = flops / (ms / 1e3) / 1e12
@@ -617,6 +685,8 @@ def main():
     }
     if masked is not None:
         out["row_masking"] = masked
+    if delayed is not None:
+        out["tile_stationary"] = delayed
     del pristine, A, work
     torch.cuda.empty_cache()
     if not args.no_ir:

@@ -113,6 +113,23 @@ int cfx_overlap_tuning(cfx_handle *h, int32_t *schur_workgroups, int32_t *chunk_
 int cfx_set_overlap_tuning(cfx_handle *h, int32_t schur_workgroups, int32_t chunk_cols,
                            int32_t one_stream);
 
+/* Tile-stationary schedule of cfx_getrf (rows interchanged; not used by
+ * cfx_getrf_masked, which returns CFX_ENOTSUP when it is set): with delay
+ * d > 1 the trailing matrix receives the Schur updates of d panels at once,
+ * C -= [L21_1 .. L21_d] [U12_1; ..; U12_d] (K = d v), so every C tile is
+ * read and written once per d panels instead of once per panel (the S2
+ * subcomputations of the I/O-optimal schedule, Sec. 6, with K toward
+ * sqrt(M); COnfLUX's per-step cost, Sec. 7.4).  Inside a batch each
+ * panel's columns, and its pivot rows' trailing columns, first receive the
+ * batch's earlier panels (thin updates).  The pivots and the arithmetic of
+ * each element are those of Alg. 1 up to the grouping of the sums (d
+ * panels' products accumulate together), so the factors agree with d = 1
+ * to rounding.  d in 1..8 (default 1); the workspace of low-precision
+ * factorisations grows with d (query cfx_getrf_buffer_size after setting
+ * it).  Set returns -2 for an invalid d. */
+int cfx_schur_delay(cfx_handle *h, int32_t *delay);
+int cfx_set_schur_delay(cfx_handle *h, int32_t delay);
+
 /* Static description of the library build (host memory, NUL-terminated). */
 const char *cfx_version(void);
 

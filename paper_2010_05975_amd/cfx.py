@@ -124,6 +124,8 @@ def lib():
         L.cfx_profile_begin.argtypes = [vp]
         L.cfx_profile_end.argtypes = [vp, C.POINTER(Profile)]
         L.cfx_getrs_check.argtypes = [vp, vp]
+        L.cfx_schur_delay.argtypes = [vp, vp]
+        L.cfx_set_schur_delay.argtypes = [vp, i32]
         L.cfx_getrf_masked.argtypes = [vp, i64, vp, i64, vp, vp, vp, C.POINTER(LuOpts), vp, sz, vp]
         L.cfx_getrs_masked.argtypes = [vp, i64, i64, vp, i64, vp, vp, i64, vp]
         L.cfx_schur_update_buffer_size.argtypes = [vp, i32, i64, i64, i64, C.POINTER(sz)]
@@ -131,7 +133,7 @@ def lib():
         L.cfx_set_solve_spin_limit.argtypes = [vp, i32]
         for f in ("cfx_create", "cfx_destroy", "cfx_getrf_buffer_size", "cfx_getrf",
                   "cfx_tslu", "cfx_getrs", "cfx_getrs_check", "cfx_set_solve_spin_limit",
-                  "cfx_getrf_masked", "cfx_getrs_masked",
+                  "cfx_getrf_masked", "cfx_getrs_masked", "cfx_schur_delay", "cfx_set_schur_delay",
                   "cfx_schur_update_buffer_size", "cfx_schur_update",
                   "cfx_gesv_ir_buffer_size", "cfx_gesv_ir",
                   "cfx_gesv_batched_buffer_size", "cfx_gesv_batched", "cfx_batched_tune",
@@ -434,6 +436,19 @@ def batched_set_tuning(vb, handle=None):
     h = handle or default_handle()
     t = (C.c_int32 * 5)(*vb)
     _check("cfx_batched_set_tuning", lib().cfx_batched_set_tuning(h.h, t))
+
+
+def schur_delay(handle=None):
+    """cfx_schur_delay: panels per trailing update (tile-stationary schedule)."""
+    h = handle or default_handle()
+    d = C.c_int32()
+    _check("cfx_schur_delay", lib().cfx_schur_delay(h.h, C.byref(d)))
+    return d.value
+
+
+def set_schur_delay(delay, handle=None):
+    h = handle or default_handle()
+    _check("cfx_set_schur_delay", lib().cfx_set_schur_delay(h.h, int(delay)))
 
 
 def overlap_tuning(handle=None):

@@ -72,6 +72,7 @@ struct cfx_handle {
     // compute units to the tournament at little cost of its own)
     int schur_wgs = -1;
     int64_t la_chunk = 512;         // columns per overlapped Schur launch
+    int delay = 1;                  // panels per trailing update (tile-stationary schedule)
     bool one_stream = false;        // lookahead launches on the caller's stream only
     // batched: panel width per size class (the tuner's table) and the graph
     // of the last batched call, replayed when the arguments repeat
@@ -99,7 +100,7 @@ struct Layout {
         off_utg, off_rtg, off_mp, total;
 };
 
-static Layout layout(int64_t n, int v, int leaves, int precision)
+static Layout layout(int64_t n, int v, int leaves, int precision, int delay)
 {
     Layout L{};
     int64_t h0 = (n + leaves - 1) / leaves;
@@ -122,20 +123,21 @@ static Layout layout(int64_t n, int v, int leaves, int precision)
     L.off_utg = o;   o = align_up(o + (size_t)L.max_nodes * 32 * kMaxV * sizeof(double));
     L.off_rtg = o;   o = align_up(o + (size_t)L.max_nodes * 32 * 40 * sizeof(double));
     L.off_mp = o;
-    if (precision != CFX_PREC_FP64) o = align_up(o + lp_pack_bytes(precision, n, n, v));
+    // packed operands of the widest low-precision update (K = delay v)
+    if (precision != CFX_PREC_FP64) o = align_up(o + lp_pack_bytes(precision, n, n, v * delay));
     L.total = o;
     return L;
 }
 
-size_t workspace_bytes(int64_t n, int v, int leaves, int precision)
+size_t workspace_bytes(int64_t n, int v, int leaves, int precision, int delay)
 {
-    return layout(n, v, leaves, precision).total;
+    return layout(n, v, leaves, precision, delay).total;
 }
 
 int carve_workspace(void *work, size_t bytes, int64_t n, int v, int leaves, int precision,
-                    Workspace *ws)
+                    Workspace *ws, int delay)
 {
-    Layout L = layout(n, v, leaves, precision);
+    Layout L = layout(n, v, leaves, precision, delay);
     if (bytes < L.total) return CFX_ENOMEM;
     char *b = static_cast<char *>(work);
     ws->S = reinterpret_cast<double *>(b + L.off_S);
@@ -198,7 +200,7 @@ struct IrLayout {
     size_t off_F, off_ipiv, off_perm, off_info, off_getrf, getrf_bytes, off_vec, total;
 };
 
-static IrLayout ir_layout(int64_t n, const cfx_ir_opts *o)
+static IrLayout ir_layout(int64_t n, const cfx_ir_opts *o, int delay)
 {
     IrLayout L{};
     size_t p = 0;
@@ -207,7 +209,7 @@ static IrLayout ir_layout(int64_t n, const cfx_ir_opts *o)
     L.off_perm = p;  p = align_up(p + (size_t)n * sizeof(int32_t));
     L.off_info = p;  p = align_up(p + sizeof(int32_t));
     L.off_getrf = p;
-    L.getrf_bytes = workspace_bytes(n, o->lu.v, o->lu.leaves, o->lu.precision);
+    L.getrf_bytes = workspace_bytes(n, o->lu.v, o->lu.leaves, o->lu.precision, delay);
     p = align_up(p + L.getrf_bytes);
     L.off_vec = p;   p = align_up(p + ir_vec_bytes(n, o->gmres_restart));
     L.total = p;
@@ -317,13 +319,133 @@ int cfx_getrf_buffer_size(cfx_handle *h, int64_t n, const cfx_lu_opts *opts, siz
     if (n < 0) return -2;
     if (check_opts(opts)) return check_opts(opts) == 2 ? CFX_ENOTSUP : -3;
     if (!bytes) return -4;
-    *bytes = workspace_bytes(n, opts->v, opts->leaves, opts->precision);
+    *bytes = workspace_bytes(n, opts->v, opts->leaves, opts->precision, h->delay);
     return CFX_OK;
 }
 
 }  // extern "C"
 
 namespace cfx {
+
+// The tile-stationary schedule (the handle's delay d > 1): the trailing
+// matrix receives the Schur updates of d panels at once, C -= [L21 ...]
+// [U12; ...] with K = d v, so each C tile is read and written once per d
+// panels while it accumulates d v products in registers: the S2
+// subcomputations of the I/O-optimal schedule (Sec. 6, X-partition with
+// rho = sqrt(M)/2; COnfLUX's per-step cost, Sec. 7.4) take K toward
+// sqrt(M).  Inside a batch only what the next steps read is brought up to
+// date: panel k's columns receive the batch's earlier panels before its
+// tournament, and its pivot rows' trailing columns before U12 (both K =
+// k - K0 updates of thin blocks).  Interchanges move whole rows, so the
+// batch's L21 columns stay aligned with the rows of the trailing matrix.
+// The first tournament of each batch runs beside the batch-end update
+// (lookahead); the others have only the thin updates beside them.
+static int getrf_run_delayed(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *ipiv, int32_t *info,
+                             const cfx_lu_opts *opts, const Workspace &ws, hipStream_t st)
+{
+    const int prec = opts->precision, v = opts->v, Lv = opts->leaves, d = h->delay;
+    const bool la = opts->lookahead != 0;
+    hipStream_t side = h->one_stream ? st : h->side;
+    Profiler &pf = h->prof;
+    auto at = [&](int64_t r, int64_t c) { return A + r * lda + c; };
+    // A[r:r+m, c:c+nc] -= A[r:r+m, k0:k0+K] A[k0:k0+K, c:c+nc], one launch
+    auto update = [&](int64_t r, int64_t c, int64_t m, int64_t nc, int64_t k0, int64_t K, hipStream_t s) -> int {
+        if (m <= 0 || nc <= 0 || K <= 0) return CFX_OK;
+        hipEvent_t e = pf.begin(s);
+        int rc;
+        if (prec == CFX_PREC_FP64) {
+            rc = launch_schur_f64(at(r, k0), lda, at(k0, c), lda, at(r, c), lda, m, nc, (int)K, 0, s);
+        } else {
+            rc = launch_pack_lp(prec, at(r, k0), lda, m, at(k0, c), lda, nc, (int)K, ws.scratch, s);
+            if (!rc) rc = launch_schur_lp(prec, ws.scratch, m, nc, (int)K, 0, nc, at(r, c), lda, 0, s);
+        }
+        pf.end(PH_SCHUR, e, s, 2.0 * (double)m * (double)nc * (double)K);
+        return rc;
+    };
+    auto tslu = [&](int64_t k, hipStream_t s) -> int {
+        const int vb = (int)((n - k) < v ? (n - k) : v);
+        hipEvent_t e = pf.begin(s);
+        const int rc = launch_tslu(at(k, k), lda, k, n - k, vb, Lv, ws, nullptr, ipiv, info, s);
+        pf.end(PH_TSLU, e, s);
+        return rc;
+    };
+    int rc;
+    if ((rc = tslu(0, st))) return rc;
+    bool tslu_on_side = false;
+    for (int64_t K0 = 0; K0 < n; K0 += (int64_t)d * v) {
+        const int64_t kE = (K0 + (int64_t)d * v) < n ? K0 + (int64_t)d * v : n;
+        for (int64_t k = K0; k < kE; k += v) {
+            const int vb = (int)((n - k) < v ? (n - k) : v);
+            const int64_t m = n - k - vb;
+            if (k > K0) {
+                // panel k's columns receive the batch's earlier panels
+                if ((rc = update(k, k, n - k, vb, K0, k - K0, st))) return rc;
+                if ((rc = tslu(k, st))) return rc;
+            } else if (tslu_on_side) {
+                CFX_HIP(hipStreamWaitEvent(st, h->ev_tslu, 0));
+                tslu_on_side = false;
+            } else if (k > 0) {
+                if ((rc = tslu(k, st))) return rc;
+            }
+            hipEvent_t e = pf.begin(st);
+            if ((rc = launch_laswp(A, lda, n, k, vb, ws, st))) return rc;
+            pf.end(PH_LASWP, e, st);
+            if (m > 0) {
+                if (k == K0) {
+                    e = pf.begin(st);
+                    if ((rc = launch_trsm(A, lda, k, vb, m, st))) return rc;
+                    pf.end(PH_TRSM, e, st);
+                } else {
+                    e = pf.begin(st);
+                    if ((rc = launch_trsm_first(A, lda, k, vb, m, 0, st))) return rc;   // L21
+                    pf.end(PH_TRSM, e, st);
+                    // the pivot rows' trailing columns receive the batch's earlier panels
+                    if ((rc = update(k, k + vb, vb, m, K0, k - K0, st))) return rc;
+                    e = pf.begin(st);
+                    if ((rc = launch_trsm_rest(A, lda, k, vb, m, 0, st))) return rc;    // U12
+                    pf.end(PH_TRSM, e, st);
+                }
+            }
+            if (pf.on) ++pf.panels;
+        }
+        // the batch-end update of rows and columns kE.. with K = kE - K0
+        const int64_t m = n - kE, K = kE - K0;
+        if (m <= 0) break;
+        const int vbn = (int)(m < v ? m : v);
+        const double *Lb = at(kE, K0), *Ub = at(K0, kE);
+        double *Cb = at(kE, kE);
+        auto part = [&](int64_t c0, int64_t cw, int wgs, hipStream_t s) -> int {
+            if (prec == CFX_PREC_FP64)
+                return launch_schur_f64(Lb, lda, Ub + c0, lda, Cb + c0, lda, m, cw, (int)K, wgs, s);
+            return launch_schur_lp(prec, ws.scratch, m, m, (int)K, c0, cw, Cb, lda, wgs, s);
+        };
+        hipEvent_t e = pf.begin(st);
+        if (prec != CFX_PREC_FP64 && (rc = launch_pack_lp(prec, Lb, lda, m, Ub, lda, m, (int)K, ws.scratch, st)))
+            return rc;
+        if ((rc = part(0, vbn, 0, st))) return rc;       // the next panel's columns first
+        pf.end(PH_SCHUR, e, st, 2.0 * (double)m * vbn * (double)K);
+        if (la) {
+            CFX_HIP(hipEventRecord(h->ev_panel, st));
+            CFX_HIP(hipStreamWaitEvent(side, h->ev_panel, 0));
+            if ((rc = tslu(kE, side))) return rc;
+            CFX_HIP(hipEventRecord(h->ev_tslu, side));
+            tslu_on_side = true;
+        }
+        const int64_t chunk = la ? h->la_chunk : m;
+        const int wgs = la ? (h->schur_wgs >= 0 ? h->schur_wgs : (prec == CFX_PREC_FP64 ? 0 : cfx::kLpSchurWgs)) : 0;
+        if (vbn < m) {
+            e = pf.begin(st);
+            int nl = 0;
+            for (int64_t c0 = vbn; c0 < m; c0 += chunk, ++nl) {
+                const int64_t cw = (m - c0) < chunk ? (m - c0) : chunk;
+                if ((rc = part(c0, cw, wgs, st))) return rc;
+            }
+            pf.end(PH_SCHUR, e, st, 2.0 * (double)m * (double)(m - vbn) * (double)K, nl);
+        }
+    }
+    if (tslu_on_side) CFX_HIP(hipStreamWaitEvent(st, h->ev_tslu, 0));
+    return CFX_OK;
+}
 
 // The host loop of Alg. 1 shared by cfx_getrf (rm null: rows interchanged)
 // and cfx_getrf_masked (rm: the row map, rows never moved).  Arguments are
@@ -341,8 +463,12 @@ static int getrf_run(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *
         if (h0 > kMaxLeafRows) return CFX_ENOTSUP;
     }
     Workspace ws;
-    if ((rc = carve_workspace(work, work_bytes, n, v, L, opts->precision, &ws))) return rc;
+    if ((rc = carve_workspace(work, work_bytes, n, v, L, opts->precision, &ws, h->delay))) return rc;
     if (rm && (rc = launch_rowmap_init(rm, n, st))) return rc;
+    if (h->delay > 1) {
+        if (rm) return CFX_ENOTSUP;
+        return getrf_run_delayed(h, n, A, lda, ipiv, info, opts, ws, st);
+    }
 
     // Per panel k: the tournament's panel (W, row0 = k; with a row map W
     // points at row 0 of column k), the interchanges (or the row-map update),
@@ -518,7 +644,7 @@ int cfx_gesv_ir_buffer_size(cfx_handle *h, int64_t n, int64_t nrhs, const cfx_ir
     if (nrhs < 0) return -3;
     if (int c = check_ir_opts(opts)) return c == 2 ? CFX_ENOTSUP : -4;
     if (!bytes) return -5;
-    *bytes = ir_layout(n, opts).total;
+    *bytes = ir_layout(n, opts, h->delay).total;
     return CFX_OK;
 }
 
@@ -537,7 +663,7 @@ int cfx_gesv_ir(cfx_handle *h, int64_t n, int64_t nrhs, const double *A, int64_t
     if (ldx < (nrhs > 1 ? nrhs : 1)) return -9;
     if (int c = check_ir_opts(opts)) return c == 2 ? CFX_ENOTSUP : -10;
     if (!rep) return -11;
-    const IrLayout lay = ir_layout(n, opts);
+    const IrLayout lay = ir_layout(n, opts, h->delay);
     if (n > 0 && (!work || (reinterpret_cast<uintptr_t>(work) & 255))) return -12;
     if (n > 0 && work_bytes < lay.total) return CFX_ENOMEM;
     cfx_ir_report r{};
@@ -779,6 +905,22 @@ int cfx_set_overlap_tuning(cfx_handle *h, int32_t schur_workgroups, int32_t chun
     h->schur_wgs = schur_workgroups;
     h->la_chunk = chunk_cols;
     h->one_stream = one_stream != 0;
+    return CFX_OK;
+}
+
+int cfx_schur_delay(cfx_handle *h, int32_t *delay)
+{
+    if (!h) return -1;
+    if (!delay) return -2;
+    *delay = h->delay;
+    return CFX_OK;
+}
+
+int cfx_set_schur_delay(cfx_handle *h, int32_t delay)
+{
+    if (!h) return -1;
+    if (delay < 1 || delay > 8) return -2;
+    h->delay = delay;
     return CFX_OK;
 }
 

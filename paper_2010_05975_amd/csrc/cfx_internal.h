@@ -39,9 +39,11 @@ struct Workspace {
 };
 
 // Bytes of workspace for order n and options; and the carve-up.
-size_t workspace_bytes(int64_t n, int v, int leaves, int precision);
+// delay: panels per trailing update of the tile-stationary schedule (the
+// low-precision packed operands then hold K = delay v).
+size_t workspace_bytes(int64_t n, int v, int leaves, int precision, int delay = 1);
 int carve_workspace(void *work, size_t bytes, int64_t n, int v, int leaves,
-                    int precision, Workspace *ws);
+                    int precision, Workspace *ws, int delay = 1);
 
 // Tournament pivoting of the rows x vb panel at W (stride ldw); panel row i
 // is global row row0 + i.  When `ipiv` is set the root also turns the
