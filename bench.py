@@ -149,6 +149,40 @@ def schur_replay(cfx, torch, n, v, chunk, seed, delay=1):
     return launches, flops, dt
 
 
+def tslu_bench(cfx, torch, n, v, L, seed, reps=5):
+    """The tournament alone (cfx_tslu: leaves and playoff rounds of one
+    panel, no other work on the device) on N(0,1) panels of the heights the
+    factorisation meets (rows = n - k), with the factorisation's leaf count,
+    plus a single 2v-row node (one leaf of a merge's size): median time per
+    call and per pivot step (HIP events)."""
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    out = []
+    cases = [(r, L) for r in (n, (3 * n) // 4, n // 2, n // 4, n // 8, 4 * v)] + [(2 * v, 1), (v, 1)]
+    for rows, leaves in cases:
+        W = torch.randn(rows, v, dtype=torch.float64, device=dev, generator=g)
+        work = cfx.workspace(rows, v, leaves, "fp64", 0, dev)
+        times = []
+        for it in range(reps + 1):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            cfx.tslu(W, v, leaves, work=work)
+            e1.record()
+            torch.cuda.synchronize()
+            if it:
+                times.append(e0.elapsed_time(e1))
+        h = max(v, -(-rows // leaves))
+        nl = -(-rows // h)
+        levels = 1 + int(np.ceil(np.log2(nl))) if nl > 1 else 1
+        ms = float(np.median(times))
+        out.append({"rows": rows, "leaves": leaves, "leaf_rows": h, "levels": levels, "ms": round(ms, 4),
+                    "us_per_pivot_step": round(1e3 * ms / (levels * v), 3)})
+        log(f"tslu rows={rows} L={leaves}: {out[-1]}")
+        del W, work
+    return out
+
+
 def cpu_baseline(A_host, n, v, L, panels):
     from oracle import oracle as O
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -511,6 +545,9 @@ def main():
                          "used for the counter runs (no CPU baseline then)")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="end with a plain 1 GiB device copy (calibrates HBM byte counters)")
+    ap.add_argument("--tslu-bench", action="store_true",
+                    help="time the tournament alone (cfx_tslu) on panels of the factorisation's shapes and print "
+                         "the results")
     ap.add_argument("--schur-replay", action="store_true",
                     help="run only the Schur-complement launches of one factorisation (one stream) "
                          "and print their statistics; for counter runs")
@@ -533,6 +570,9 @@ def main():
 
     n, v, L = args.n, args.v, args.leaves
     dev = torch.device("cuda:0")
+    if args.tslu_bench:
+        print(json.dumps({"tslu_bench": tslu_bench(cfx, torch, n, v, L, args.seed)}), flush=True)
+        return
     if args.schur_replay:
         chunk = args.chunk or cfx.overlap_tuning()[1]
         launches, flops, dt = schur_replay(cfx, torch, n, v, chunk, args.seed, args.delay)
