@@ -245,6 +245,23 @@ int cfx_getrs_masked(cfx_handle *h, int64_t n, int64_t nrhs, const double *LU,
 int cfx_getrs_check(cfx_handle *h, void *stream);
 int cfx_set_solve_spin_limit(cfx_handle *h, int32_t polls);
 
+/* cfx_getrs for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same solve, with the same arguments, results and errors, but its
+ * permutation, gathered right-hand sides and counters live in a fixed
+ * device array of 32 MiB per GPU (set up by cfx_create; held until the
+ * process ends) instead of the handle's growable scratch.  No call on this
+ * path allocates or frees memory.
+ *   Limit: 256 + 4 n (rounded up to 256) + 8 n nrhs bytes <= 32 MiB (e.g.
+ *   n = 32768 with up to 127 right-hand sides); larger problems return
+ *   CFX_ENOTSUP without doing anything.
+ *   Every call on one GPU shares that array: calls that overlap on the
+ *   device race (order them on one stream, or through events).  The
+ *   give-up flag of its one-launch solve is cleared at the start of each
+ *   call and read by cfx_getrs_check. */
+int cfx_getrs_noalloc(cfx_handle *h, int64_t n, int64_t nrhs, const double *LU,
+                      int64_t lda, const int32_t *ipiv, double *B, int64_t ldb,
+                      void *stream);
 
 /* Mixed-precision solve with iterative refinement.  The paper computes the
  * factorisation only; refinement is the standard GMRES-IR of Carson and

@@ -128,12 +128,14 @@ def lib():
         L.cfx_set_schur_delay.argtypes = [vp, i32]
         L.cfx_getrf_masked.argtypes = [vp, i64, vp, i64, vp, vp, vp, C.POINTER(LuOpts), vp, sz, vp]
         L.cfx_getrs_masked.argtypes = [vp, i64, i64, vp, i64, vp, vp, i64, vp]
+        L.cfx_getrs_noalloc.argtypes = [vp, i64, i64, vp, i64, vp, vp, i64, vp]
         L.cfx_schur_update_buffer_size.argtypes = [vp, i32, i64, i64, i64, C.POINTER(sz)]
         L.cfx_schur_update.argtypes = [vp, i32, i64, i64, i64, vp, i64, vp, i64, vp, i64, i32, vp, sz, vp]
         L.cfx_set_solve_spin_limit.argtypes = [vp, i32]
         for f in ("cfx_create", "cfx_destroy", "cfx_getrf_buffer_size", "cfx_getrf",
                   "cfx_tslu", "cfx_getrs", "cfx_getrs_check", "cfx_set_solve_spin_limit",
                   "cfx_getrf_masked", "cfx_getrs_masked", "cfx_schur_delay", "cfx_set_schur_delay",
+                  "cfx_getrs_noalloc",
                   "cfx_schur_update_buffer_size", "cfx_schur_update",
                   "cfx_gesv_ir_buffer_size", "cfx_gesv_ir",
                   "cfx_gesv_batched_buffer_size", "cfx_gesv_batched", "cfx_batched_tune",
@@ -315,6 +317,18 @@ def schur_update(L21, U12, Cm, precision="fp64", max_workgroups=0, work=None, st
         h.h, p, m, n, K, _ptr(L21), ldl, _ptr(U12), ldu, _ptr(Cm), ldc, int(max_workgroups),
         _ptr(work), 0 if work is None else work.numel(), _stream(stream)))
     return Cm
+
+
+def getrs_noalloc(LU, ipiv, B, stream=None, handle=None):
+    """cfx_getrs_noalloc: as getrs, with the fixed per-device scratch."""
+    h = handle or default_handle()
+    lda = _mat(LU, "LU")
+    Bm = B.view(-1, 1) if B.dim() == 1 else B
+    ldb = _mat(Bm, "B")
+    n, nrhs = Bm.shape
+    _check("cfx_getrs_noalloc", lib().cfx_getrs_noalloc(h.h, n, nrhs, _ptr(LU), lda, _ptr(ipiv), _ptr(Bm),
+                                                        ldb, _stream(stream)))
+    return B
 
 
 def getrs_check(stream=None, handle=None):

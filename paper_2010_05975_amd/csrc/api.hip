@@ -64,6 +64,7 @@ struct cfx_handle {
     hipEvent_t ev_getrs = nullptr;  // the last getrs on this handle (scratch reuse)
     bool getrs_issued = false;
     int spin_limit = cfx::kSolveSpinLimit;
+    void *na_scratch = nullptr;     // this device's scratch of cfx_getrs_noalloc
     cfx::Profiler prof;
     int cu_count = 256;
     // grid bound of the Schur updates that overlap the next tournament
@@ -250,6 +251,10 @@ int cfx_create(cfx_handle **h)
         cus > 0)
         p->cu_count = cus;
     if (int rc = init_kernel_attributes()) {
+        cfx_destroy(p);
+        return rc;
+    }
+    if (int rc = noalloc_scratch(p->device, &p->na_scratch)) {
         cfx_destroy(p);
         return rc;
     }
@@ -1024,13 +1029,71 @@ int cfx_schur_update(cfx_handle *h, int32_t precision, int64_t m, int64_t n, int
     return launch_schur_lp(precision, work, m, n, (int)K, 0, n, C, ldc, max_workgroups, st);
 }
 
+int cfx_getrs_noalloc(cfx_handle *h, int64_t n, int64_t nrhs, const double *LU, int64_t lda,
+                      const int32_t *ipiv, double *B, int64_t ldb, void *stream)
+{
+    if (!h) return -1;
+    if (n < 0 || n > INT32_MAX) return -2;
+    if (nrhs < 0) return -3;
+    if (!LU && n > 0) return -4;
+    if (lda < (n > 1 ? n : 1)) return -5;
+    if (!ipiv && n > 0) return -6;
+    if (!B && n > 0 && nrhs > 0) return -7;
+    if (ldb < (nrhs > 1 ? nrhs : 1)) return -8;
+    if (n == 0 || nrhs == 0) return CFX_OK;
+    // counters | permutation | gathered right-hand sides, all in the
+    // device's fixed scratch (no allocation on this path)
+    const size_t off_perm = kTrsvSyncBytes;
+    const size_t off_tmp = off_perm + align_up((size_t)n * sizeof(int32_t));
+    if ((size_t)nrhs > (kNoAllocScratchBytes - off_tmp) / sizeof(double) / (size_t)n) return CFX_ENOTSUP;
+    if (!h->na_scratch) return CFX_EHIP;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char *base = static_cast<char *>(h->na_scratch);
+    int32_t *sync = reinterpret_cast<int32_t *>(base);
+    // the give-up flag starts at zero for this call (the tickets and solved
+    // counts are cleared by the solve itself); a fill kernel, not a memset
+    int rc = launch_set_int(sync + 4, 0, st);
+    if (rc) return rc;
+    return launch_getrs(n, nrhs, LU, lda, ipiv, B, ldb, reinterpret_cast<int32_t *>(base + off_perm),
+                        reinterpret_cast<double *>(base + off_tmp), sync, st, h->spin_limit);
+}
+
+int cfx_getrs_masked(cfx_handle *h, int64_t n, int64_t nrhs, const double *LU, int64_t lda,
+                     const int32_t *rowmap, double *B, int64_t ldb, void *stream)
+{
+    if (!h) return -1;
+    if (n < 0 || n > INT32_MAX) return -2;
+    if (nrhs < 0) return -3;
+    if (!LU && n > 0) return -4;
+    if (lda < (n > 1 ? n : 1)) return -5;
+    if (!rowmap && n > 0) return -6;
+    if (!B && n > 0 && nrhs > 0) return -7;
+    if (ldb < (nrhs > 1 ? nrhs : 1)) return -8;
+    if (n == 0 || nrhs == 0) return CFX_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t need = (size_t)n * nrhs * sizeof(double);
+    int rc = ensure_scratch(h, need);
+    if (rc) return rc;
+    if (h->getrs_issued) CFX_HIP(hipStreamWaitEvent(st, h->ev_getrs, 0));
+    rc = launch_getrs(n, nrhs, LU, lda, nullptr, B, ldb, nullptr, static_cast<double *>(h->scratch), h->gsync, st,
+                      h->spin_limit, rowmap);
+    if (rc) return rc;
+    CFX_HIP(hipEventRecord(h->ev_getrs, st));
+    h->getrs_issued = true;
+    return CFX_OK;
+}
+
 int cfx_getrs_check(cfx_handle *h, void *stream)
 {
     if (!h) return -1;
-    bool gave_up = false;
+    bool gave_up = false, na_gave_up = false;
     int rc = read_solve_flag(h->gsync, static_cast<hipStream_t>(stream), &gave_up);
     if (rc) return rc;
-    return gave_up ? CFX_ESOLVE : CFX_OK;
+    if (h->na_scratch &&
+        (rc = read_solve_flag(static_cast<int32_t *>(h->na_scratch), static_cast<hipStream_t>(stream),
+                              &na_gave_up)))
+        return rc;
+    return (gave_up || na_gave_up) ? CFX_ESOLVE : CFX_OK;
 }
 
 int cfx_set_solve_spin_limit(cfx_handle *h, int32_t polls)

@@ -60,6 +60,12 @@ int launch_tslu(const double *W, int64_t ldw, int64_t row0, int64_t rows, int vb
 // Kernel attributes (dynamic LDS limits) of the current device; called by
 // cfx_create, so that no launch path sets them.
 int init_kernel_attributes();
+
+// Scratch of the allocation-free solve: a device array of this many bytes
+// per GPU.  noalloc_scratch returns its device address on `device`, which
+// must be the current device (looked up once per device, then cached).
+constexpr size_t kNoAllocScratchBytes = (size_t)32 << 20;
+int noalloc_scratch(int device, void **ptr);
 // The handle's spin limit of the one-launch triangular solves.
 int solve_spin_limit(const cfx_handle *h);
 
