@@ -113,6 +113,19 @@ int cfx_overlap_tuning(cfx_handle *h, int32_t *schur_workgroups, int32_t *chunk_
 int cfx_set_overlap_tuning(cfx_handle *h, int32_t schur_workgroups, int32_t chunk_cols,
                            int32_t one_stream);
 
+/* Launch shape of the tournament (scheduling only: the same selection and
+ * values bit for bit).  Nodes of at most node_rows rows (every merge node
+ * at v <= 256, and the short leaves of late panels, when node_rows = 512)
+ * run as ONE launch each: one workgroup takes the node's pivot
+ * steps block by block and applies each block's rank update to the node's
+ * remaining columns itself.  Taller nodes, and every node when node_rows =
+ * 0 (the default: one workgroup's update was measured slower than the
+ * spread one), take two launches per 32-column block (the pivot steps in
+ * one workgroup, the update spread over many).  node_rows in 0..512; set
+ * returns -2 otherwise. */
+int cfx_tournament_fusion(cfx_handle *h, int32_t *node_rows);
+int cfx_set_tournament_fusion(cfx_handle *h, int32_t node_rows);
+
 /* Tile-stationary schedule of cfx_getrf (rows interchanged; not used by
  * cfx_getrf_masked, which returns CFX_ENOTSUP when it is set): with delay
  * d > 1 the trailing matrix receives the Schur updates of d panels at once,

@@ -125,6 +125,8 @@ def lib():
         L.cfx_profile_end.argtypes = [vp, C.POINTER(Profile)]
         L.cfx_getrs_check.argtypes = [vp, vp]
         L.cfx_schur_delay.argtypes = [vp, vp]
+        L.cfx_tournament_fusion.argtypes = [vp, vp]
+        L.cfx_set_tournament_fusion.argtypes = [vp, i32]
         L.cfx_set_schur_delay.argtypes = [vp, i32]
         L.cfx_getrf_masked.argtypes = [vp, i64, vp, i64, vp, vp, vp, C.POINTER(LuOpts), vp, sz, vp]
         L.cfx_getrs_masked.argtypes = [vp, i64, i64, vp, i64, vp, vp, i64, vp]
@@ -135,6 +137,7 @@ def lib():
         for f in ("cfx_create", "cfx_destroy", "cfx_getrf_buffer_size", "cfx_getrf",
                   "cfx_tslu", "cfx_getrs", "cfx_getrs_check", "cfx_set_solve_spin_limit",
                   "cfx_getrf_masked", "cfx_getrs_masked", "cfx_schur_delay", "cfx_set_schur_delay",
+                  "cfx_tournament_fusion", "cfx_set_tournament_fusion",
                   "cfx_getrs_noalloc",
                   "cfx_schur_update_buffer_size", "cfx_schur_update",
                   "cfx_gesv_ir_buffer_size", "cfx_gesv_ir",
@@ -450,6 +453,19 @@ def batched_set_tuning(vb, handle=None):
     h = handle or default_handle()
     t = (C.c_int32 * 5)(*vb)
     _check("cfx_batched_set_tuning", lib().cfx_batched_set_tuning(h.h, t))
+
+
+def tournament_fusion(handle=None):
+    """cfx_tournament_fusion: nodes of at most this many rows run as one launch."""
+    h = handle or default_handle()
+    r = C.c_int32()
+    _check("cfx_tournament_fusion", lib().cfx_tournament_fusion(h.h, C.byref(r)))
+    return r.value
+
+
+def set_tournament_fusion(node_rows, handle=None):
+    h = handle or default_handle()
+    _check("cfx_set_tournament_fusion", lib().cfx_set_tournament_fusion(h.h, int(node_rows)))
 
 
 def schur_delay(handle=None):

@@ -74,6 +74,7 @@ struct cfx_handle {
     int schur_wgs = -1;
     int64_t la_chunk = 512;         // columns per overlapped Schur launch
     int delay = 1;                  // panels per trailing update (tile-stationary schedule)
+    int fuse_rows = cfx::kFuseRowsDefault;  // tournament nodes up to this height run as one launch
     bool one_stream = false;        // lookahead launches on the caller's stream only
     // batched: panel width per size class (the tuner's table) and the graph
     // of the last batched call, replayed when the arguments repeat
@@ -370,7 +371,8 @@ static int getrf_run_delayed(cfx_handle *h, int64_t n, double *A, int64_t lda, i
     auto tslu = [&](int64_t k, hipStream_t s) -> int {
         const int vb = (int)((n - k) < v ? (n - k) : v);
         hipEvent_t e = pf.begin(s);
-        const int rc = launch_tslu(at(k, k), lda, k, n - k, vb, Lv, ws, nullptr, ipiv, info, s);
+        const int rc =
+            launch_tslu(at(k, k), lda, k, n - k, vb, Lv, ws, nullptr, ipiv, info, s, nullptr, h->fuse_rows);
         pf.end(PH_TSLU, e, s);
         return rc;
     };
@@ -512,7 +514,9 @@ static int getrf_run(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *
             const int vb = (int)((n - k) < v ? (n - k) : v);
             const int64_t m = n - k - vb;
             hipEvent_t e = pf.begin(st);
-            if ((rc = launch_tslu(panel_w(k), lda, k, n - k, vb, L, ws, nullptr, ipiv, info, st, rm))) return rc;
+            if ((rc = launch_tslu(panel_w(k), lda, k, n - k, vb, L, ws, nullptr, ipiv, info, st, rm,
+                                  h->fuse_rows)))
+                return rc;
             pf.end(PH_TSLU, e, st);
             e = pf.begin(st);
             if ((rc = swap(k, vb, st))) return rc;
@@ -541,7 +545,8 @@ static int getrf_run(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *
     {
         const int vb0 = (int)(n < v ? n : v);
         hipEvent_t e = pf.begin(st);
-        if ((rc = launch_tslu(panel_w(0), lda, 0, n, vb0, L, ws, nullptr, ipiv, info, st, rm))) return rc;
+        if ((rc = launch_tslu(panel_w(0), lda, 0, n, vb0, L, ws, nullptr, ipiv, info, st, rm, h->fuse_rows)))
+            return rc;
         pf.end(PH_TSLU, e, st);
     }
     bool tslu_on_side = false;
@@ -573,7 +578,8 @@ static int getrf_run(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *
             CFX_HIP(hipStreamWaitEvent(ts, h->ev_panel, 0));
             const int64_t kn = k + vb;
             e = pf.begin(ts);
-            if ((rc = launch_tslu(panel_w(kn), lda, kn, n - kn, vbn, L, ws, nullptr, ipiv, info, ts, rm)))
+            if ((rc = launch_tslu(panel_w(kn), lda, kn, n - kn, vbn, L, ws, nullptr, ipiv, info, ts, rm,
+                                  h->fuse_rows)))
                 return rc;
             pf.end(PH_TSLU, e, ts);
             CFX_HIP(hipEventRecord(h->ev_tslu, ts));
@@ -913,6 +919,22 @@ int cfx_set_overlap_tuning(cfx_handle *h, int32_t schur_workgroups, int32_t chun
     return CFX_OK;
 }
 
+int cfx_tournament_fusion(cfx_handle *h, int32_t *node_rows)
+{
+    if (!h) return -1;
+    if (!node_rows) return -2;
+    *node_rows = h->fuse_rows;
+    return CFX_OK;
+}
+
+int cfx_set_tournament_fusion(cfx_handle *h, int32_t node_rows)
+{
+    if (!h) return -1;
+    if (node_rows < 0 || node_rows > kFuseRows) return -2;
+    h->fuse_rows = node_rows;
+    return CFX_OK;
+}
+
 int cfx_schur_delay(cfx_handle *h, int32_t *delay)
 {
     if (!h) return -1;
@@ -956,7 +978,7 @@ int cfx_tslu(cfx_handle *h, int64_t rows, int64_t vb, const double *W, int64_t l
     int rc = carve_workspace(work, work_bytes, rows, (int)vb, leaves, CFX_PREC_FP64, &ws);
     if (rc) return rc;
     return launch_tslu(W, ldw, row0, rows, (int)vb, leaves, ws, piv, nullptr, nullptr,
-                       static_cast<hipStream_t>(stream));
+                       static_cast<hipStream_t>(stream), nullptr, h->fuse_rows);
 }
 
 int cfx_getrs(cfx_handle *h, int64_t n, int64_t nrhs, const double *LU, int64_t lda,

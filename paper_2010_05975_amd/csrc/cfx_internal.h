@@ -51,9 +51,15 @@ int carve_workspace(void *work, size_t bytes, int64_t n, int v, int leaves,
 // row-move plan (row0 is then the panel's diagonal row).  The root always
 // copies its factored top block to ws.lu00.  `piv_out` (may be null)
 // receives the selected global rows.
+// fuse_rows: nodes of at most this many rows (<= 512) run as one launch each
+// (pivot steps and the node's own updates in one workgroup); taller nodes
+// take two launches per column block.  Same results either way.
+constexpr int kFuseRows = 512;          // largest fusable node (2 v at v = 256)
+constexpr int kFuseRowsDefault = 0;    // measured slower than two launches
 int launch_tslu(const double *W, int64_t ldw, int64_t row0, int64_t rows, int vb,
                 int leaves, const Workspace &ws, int32_t *piv_out, int32_t *ipiv,
-                int32_t *info, hipStream_t st, const int32_t *rm = nullptr);
+                int32_t *info, hipStream_t st, const int32_t *rm = nullptr,
+                int fuse_rows = kFuseRowsDefault);
 // (rm: row masking; panel row i, global row row0 + i, is then physical row
 // rm[row0 + i] of W, which points at row 0 of the panel's first column.)
 

@@ -90,45 +90,7 @@ __device__ __forceinline__ void static_for(F &&f)
     static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double a)
-{
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(a), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(a), CTRL, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
-}
-
-__device__ __forceinline__ double readlane_f64(double a, int l)
-{
-    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(a), l),
-                            __builtin_amdgcn_readlane(__double2loint(a), l));
-}
-
 __device__ __forceinline__ double max2(double a, double b) { return b > a ? b : a; }
-
-template <int CTRL, int ROWS>
-__device__ __forceinline__ double dpp_rows_f64(double a)
-{
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(a), CTRL, ROWS, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(a), CTRL, ROWS, 0xF, false);
-    return __hiloint2double(hi, lo);
-}
-
-// Largest value over the wavefront, uniform across lanes: a DPP butterfly
-// inside each row of 16 lanes (xor 1, xor 2, half-mirror, mirror leave the
-// row's maximum in every lane of the row), then row broadcasts (lane 15 into
-// rows 1 and 3, lane 31 into rows 2 and 3) leave the wave's maximum in lane
-// 63.  Exact: only comparisons.
-__device__ __forceinline__ double wave_max(double a)
-{
-    a = max2(a, dpp_f64<0xB1>(a));   // quad_perm [1,0,3,2]
-    a = max2(a, dpp_f64<0x4E>(a));   // quad_perm [2,3,0,1]
-    a = max2(a, dpp_f64<0x141>(a));  // row_half_mirror
-    a = max2(a, dpp_f64<0x140>(a));  // row_mirror
-    a = max2(a, dpp_rows_f64<0x142, 0xA>(a));   // row_bcast:15
-    a = max2(a, dpp_rows_f64<0x143, 0xC>(a));   // row_bcast:31
-    return readlane_f64(a, 63);
-}
 
 // Smallest integer over the wavefront, uniform across lanes (same pattern).
 __device__ __forceinline__ int wave_min(int g)
@@ -149,6 +111,45 @@ __device__ __forceinline__ double score(double a)
     return s == s ? s : -0.5;
 }
 
+// The same order as an unsigned integer key (the bit patterns of
+// non-negative doubles order as the values do): 0 = not a candidate,
+// 1 = NaN, |a| -> its bits + 2.  Integer reductions keep the argmax off the
+// FP64 pipeline.
+__device__ __forceinline__ unsigned long long score_key(double a)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(a) & 0x7FFFFFFFFFFFFFFFull;
+    return b > 0x7FF0000000000000ull ? 1ull : b + 2ull;
+}
+
+// Largest unsigned value over the wavefront, uniform across lanes: a DPP
+// butterfly inside each row of 16 lanes (xor 1, xor 2, half-mirror,
+// mirror leave the row's maximum in every lane of the row), then row
+// broadcasts (lane 15 into rows 1 and 3, lane 31 into rows 2 and 3) leave
+// the wave's maximum in lane 63.
+__device__ __forceinline__ unsigned wave_max_u32(unsigned a)
+{
+    a = max(a, (unsigned)__builtin_amdgcn_update_dpp(0, (int)a, 0xB1, 0xF, 0xF, false));
+    a = max(a, (unsigned)__builtin_amdgcn_update_dpp(0, (int)a, 0x4E, 0xF, 0xF, false));
+    a = max(a, (unsigned)__builtin_amdgcn_update_dpp(0, (int)a, 0x141, 0xF, 0xF, false));
+    a = max(a, (unsigned)__builtin_amdgcn_update_dpp(0, (int)a, 0x140, 0xF, 0xF, false));
+    a = max(a, (unsigned)__builtin_amdgcn_update_dpp(0, (int)a, 0x142, 0xA, 0xF, false));
+    a = max(a, (unsigned)__builtin_amdgcn_update_dpp(0, (int)a, 0x143, 0xC, 0xF, false));
+    return (unsigned)__builtin_amdgcn_readlane((int)a, 63);
+}
+
+// Largest 64-bit key over the wavefront: the high words first; the low
+// words only among the lanes holding the largest high word (one lane in
+// the usual case, read directly).
+__device__ __forceinline__ unsigned long long wave_max_key(unsigned long long k)
+{
+    const unsigned hi = (unsigned)(k >> 32), lo = (unsigned)k;
+    const unsigned mh = wave_max_u32(hi);
+    const unsigned long long at = __ballot(hi == mh);
+    const unsigned ml = __popcll(at) == 1 ? (unsigned)__builtin_amdgcn_readlane((int)lo, __ffsll((long long)at) - 1)
+                                          : wave_max_u32(hi == mh ? lo : 0u);
+    return ((unsigned long long)mh << 32) | ml;
+}
+
 constexpr int UTLD = kMaxV;                 // row stride of the saved U rows
 
 template <int RPT>
@@ -157,9 +158,9 @@ struct BlockW {
 };
 
 struct __attribute__((aligned(16))) Slot {
-    double a;   // best score of the wave (-1: no candidate)
-    int g;      // smallest global row with that score
-    int p;      // its physical row in the node
+    double v;   // the wave's best row's value in the pivot column
+    int g;      // smallest global row with the best score
+    int p;      // its physical row in the node (-1: no candidate in the wave)
 };
 
 template <int BW, int NWV>
@@ -217,25 +218,17 @@ __device__ __forceinline__ int node_gid(const NodeArgs &p, const NodeRows &n, in
 // P: pivot steps and U rows of one block, one workgroup per node.
 // ---------------------------------------------------------------------------
 template <int RPT, int NT>
-__global__ __launch_bounds__(NT) void tslu_panel_kernel(NodeArgs p)
+__device__ __forceinline__ void panel_block(const NodeArgs &p, const int node, const int jb,
+                                            Lds<BlockW<RPT>::value, NT / 64> &s)
 {
-    // The tournament is the critical path and runs beside the Schur update:
-    // its (latency-bound) waves go first when they share a SIMD with the
-    // update's matrix-core waves.
-    __builtin_amdgcn_s_setprio(3);
     constexpr int BW = BlockW<RPT>::value;
     constexpr int NW = NT / 64;
-    using L = Lds<BW, NW>;
-    extern __shared__ double smem_raw[];
-    L &s = *reinterpret_cast<L *>(smem_raw);
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int node = blockIdx.x;
     const int vb = p.vb;
     const int rc = p.rc;
-    const int jb = p.jb;
 
     const NodeRows nr = node_rows(p, node);
     if (nr.promoted) {                        // unpaired: promoted unchanged
@@ -260,6 +253,29 @@ __global__ __launch_bounds__(NT) void tslu_panel_kernel(NodeArgs p)
     double *utg = p.utg + (size_t)node * 32 * UTLD;
     double *rtg = p.rtg + (size_t)node * 32 * 40;
 
+    // this thread's rows and their block columns are requested first: they
+    // do not depend on the node state below, so the loads overlap (rows
+    // selected in earlier blocks are loaded too but never used; the root's
+    // U-row copy below only writes such rows)
+    int gid[RPT];
+    static_for<RPT>([&](auto QC) {
+        constexpr int q = decltype(QC)::value;
+        const int pr = tid + q * NT;
+        gid[q] = pr < r ? node_gid(p, nr, pr) : INT_MAX;
+    });
+    // x: the block columns of this thread's rows.  The block is eliminated
+    // in sub-panels of SP columns: x[q][0..SP) always holds the current
+    // sub-panel (the register window shifts left by SP after each one), so
+    // only SP pivot steps are unrolled.
+    constexpr int SP = BW < 8 ? BW : 8;
+    double x[RPT][BW];
+    static_for<RPT>([&](auto QC) {
+        constexpr int q = decltype(QC)::value;
+        const int pr = tid + q * NT;
+#pragma unroll
+        for (int c = 0; c < BW; ++c)
+            x[q][c] = (pr < r && c < bwc) ? Sn[(size_t)(jb + c) * rc + pr] : 0.0;
+    });
     if (jb > 0) {
         for (int i = tid; i < jb; i += NT) {
             s.sel[i] = selg[i];
@@ -284,32 +300,17 @@ __global__ __launch_bounds__(NT) void tslu_panel_kernel(NodeArgs p)
 #pragma unroll
             for (int i = 0; i < BW; ++i) Sn[(size_t)(jb + c) * rc + s.selp[pj0 + i]] = u[i];
         }
-        __syncthreads();    // the copies above land before any row is loaded
+        __syncthreads();    // the copies above land before the block's outputs
     }
 
-    int gid[RPT];
     bool live[RPT];     // a real row that is not selected yet
     static_for<RPT>([&](auto QC) {
         constexpr int q = decltype(QC)::value;
         const int pr = tid + q * NT;
         live[q] = pr < r && !s.rowsel[pr];
-        gid[q] = pr < r ? node_gid(p, nr, pr) : INT_MAX;
     });
 
-    {   // x: the block columns of this thread's rows.  The block is
-        // eliminated in sub-panels of SP columns: x[q][0..SP) always holds
-        // the current sub-panel (the register window shifts left by SP
-        // after each one), so only SP pivot steps are unrolled.
-        constexpr int SP = BW < 8 ? BW : 8;
-        double x[RPT][BW];
-        static_for<RPT>([&](auto QC) {
-            constexpr int q = decltype(QC)::value;
-            const int pr = tid + q * NT;
-#pragma unroll
-            for (int c = 0; c < BW; ++c)
-                x[q][c] = (pr < r && c < bwc) ? Sn[(size_t)(jb + c) * rc + pr] : 0.0;
-        });
-
+    {
         for (int sp0 = 0; sp0 < bwc; sp0 += SP) {
             const int spc = (bwc - sp0) < SP ? (bwc - sp0) : SP;   // steps in this sub-panel
             const int rem = bwc - sp0 - SP;                        // block columns right of it
@@ -324,21 +325,22 @@ __global__ __launch_bounds__(NT) void tslu_panel_kernel(NodeArgs p)
                 constexpr int j = decltype(JC)::value;
                 if (j < spc) {
                     const int par = j & 1;
-                    // this thread's scores and the wave's best score (exact)
-                    double sc[RPT];
-                    double m = -1.0;
+                    // this thread's scores and the wave's best score (exact,
+                    // as integer keys of the same order)
+                    unsigned long long kq[RPT];
+                    unsigned long long km = 0;
                     static_for<RPT>([&](auto QC) {
                         constexpr int q = decltype(QC)::value;
-                        sc[q] = live[q] ? score(x[q][j]) : -1.0;
-                        m = max2(m, sc[q]);
+                        kq[q] = live[q] ? score_key(x[q][j]) : 0ull;
+                        km = kq[q] > km ? kq[q] : km;
                     });
-                    m = wave_max(m);
-                    // the smallest global row of this lane scoring m; one
-                    // lane holding m (the usual case) needs no reduction
+                    km = wave_max_key(km);
+                    // the smallest global row of this lane scoring km; one
+                    // lane holding it (the usual case) needs no reduction
                     int lg = INT_MAX;
                     static_for<RPT>([&](auto QC) {
                         constexpr int q = decltype(QC)::value;
-                        lg = sc[q] == m ? min(lg, gid[q]) : lg;
+                        lg = kq[q] == km ? min(lg, gid[q]) : lg;
                     });
                     const unsigned long long hits = __ballot(lg != INT_MAX);
                     const int wg = __popcll(hits) == 1 ? __builtin_amdgcn_readlane(lg, __ffsll((long long)hits) - 1)
@@ -350,34 +352,46 @@ __global__ __launch_bounds__(NT) void tslu_panel_kernel(NodeArgs p)
                         static_for<RPT>([&](auto QC) {
                             constexpr int q = decltype(QC)::value;
                             if (gid[q] == wg) {
-                                s.slot[par][wave] = Slot{m, wg, tid + q * NT};
+                                // km == 0: no candidate in this wave
+                                s.slot[par][wave] = Slot{x[q][j], wg, km ? tid + q * NT : -1};
 #pragma unroll
                                 for (int cc = j; cc < SP; ++cc) s.cand[par][wave][cc] = x[q][cc];
                             }
                         });
                     } else if (lane == 0) {
-                        s.slot[par][wave] = Slot{-1.0, INT_MAX, 0};
+                        s.slot[par][wave] = Slot{0.0, INT_MAX, -1};
                     }
                     __syncthreads();
                     // the node's winner: best score, ties to the smallest
                     // global row (some row is live at every step, so the
                     // best score is at least -0.5)
                     Slot sl[NW];
+                    double sw[NW];      // the waves' best scores (-1: none)
 #pragma unroll
-                    for (int w = 0; w < NW; ++w) sl[w] = s.slot[par][w];
-                    double M = sl[0].a;
+                    for (int w = 0; w < NW; ++w) {
+                        sl[w] = s.slot[par][w];
+                        sw[w] = sl[w].p < 0 ? -1.0 : score(sl[w].v);
+                    }
+                    double M = sw[0];
 #pragma unroll
-                    for (int w = 1; w < NW; ++w) M = max2(M, sl[w].a);
+                    for (int w = 1; w < NW; ++w) M = max2(M, sw[w]);
                     int Gw = INT_MAX;
 #pragma unroll
-                    for (int w = 0; w < NW; ++w) Gw = sl[w].a == M ? min(Gw, sl[w].g) : Gw;
+                    for (int w = 0; w < NW; ++w) Gw = sw[w] == M ? min(Gw, sl[w].g) : Gw;
                     int mw = 0, pw = sl[0].p;
+                    double piv = sl[0].v;
 #pragma unroll
                     for (int w = 1; w < NW; ++w) {
                         mw = sl[w].g == Gw ? w : mw;
                         pw = sl[w].g == Gw ? sl[w].p : pw;
+                        piv = sl[w].g == Gw ? sl[w].v : piv;
                     }
+                    // the rest of the pivot row is requested now; the pivot
+                    // itself came with the slot
                     const double *prow = &s.cand[par][mw][0];
+                    double pv[SP];
+#pragma unroll
+                    for (int cc = j + 1; cc < SP; ++cc) pv[cc] = prow[cc];
                     if (tid == 0) {
                         s.sel[jb + sp0 + j] = Gw;
                         s.selp[jb + sp0 + j] = pw;
@@ -390,11 +404,7 @@ __global__ __launch_bounds__(NT) void tslu_panel_kernel(NodeArgs p)
                             selstep[q] = j;
                         }
                     });
-                    const double piv = prow[j];
                     if (piv != 0.0) {
-                        double pv[SP];
-#pragma unroll
-                        for (int cc = j + 1; cc < SP; ++cc) pv[cc] = prow[cc];
                         static_for<RPT>([&](auto QC) {
                             constexpr int q = decltype(QC)::value;
                             if (live[q]) {
@@ -432,33 +442,52 @@ __global__ __launch_bounds__(NT) void tslu_panel_kernel(NodeArgs p)
                 // U rows of the sub-panel's pivots at the rest of the block:
                 // PR[i][SP + c] -= sum_{l<i} PR[i][l] * U[l][SP + c]
                 if (tid < rem) {
+                    // one column per thread, kept in registers (the same
+                    // operations in the same order as updating PR in place)
                     const int c = SP + tid;
+                    double uc[SP];
+#pragma unroll
+                    for (int i = 0; i < SP; ++i) uc[i] = s.PR[i][c];
 #pragma unroll
                     for (int i = 1; i < SP; ++i) {
-                        double u = s.PR[i][c];
 #pragma unroll
                         for (int l = 0; l < SP; ++l)
-                            if (l < i) u -= s.PR[i][l] * s.PR[l][c];
-                        s.PR[i][c] = u;
+                            if (l < i) uc[i] -= s.PR[i][l] * uc[l];
                     }
                     // the sub-panel's pivot rows hold U rows in the rest of the block
 #pragma unroll
-                    for (int i = 0; i < SP; ++i)
-                        Sn[(size_t)(jb + sp0 + c) * rc + s.selp[jb + sp0 + i]] = s.PR[i][c];
+                    for (int i = 0; i < SP; ++i) {
+                        s.PR[i][c] = uc[i];
+                        Sn[(size_t)(jb + sp0 + c) * rc + s.selp[jb + sp0 + i]] = uc[i];
+                    }
                 }
                 __syncthreads();
-                // rank-SP update of the rest of the block, then shift the window
+                // rank-SP update of the rest of the block: pivot by pivot,
+                // the pivot's U row (up to BW - SP values) requested from
+                // LDS at once, then every remaining column of this thread's
+                // live rows (per element the same subtractions in the same
+                // order as a column-by-column loop)
+                constexpr int RW = BW - SP;
+#pragma unroll
+                for (int l = 0; l < SP; ++l) {
+                    double ur[RW > 0 ? RW : 1];
+#pragma unroll
+                    for (int c = 0; c < RW; c += 2) {
+                        const d2 t = *reinterpret_cast<const d2 *>(&s.PR[l][SP + c]);
+                        ur[c] = t[0];
+                        if (c + 1 < RW) ur[c + 1] = t[1];
+                    }
+                    static_for<RPT>([&](auto QC) {
+                        constexpr int q = decltype(QC)::value;
+                        if (live[q]) {
+#pragma unroll
+                            for (int c = 0; c < RW; ++c) x[q][SP + c] -= x[q][l] * ur[c];
+                        }
+                    });
+                }
+                // shift the window
                 static_for<RPT>([&](auto QC) {
                     constexpr int q = decltype(QC)::value;
-                    if (live[q]) {
-#pragma unroll
-                        for (int c = SP; c < BW; ++c) {
-                            double acc = x[q][c];
-#pragma unroll
-                            for (int l = 0; l < SP; ++l) acc -= x[q][l] * s.PR[l][c];
-                            x[q][c] = acc;
-                        }
-                    }
 #pragma unroll
                     for (int c = 0; c + SP < BW; ++c) x[q][c] = x[q][c + SP];
                 });
@@ -568,6 +597,18 @@ __global__ __launch_bounds__(NT) void tslu_panel_kernel(NodeArgs p)
     }
 }
 
+template <int RPT, int NT>
+__global__ __launch_bounds__(NT) void tslu_panel_kernel(NodeArgs p)
+{
+    // The tournament is the critical path and runs beside the Schur update:
+    // its (latency-bound) waves go first when they share a SIMD with the
+    // update's matrix-core waves.
+    __builtin_amdgcn_s_setprio(3);
+    extern __shared__ double smem_raw[];
+    auto &s = *reinterpret_cast<Lds<BlockW<RPT>::value, NT / 64> *>(smem_raw);
+    panel_block<RPT, NT>(p, blockIdx.x, p.jb, s);
+}
+
 // ---------------------------------------------------------------------------
 // E: rank-BW update of the trailing columns of every node of the level.
 // Workgroup = one 64-row x 64-column tile of one node; wave w owns rows
@@ -575,24 +616,25 @@ __global__ __launch_bounds__(NT) void tslu_panel_kernel(NodeArgs p)
 // (4 pivots x 16 rows, zero for selected rows), D = C^T (16 x 16).
 // ---------------------------------------------------------------------------
 template <int BW>
-__global__ __launch_bounds__(256) void tslu_update_kernel(NodeArgs p, int tiles_r, int tiles_c)
+struct UpdLds {
+    double Ut[BW][64 + 1];   // -U rows of the block at the tile's columns
+    double Rt[BW][BW + 8];
+    int sp[BW];
+};
+
+// One 64 x 64 tile (trow, tcol) of node `node`'s rank-BW update; 256
+// threads (4 wavefronts), which all take the same early returns.
+template <int BW>
+__device__ __forceinline__ void update_tile(const NodeArgs &p, const int node, const int jb, const int trow,
+                                            const int tcol, UpdLds<BW> &u)
 {
-    __builtin_amdgcn_s_setprio(3);      // critical path (see tslu_panel_kernel)
-    __shared__ double Ut[BW][64 + 1];   // -U rows of the block at the tile's columns
-    __shared__ double Rt[BW][BW + 8];
-    __shared__ int sp[BW];
-
-    const int tile = blockIdx.x;
-    const int per_node = tiles_r * tiles_c;
-    const int node = tile / per_node;
-    const int t = tile - node * per_node;
-    const int trow = t / tiles_c, tcol = t - trow * tiles_c;
-
+    auto &Ut = u.Ut;
+    auto &Rt = u.Rt;
+    auto &sp = u.sp;
     const NodeRows nr = node_rows(p, node);
     if (nr.promoted) return;
     const int r = nr.r;
     const int nsel = r < p.vb ? r : p.vb;
-    const int jb = p.jb;
     if (jb >= nsel) return;
     const int bwc = (nsel - jb) < BW ? (nsel - jb) : BW;
     const int tc0 = jb + bwc, ncol = nsel - tc0;
@@ -683,6 +725,172 @@ __global__ __launch_bounds__(256) void tslu_update_kernel(NodeArgs p, int tiles_
         }
 }
 
+template <int BW>
+__global__ __launch_bounds__(256) void tslu_update_kernel(NodeArgs p, int tiles_r, int tiles_c)
+{
+    __builtin_amdgcn_s_setprio(3);      // critical path (see tslu_panel_kernel)
+    __shared__ UpdLds<BW> u;
+    const int tile = blockIdx.x;
+    const int per_node = tiles_r * tiles_c;
+    const int node = tile / per_node;
+    const int t = tile - node * per_node;
+    const int trow = t / tiles_c, tcol = t - trow * tiles_c;
+    update_tile<BW>(p, node, p.jb, trow, tcol, u);
+}
+
+// The rank-BW update of one node's remaining columns after block jb, by
+// the node's own workgroup (256 threads): the block triangle and pivot
+// positions are staged once; the U rows of the block are computed for up to
+// UPC columns at a time (one column per thread, the same substitution as
+// update_tile) into Ut (BW x (UPC + 2) doubles), and every 64 x 64 tile of
+// those columns is updated on the matrix cores as in update_tile (the
+// block's L rows of a 64-row strip are loaded once per strip).  Same
+// operations per element as update_tile, so the same values.
+template <int BW>
+struct UpdStage {
+    double Rt[BW][BW + 8];
+    int sp[BW];
+};
+constexpr int UPC = 128;
+
+template <int BW>
+__device__ __forceinline__ void update_node(const NodeArgs &p, const int node, const int jb, const int tiles_r,
+                                            double (*Ut)[UPC + 2], UpdStage<BW> &u)
+{
+    auto &Rt = u.Rt;
+    auto &sp = u.sp;
+    const NodeRows nr = node_rows(p, node);
+    const int r = nr.r;
+    const int nsel = r < p.vb ? r : p.vb;
+    const int bwc = (nsel - jb) < BW ? (nsel - jb) : BW;
+    const int tc0 = jb + bwc, ncol = nsel - tc0;
+    const int rc = p.rc;
+    const int tid = threadIdx.x;
+    double *Sn = p.S + (size_t)node * p.s_node;
+    const unsigned char *rselg = p.rsel + (size_t)node * p.rs_node;
+    const int32_t *selg = p.selg + (size_t)node * 2 * kMaxV;
+    double *utg = p.utg + (size_t)node * 32 * UTLD;
+    const double *rtg = p.rtg + (size_t)node * 32 * 40;
+
+    for (int e = tid; e < BW * (BW + 8); e += 256) (&Rt[0][0])[e] = rtg[e];
+    if (tid < BW) sp[tid] = selg[kMaxV + jb + tid];
+    __syncthreads();
+
+    const int lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    constexpr int KS = (BW + 3) / 4;
+    for (int c0 = 0; c0 < ncol; c0 += UPC) {
+        if (tid < UPC) {
+            const int cc = c0 + tid;
+            if (cc < ncol) {
+                const size_t col = (size_t)(tc0 + cc) * rc;
+                for (int h = 0; h < BW; h += 8) {
+                    double uv[8];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) uv[i] = (h + i < bwc) ? Sn[col + sp[h + i]] : 0.0;
+                    for (int l = 0; l < h; ++l) {
+                        const double ul = -Ut[l][tid];
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) uv[i] -= Rt[l][h + i] * ul;
+                    }
+#pragma unroll
+                    for (int l = 0; l < 8; ++l)
+#pragma unroll
+                        for (int i = l + 1; i < 8; ++i) uv[i] -= Rt[h + l][h + i] * uv[l];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        Ut[h + i][tid] = (h + i < bwc) ? -uv[i] : 0.0;
+                        if (p.root && h + i < bwc) utg[(size_t)(h + i) * UTLD + cc] = uv[i];
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < BW; ++i) Ut[i][tid] = 0.0;
+            }
+        }
+        __syncthreads();
+        const int ctiles = (ncol - c0) < UPC ? (ncol - c0 + 63) / 64 : UPC / 64;
+        for (int trow = 0; trow < tiles_r; ++trow) {
+            const int r00 = trow * 64;
+            if (r00 >= r) break;
+            const int pr = r00 + wave * 16 + lr;
+            const bool rowin = pr < r;
+            const bool rowok = rowin && !rselg[pr];
+            double bop[KS];
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const int l = 4 * ks + lk;
+                bop[ks] = (rowok && l < bwc) ? Sn[(size_t)(jb + l) * rc + pr] : 0.0;
+            }
+            for (int tc = 0; tc < ctiles; ++tc) {
+                const int c00 = c0 + tc * 64;
+                d4 acc[4];
+#pragma unroll
+                for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int cc = c00 + 16 * tt + lk + 4 * q;
+                        acc[tt][q] = (cc < ncol && rowin) ? Sn[(size_t)(tc0 + cc) * rc + pr] : 0.0;
+                    }
+#pragma unroll
+                for (int tt = 0; tt < 4; ++tt) {
+#pragma unroll
+                    for (int ks = 0; ks < KS; ++ks) {
+                        const int l = 4 * ks + lk;
+                        const double aop = (l < bwc) ? Ut[l][tc * 64 + 16 * tt + lr] : 0.0;
+                        acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, bop[ks], acc[tt], 0, 0, 0);
+                    }
+                }
+#pragma unroll
+                for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int cc = c00 + 16 * tt + lk + 4 * q;
+                        if (cc < ncol && rowin) Sn[(size_t)(tc0 + cc) * rc + pr] = acc[tt][q];
+                    }
+            }
+        }
+        __syncthreads();    // Ut is rewritten by the next column range
+    }
+}
+
+// A whole node in one launch, for nodes of at most 512 rows (every merge
+// node at v <= 256, and the short leaves of late panels): the workgroup
+// runs the pivot steps of each column block and then the block's rank-BW
+// update of the node's remaining columns itself on its own matrix cores
+// (the node's block, at most 1 MiB, stays in L2).  The work per element is
+// that of the two-launch scheme, so the selection and the values are the
+// same bit for bit; what goes away is two launches per block, each with its
+// own start-up (kernel code and node state fetched afresh).
+template <int RPT, int NT>
+__global__ __launch_bounds__(NT) void tslu_node_kernel(NodeArgs p, int tiles_r)
+{
+    static_assert(NT == 256, "the update takes 256 threads");
+    __builtin_amdgcn_s_setprio(3);      // critical path (see tslu_panel_kernel)
+    constexpr int BW = BlockW<RPT>::value;
+    using L = Lds<BW, NT / 64>;
+    static_assert(sizeof(L::tile) >= sizeof(double) * BW * (UPC + 2), "Ut fits the staging area");
+    extern __shared__ double smem_raw[];
+    L &s = *reinterpret_cast<L *>(smem_raw);
+    UpdStage<BW> &u = *reinterpret_cast<UpdStage<BW> *>(reinterpret_cast<char *>(smem_raw) + sizeof(L));
+    // the panel blocks use the staging area only at the root's last block
+    double(*Ut)[UPC + 2] = reinterpret_cast<double(*)[UPC + 2]>(&s.tile[0]);
+    const int node = blockIdx.x;
+    const NodeRows nr = node_rows(p, node);
+    const int nsel = nr.promoted ? 0 : (nr.r < p.vb ? nr.r : p.vb);
+    const int nsteps = nr.promoted ? 1 : nsel;     // a promoted node only copies (at jb = 0)
+    for (int jb = 0; jb < nsteps; jb += BW) {
+        panel_block<RPT, NT>(p, node, jb, s);
+        if (nsel - (jb + BW) <= 0) break;
+        // the block's state written above (workspace) is read back below
+        __threadfence_block();
+        __syncthreads();
+        update_node<BW>(p, node, jb, tiles_r, Ut, u);
+        __threadfence_block();
+        __syncthreads();
+    }
+}
+
 // Gather of a level: the current-step panel values of every node's rows into
 // its column-major scratch block, one 64 x 64 tile per workgroup (transposed
 // through LDS); also clears the node's selected-row mask.
@@ -737,6 +945,29 @@ int set_panel_attr()
     constexpr int BW = BlockW<RPT>::value;
     CFX_HIP(hipFuncSetAttribute((const void *)tslu_panel_kernel<RPT, NT>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(Lds<BW, NT / 64>)));
+    if constexpr (NT == 256)
+        CFX_HIP(hipFuncSetAttribute((const void *)tslu_node_kernel<RPT, NT>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)(sizeof(Lds<BW, NT / 64>) + sizeof(UpdStage<BW>))));
+    return CFX_OK;
+}
+
+// Whole nodes in one launch each (nodes of at most 512 rows).
+template <int RPT, int NT>
+int launch_level_fused(NodeArgs a, int grid, int rows_cap, hipStream_t st)
+{
+    constexpr int BW = BlockW<RPT>::value;
+    const size_t lds = sizeof(Lds<BW, NT / 64>) + sizeof(UpdStage<BW>);
+    const int tiles_r = (rows_cap + 63) / 64;
+    {
+        const int tiles_v = (a.vb + 63) / 64;
+        hipLaunchKernelGGL(tslu_gather_kernel, dim3(grid * tiles_r * tiles_v), dim3(256), 0, st, a, tiles_r,
+                           tiles_v);
+        CFX_HIP(hipGetLastError());
+    }
+    a.jb = 0;
+    hipLaunchKernelGGL((tslu_node_kernel<RPT, NT>), dim3(grid), dim3(NT), lds, st, a, tiles_r);
+    CFX_HIP(hipGetLastError());
     return CFX_OK;
 }
 
@@ -772,8 +1003,12 @@ int launch_level(NodeArgs a, int grid, int rows_cap, hipStream_t st)
 // threads; taller nodes 512 threads (two wavefronts per SIMD still leave
 // each lane 256 registers), so that the register block x[RPT][BW] can be
 // twice as wide as with 256 threads: fewer blocks, fewer update passes.
-int launch_node_level(const NodeArgs &a, int grid, int rows_cap, hipStream_t st)
+int launch_node_level(const NodeArgs &a, int grid, int rows_cap, int fuse_rows, hipStream_t st)
 {
+    if (rows_cap <= fuse_rows) {
+        if (rows_cap <= 256) return launch_level_fused<1, 256>(a, grid, rows_cap, st);
+        if (rows_cap <= 512) return launch_level_fused<2, 256>(a, grid, rows_cap, st);
+    }
     if (rows_cap <= 256) return launch_level<1, 256>(a, grid, rows_cap, st);
     if (rows_cap <= 512) return launch_level<2, 256>(a, grid, rows_cap, st);
     if (rows_cap <= 1024) return launch_level<2, 512>(a, grid, rows_cap, st);
@@ -798,7 +1033,7 @@ int init_kernel_attributes()
 
 int launch_tslu(const double *W, int64_t ldw, int64_t row0, int64_t rows, int vb, int leaves,
                 const Workspace &ws, int32_t *piv_out, int32_t *ipiv, int32_t *info, hipStream_t st,
-                const int32_t *rm)
+                const int32_t *rm, int fuse_rows)
 {
     int64_t h = (rows + leaves - 1) / leaves;
     if (h < vb) h = vb;
@@ -833,7 +1068,7 @@ int launch_tslu(const double *W, int64_t ldw, int64_t row0, int64_t rows, int vb
     a.ccnt_out = ws.ccnt[0];
     a.rc = (int)h;
     a.root = nl == 1;
-    int rc = launch_node_level(a, nl, (int)h, st);
+    int rc = launch_node_level(a, nl, (int)h, fuse_rows, st);
     if (rc) return rc;
 
     // playoff rounds
@@ -848,7 +1083,7 @@ int launch_tslu(const double *W, int64_t ldw, int64_t row0, int64_t rows, int vb
         a.ccnt_out = ws.ccnt[cur ^ 1];
         a.rc = 2 * vb;
         a.root = nout == 1;
-        if ((rc = launch_node_level(a, nout, 2 * vb, st))) return rc;
+        if ((rc = launch_node_level(a, nout, 2 * vb, fuse_rows, st))) return rc;
         nn = nout;
         cur ^= 1;
     }

@@ -325,3 +325,29 @@ def test_getrf_full_size_against_stored_oracle(cfx, n):
     res = gpu_frob_residual(A0, dA, O.ipiv_to_perm(piv))
     say(f"  ||PA-LU||_F/||A||_F = {res:.3e} (oracle's own factors: {float(gold['residual']):.3e})")
     assert res <= 1e-12
+
+
+@pytest.mark.parametrize("n,v,L,la", [(2048, 256, 8, 1), (3000, 128, 4, 0), (700, 64, 3, 1), (5000, 256, 16, 1)])
+def test_fused_tournament_nodes_bitwise_equal(cfx, n, v, L, la):
+    """Nodes of at most 512 rows run as one launch each (pivot steps and the
+    node's own updates in one workgroup) or as two launches per column
+    block: a scheduling choice only, so the factors are equal bit for bit."""
+    say(f"fused tournament nodes n={n} v={v} L={L} la={la}")
+    A = G.normal_matrix(n, 900 + n)
+    out = []
+    for rows in (512, 0):
+        h = cfx.Handle()
+        try:
+            cfx.set_tournament_fusion(rows, handle=h)
+            assert cfx.tournament_fusion(handle=h) == rows
+            dA = to_dev(A)
+            ipiv, info = cfx.getrf(dA, v=v, leaves=L, lookahead=la, handle=h)
+            torch.cuda.synchronize()
+            out.append((dA.cpu().numpy(), ipiv.cpu().numpy(), int(info.cpu()[0])))
+        finally:
+            h.close()
+    assert out[0][2] == out[1][2] == 0
+    assert np.array_equal(out[0][1], out[1][1])
+    assert np.array_equal(out[0][0], out[1][0])
+    ref = O.getrf(A, v, L)
+    assert compare_panels(out[0][1][:n], ref.ipiv, ref.margins, v) == len(ref.margins)
