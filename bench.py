@@ -521,6 +521,8 @@ def main():
                     help="grid bound of the overlapped Schur launches (cfx_set_overlap_tuning; "
                          "-1 = by precision, the default; 0 = none)")
     ap.add_argument("--chunk", type=int, default=None, help="columns per overlapped Schur launch")
+    ap.add_argument("--reserve-cus", type=int, default=None,
+                    help="compute units kept free of the overlapped Schur launches (cfx_set_reserved_cus)")
     ap.add_argument("--one-stream", action="store_true",
                     help="issue the lookahead schedule on one stream (for PMC counter runs)")
     ap.add_argument("--seed", type=int, default=0)
@@ -574,7 +576,7 @@ def main():
         print(json.dumps({"tslu_bench": tslu_bench(cfx, torch, n, v, L, args.seed)}), flush=True)
         return
     if args.schur_replay:
-        chunk = args.chunk or cfx.overlap_tuning()[1]
+        chunk = args.chunk or cfx.overlap_tuning()[1] or n     # 0: the whole rest in one launch
         launches, flops, dt = schur_replay(cfx, torch, n, v, chunk, args.seed, args.delay)
         out = {"schur_replay": {"n": n, "v": v, "chunk": chunk, "delay": args.delay, "launches": launches,
                                 "flops": flops, "seconds": round(dt, 4), "tflops": round(flops / dt / 1e12, 3)}}
@@ -604,6 +606,8 @@ def main():
     B = torch.empty_like(pb)
     if args.delay != 1:
         cfx.set_schur_delay(args.delay)
+    if args.reserve_cus is not None:
+        cfx.set_reserved_cus(args.reserve_cus)
     work = cfx.workspace(n, v, L, "fp64", args.lookahead, dev)
     if args.schur_wgs is not None or args.chunk is not None or args.one_stream:
         w0, c0, _ = cfx.overlap_tuning()

@@ -95,13 +95,16 @@ int cfx_destroy(cfx_handle *h);
  * handle; they change scheduling only, never a result bit).  While the next
  * panel's tournament runs on the second stream, the rest of the Schur update
  * is issued in launches of `chunk_cols` columns whose grid is bounded by
- * `schur_workgroups` workgroups that walk the tiles persistently, so that
- * the tournament's launches find free compute units at once.
+ * `schur_workgroups` workgroups that walk the tiles persistently (see also
+ * cfx_set_reserved_cus, which keeps compute units free for the tournament).
  *   schur_workgroups : -1 = by precision (the default): no bound for FP64,
  *                      384 for BF16/FP16 (their update is bound by HBM and
  *                      loses little to a bound); 0 = one workgroup per tile
  *                      (no bound); else >= 8.
- *   chunk_cols       : >= 1; default 512.
+ *   chunk_cols       : >= 0; 0 (the default) = automatic: the whole rest in
+ *                      one launch when compute units are reserved, 512
+ *                      columns per launch otherwise (the tournament's
+ *                      launches then start between two of them).
  *   one_stream       : 1 issues the same launches, in the same order, on
  *                      the caller's stream only (no overlap; for counter
  *                      collection by profilers that serialize dispatches
@@ -142,6 +145,19 @@ int cfx_set_tournament_fusion(cfx_handle *h, int32_t node_rows);
  * it).  Set returns -2 for an invalid d. */
 int cfx_schur_delay(cfx_handle *h, int32_t *delay);
 int cfx_set_schur_delay(cfx_handle *h, int32_t delay);
+
+/* Compute units kept free of the overlapped Schur launches of cfx_getrf and
+ * cfx_getrf_masked with lookahead (scheduling only: the same factors bit
+ * for bit).  The rest of each panel's update runs on a handle stream whose
+ * CU mask leaves `cus` compute units out, so the next panel's tournament
+ * (the critical path of Sec. 7.3) starts its launches on them at once
+ * instead of waiting for the update's workgroups to drain.  cus = 0 puts
+ * the update on the caller's stream.  Default 32 (4 per XCD on a
+ * 256-CU device).  cus in 0..(compute units / 4);
+ * set returns -2 otherwise, and synchronises the handle's previous update
+ * stream before replacing it. */
+int cfx_reserved_cus(cfx_handle *h, int32_t *cus);
+int cfx_set_reserved_cus(cfx_handle *h, int32_t cus);
 
 /* Static description of the library build (host memory, NUL-terminated). */
 const char *cfx_version(void);

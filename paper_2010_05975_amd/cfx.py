@@ -128,6 +128,8 @@ def lib():
         L.cfx_tournament_fusion.argtypes = [vp, vp]
         L.cfx_set_tournament_fusion.argtypes = [vp, i32]
         L.cfx_set_schur_delay.argtypes = [vp, i32]
+        L.cfx_reserved_cus.argtypes = [vp, vp]
+        L.cfx_set_reserved_cus.argtypes = [vp, i32]
         L.cfx_getrf_masked.argtypes = [vp, i64, vp, i64, vp, vp, vp, C.POINTER(LuOpts), vp, sz, vp]
         L.cfx_getrs_masked.argtypes = [vp, i64, i64, vp, i64, vp, vp, i64, vp]
         L.cfx_getrs_noalloc.argtypes = [vp, i64, i64, vp, i64, vp, vp, i64, vp]
@@ -137,6 +139,7 @@ def lib():
         for f in ("cfx_create", "cfx_destroy", "cfx_getrf_buffer_size", "cfx_getrf",
                   "cfx_tslu", "cfx_getrs", "cfx_getrs_check", "cfx_set_solve_spin_limit",
                   "cfx_getrf_masked", "cfx_getrs_masked", "cfx_schur_delay", "cfx_set_schur_delay",
+                  "cfx_reserved_cus", "cfx_set_reserved_cus",
                   "cfx_tournament_fusion", "cfx_set_tournament_fusion",
                   "cfx_getrs_noalloc",
                   "cfx_schur_update_buffer_size", "cfx_schur_update",
@@ -479,6 +482,19 @@ def schur_delay(handle=None):
 def set_schur_delay(delay, handle=None):
     h = handle or default_handle()
     _check("cfx_set_schur_delay", lib().cfx_set_schur_delay(h.h, int(delay)))
+
+
+def reserved_cus(handle=None):
+    """cfx_reserved_cus: compute units kept free of the overlapped updates."""
+    h = handle or default_handle()
+    c = C.c_int32()
+    _check("cfx_reserved_cus", lib().cfx_reserved_cus(h.h, C.byref(c)))
+    return c.value
+
+
+def set_reserved_cus(cus, handle=None):
+    h = handle or default_handle()
+    _check("cfx_set_reserved_cus", lib().cfx_set_reserved_cus(h.h, int(cus)))
 
 
 def overlap_tuning(handle=None):

@@ -49,6 +49,8 @@ struct Profiler {
 
 namespace cfx {
 constexpr int kLpSchurWgs = 384;
+constexpr int64_t kLaChunk = 512;    // columns per overlapped launch without reserved compute units
+constexpr int kReserveCus = 32;      // compute units kept free for the tournament by default
 }  // namespace cfx
 
 struct cfx_handle {
@@ -56,6 +58,13 @@ struct cfx_handle {
     hipStream_t side = nullptr;     // lookahead stream (default priority)
     hipEvent_t ev_panel = nullptr;  // next panel's columns updated
     hipEvent_t ev_tslu = nullptr;   // next panel's tournament done
+    // the rest of each overlapped update runs on `upd`, a stream whose CU
+    // mask leaves `reserve_cus` compute units free: the tournament's
+    // launches start there at once instead of waiting for the update's
+    // workgroups to drain (null: the caller's stream)
+    hipStream_t upd = nullptr;
+    hipEvent_t ev_upd = nullptr;    // the rest of the last update done
+    int reserve_cus = 0;
 
     void *scratch = nullptr;        // getrs permutation + gather buffer
     size_t scratch_bytes = 0;
@@ -72,7 +81,7 @@ struct cfx_handle {
     // kLpSchurWgs for the HBM-bound low-precision update, which then leaves
     // compute units to the tournament at little cost of its own)
     int schur_wgs = -1;
-    int64_t la_chunk = 512;         // columns per overlapped Schur launch
+    int64_t la_chunk = 0;           // columns per overlapped Schur launch (0: automatic)
     int delay = 1;                  // panels per trailing update (tile-stationary schedule)
     int fuse_rows = cfx::kFuseRowsDefault;  // tournament nodes up to this height run as one launch
     bool one_stream = false;        // lookahead launches on the caller's stream only
@@ -237,7 +246,8 @@ int cfx_create(cfx_handle **h)
     if (hipGetDevice(&p->device) != hipSuccess ||
         hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&p->ev_panel, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&p->ev_tslu, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&p->ev_tslu, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_upd, hipEventDisableTiming) != hipSuccess) {
         delete p;
         return CFX_EHIP;
     }
@@ -252,6 +262,10 @@ int cfx_create(cfx_handle **h)
         cus > 0)
         p->cu_count = cus;
     if (int rc = init_kernel_attributes()) {
+        cfx_destroy(p);
+        return rc;
+    }
+    if (int rc = cfx_set_reserved_cus(p, p->cu_count >= 4 * kReserveCus ? kReserveCus : p->cu_count / 4)) {
         cfx_destroy(p);
         return rc;
     }
@@ -315,6 +329,8 @@ int cfx_destroy(cfx_handle *h)
     if (h->ev_panel) (void)hipEventDestroy(h->ev_panel);
     if (h->ev_tslu) (void)hipEventDestroy(h->ev_tslu);
     if (h->side) (void)hipStreamDestroy(h->side);
+    if (h->upd) (void)hipStreamDestroy(h->upd);
+    if (h->ev_upd) (void)hipEventDestroy(h->ev_upd);
     delete h;
     return CFX_OK;
 }
@@ -438,7 +454,7 @@ static int getrf_run_delayed(cfx_handle *h, int64_t n, double *A, int64_t lda, i
             CFX_HIP(hipEventRecord(h->ev_tslu, side));
             tslu_on_side = true;
         }
-        const int64_t chunk = la ? h->la_chunk : m;
+        const int64_t chunk = la ? (h->la_chunk > 0 ? h->la_chunk : kLaChunk) : m;
         const int wgs = la ? (h->schur_wgs >= 0 ? h->schur_wgs : (prec == CFX_PREC_FP64 ? 0 : cfx::kLpSchurWgs)) : 0;
         if (vbn < m) {
             e = pf.begin(st);
@@ -549,12 +565,13 @@ static int getrf_run(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *
             return rc;
         pf.end(PH_TSLU, e, st);
     }
-    bool tslu_on_side = false;
+    bool tslu_on_side = false, upd_pending = false;
     for (int64_t k = 0; k < n; k += v) {
         const int vb = (int)((n - k) < v ? (n - k) : v);
         const int64_t m = n - k - vb;
         if (tslu_on_side) CFX_HIP(hipStreamWaitEvent(st, h->ev_tslu, 0));
-        tslu_on_side = false;
+        if (upd_pending) CFX_HIP(hipStreamWaitEvent(st, h->ev_upd, 0));
+        tslu_on_side = upd_pending = false;
         hipEvent_t e = pf.begin(st);
         if ((rc = swap(k, vb, st))) return rc;
         pf.end(PH_LASWP, e, st);
@@ -572,10 +589,12 @@ static int getrf_run(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *
             if ((rc = pack(b, m, vb, st))) return rc;
             if ((rc = schur(b, m, 0, vbn, vb, 0, st))) return rc;
             pf.end(PH_SCHUR, e, st, 2.0 * (double)m * vbn * vb);
-            // next panel's tournament on the side stream
-            hipStream_t ts = side, us = st;
+            // next panel's tournament on the side stream, the rest of the
+            // update on the CU-masked stream when there is one
+            hipStream_t ts = side, us = (h->upd && !h->one_stream) ? h->upd : st;
             CFX_HIP(hipEventRecord(h->ev_panel, st));
             CFX_HIP(hipStreamWaitEvent(ts, h->ev_panel, 0));
+            if (us != st) CFX_HIP(hipStreamWaitEvent(us, h->ev_panel, 0));
             const int64_t kn = k + vb;
             e = pf.begin(ts);
             if ((rc = launch_tslu(panel_w(kn), lda, kn, n - kn, vbn, L, ws, nullptr, ipiv, info, ts, rm,
@@ -594,7 +613,7 @@ static int getrf_run(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *
             // the side stream instead of leaving them behind one huge grid
             // (one event pair around all chunks: events between the
             // launches would cost the step about 2 %)
-            const int64_t chunk = h->la_chunk;
+            const int64_t chunk = h->la_chunk > 0 ? h->la_chunk : (us != st ? m : kLaChunk);
             const int wgs = h->schur_wgs >= 0 ? h->schur_wgs : (prec == CFX_PREC_FP64 ? 0 : cfx::kLpSchurWgs);
             if (vbn < m) {
                 e = pf.begin(us);
@@ -605,11 +624,15 @@ static int getrf_run(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *
                 }
                 pf.end(PH_SCHUR, e, us, 2.0 * (double)m * (double)(m - vbn) * vb, nl);
             }
-
+            if (us != st) {
+                CFX_HIP(hipEventRecord(h->ev_upd, us));
+                upd_pending = true;
+            }
         }
         if (pf.on) ++pf.panels;
     }
     if (tslu_on_side) CFX_HIP(hipStreamWaitEvent(st, h->ev_tslu, 0));
+    if (upd_pending) CFX_HIP(hipStreamWaitEvent(st, h->ev_upd, 0));
     return CFX_OK;
 }
 
@@ -911,7 +934,7 @@ int cfx_set_overlap_tuning(cfx_handle *h, int32_t schur_workgroups, int32_t chun
 {
     if (!h) return -1;
     if (schur_workgroups < -1 || (schur_workgroups > 0 && schur_workgroups < 8)) return -2;
-    if (chunk_cols < 1) return -3;
+    if (chunk_cols < 0) return -3;
     if (one_stream != 0 && one_stream != 1) return -4;
     h->schur_wgs = schur_workgroups;
     h->la_chunk = chunk_cols;
@@ -948,6 +971,36 @@ int cfx_set_schur_delay(cfx_handle *h, int32_t delay)
     if (!h) return -1;
     if (delay < 1 || delay > 8) return -2;
     h->delay = delay;
+    return CFX_OK;
+}
+
+int cfx_reserved_cus(cfx_handle *h, int32_t *cus)
+{
+    if (!h) return -1;
+    if (!cus) return -2;
+    *cus = h->upd ? h->reserve_cus : 0;
+    return CFX_OK;
+}
+
+int cfx_set_reserved_cus(cfx_handle *h, int32_t cus)
+{
+    if (!h) return -1;
+    if (cus < 0 || cus > h->cu_count / 4) return -2;
+    if (h->upd) {
+        // work queued on the old stream ends before it goes away
+        CFX_HIP(hipStreamSynchronize(h->upd));
+        CFX_HIP(hipStreamDestroy(h->upd));
+        h->upd = nullptr;
+    }
+    h->reserve_cus = 0;
+    if (cus == 0) return CFX_OK;
+    // mask bits are logical compute units, consecutive bits spread over the
+    // XCDs: clearing the lowest `cus` bits leaves about cus / 8 compute
+    // units free on every XCD
+    std::vector<uint32_t> mask((size_t)(h->cu_count + 31) / 32, 0u);
+    for (int c = cus; c < h->cu_count; ++c) mask[(size_t)c / 32] |= 1u << (c % 32);
+    CFX_HIP(hipExtStreamCreateWithCUMask(&h->upd, (uint32_t)mask.size(), mask.data()));
+    h->reserve_cus = cus;
     return CFX_OK;
 }
 

@@ -10,6 +10,9 @@ and this script stores, per N, in c2_n<N>_seed0.npz:
   residual  float64    ||P A - L U||_F / ||A||_F of the oracle's factors
   digest    str        SHA-256 of rows 0, N/2 and N-1 of A (the GPU test
                        checks that it regenerates the same input)
+  seconds   float64    wall time of the oracle factorisation alone
+  threads   int32      OpenMP threads it ran with (OMP_NUM_THREADS, else
+                       the CPU count)
 Only oracle/ computes anything here (numpy's matmul forms L U for the
 residual).  It runs on the CPU in about 5 minutes (N = 16384) and 30 minutes
 (N = 32768) on 8 cores:
@@ -64,10 +67,11 @@ def frob_residual(A: np.ndarray, LU: np.ndarray, ipiv: np.ndarray, block: int = 
 
 
 def make(n: int) -> None:
-    t0 = time.time()
     A = G.normal_matrix(n, SEED)
     dg = digest(A)
-    print(f"N={n}: oracle getrf (v={V}, L={LEAVES}) ...", flush=True)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    print(f"N={n}: oracle getrf (v={V}, L={LEAVES}, {threads} threads) ...", flush=True)
+    t0 = time.time()
     f = O.getrf(A, V, LEAVES)
     t1 = time.time()
     print(f"  {t1 - t0:.0f} s; min margin {f.margins.min():.3e}; info {f.info}", flush=True)
@@ -76,7 +80,8 @@ def make(n: int) -> None:
     np.savez_compressed(path(n), ipiv=f.ipiv.astype(np.int32), margins=f.margins.astype(np.float64),
                         info=np.int32(f.info), residual=np.float64(res), digest=np.str_(dg),
                         v=np.int32(V), leaves=np.int32(LEAVES), seed=np.int32(SEED),
-                        numpy_version=np.str_(np.__version__))
+                        numpy_version=np.str_(np.__version__), seconds=np.float64(t1 - t0),
+                        threads=np.int32(threads))
 
 
 def load(n: int) -> dict:

@@ -52,9 +52,9 @@ def test_tslu_ties_smallest_row(cfx):
 # full factorisation
 # ---------------------------------------------------------------------------
 
-def run_getrf(cfx, A, v, L, lookahead=0):
+def run_getrf(cfx, A, v, L, lookahead=0, prec="fp64"):
     dA = to_dev(A)
-    ipiv, info = cfx.getrf(dA, v=v, leaves=L, lookahead=lookahead)
+    ipiv, info = cfx.getrf(dA, v=v, leaves=L, lookahead=lookahead, precision=prec)
     torch.cuda.synchronize()
     return dA.cpu().numpy(), ipiv.cpu().numpy(), int(info.cpu()[0])
 
@@ -199,21 +199,72 @@ def test_getrf_lookahead_bitwise_equal(cfx, n, v, L):
 
 def test_overlap_tuning_rejects_invalid_values(cfx):
     """cfx_set_overlap_tuning: -2 for a workgroup bound below -1 or in
-    1..7, -3 for chunk_cols < 1, -4 for one_stream outside {0, 1}; a
+    1..7, -3 for chunk_cols < 0, -4 for one_stream outside {0, 1}; a
     rejected call leaves the settings unchanged."""
     h = cfx.Handle()
     try:
         cfx.set_overlap_tuning(8, 256, 1, handle=h)
         for args, code in [((-2, 512, 0), -2), ((1, 512, 0), -2), ((7, 512, 0), -2),
-                           ((0, 0, 0), -3), ((0, 512, 2), -4)]:
+                           ((0, -1, 0), -3), ((0, 512, 2), -4)]:
             with pytest.raises(cfx.CfxError) as e:
                 cfx.set_overlap_tuning(*args, handle=h)
             assert e.value.code == code, args
             assert cfx.overlap_tuning(handle=h) == (8, 256, 1)
-        cfx.set_overlap_tuning(-1, 512, 0, handle=h)
-        assert cfx.overlap_tuning(handle=h) == (-1, 512, 0)
+        cfx.set_overlap_tuning(-1, 0, 0, handle=h)
+        assert cfx.overlap_tuning(handle=h) == (-1, 0, 0)
     finally:
         h.close()
+
+
+def test_reserved_cus_settings(cfx):
+    """cfx_set_reserved_cus: default 32 on a 256-CU device, 0..CUs/4
+    accepted (0 = the caller's stream), -2 otherwise with the setting
+    unchanged."""
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    h = cfx.Handle()
+    try:
+        assert cfx.reserved_cus(handle=h) == min(32, ncu // 4)
+        for bad in (-1, ncu // 4 + 1, 10000):
+            with pytest.raises(cfx.CfxError) as e:
+                cfx.set_reserved_cus(bad, handle=h)
+            assert e.value.code == -2
+            assert cfx.reserved_cus(handle=h) == min(32, ncu // 4)
+        for good in (0, 8, ncu // 4):
+            cfx.set_reserved_cus(good, handle=h)
+            assert cfx.reserved_cus(handle=h) == good
+    finally:
+        h.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16"])
+def test_reserved_cus_bitwise_equal(cfx, prec):
+    """The rest of each update on the CU-masked stream (0, 8 or 32
+    reserved compute units, automatic or fixed chunks, interchanged or
+    masked rows) changes scheduling only: the factors are bitwise those of
+    the plain schedule on the caller's stream."""
+    n, v, L = 2304, 128, 4
+    say(f"reserved cus bitwise {prec} n={n}")
+    A = G.normal_matrix(n, 21)
+    ref = run_getrf(cfx, A, v, L, 0, prec=prec)
+    for cus, chunk, masked in [(0, 0, False), (8, 0, False), (32, 0, False), (32, 300, False), (32, 0, True)]:
+        h = cfx.Handle()
+        try:
+            cfx.set_reserved_cus(cus, handle=h)
+            cfx.set_overlap_tuning(-1, chunk, 0, handle=h)
+            dA = to_dev(A)
+            if masked:
+                ipiv, rowmap, info = cfx.getrf_masked(dA, v=v, leaves=L, precision=prec, lookahead=1, handle=h)
+            else:
+                ipiv, info = cfx.getrf(dA, v=v, leaves=L, precision=prec, lookahead=1, handle=h)
+            torch.cuda.synchronize()
+        finally:
+            h.close()
+        LU = dA.cpu().numpy()
+        if masked:
+            LU = LU[rowmap.cpu().numpy()[:n]]
+        assert int(info.cpu()[0]) == ref[2]
+        assert np.array_equal(ipiv.cpu().numpy()[:n], ref[1][:n]), (cus, chunk, masked)
+        assert np.array_equal(LU, ref[0]), (cus, chunk, masked)
 
 
 @pytest.mark.parametrize("n,wgs,chunk", [(2100, 8, 64), (2100, 12, 300), (2100, 40, 4096), (2048, 8, 256),
@@ -229,7 +280,7 @@ def test_getrf_bounded_schur_grid_bitwise_equal(cfx, n, wgs, chunk):
     ref = run_getrf(cfx, A, v, L, 0)
     h = cfx.Handle()
     try:
-        assert cfx.overlap_tuning(handle=h) == (-1, 512, 0)     # the defaults
+        assert cfx.overlap_tuning(handle=h) == (-1, 0, 0)     # the defaults
         one = 1 if wgs == 12 else 0         # one case on the caller's stream only
         cfx.set_overlap_tuning(wgs, chunk, one, handle=h)
         assert cfx.overlap_tuning(handle=h) == (wgs, chunk, one)
