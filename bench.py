@@ -15,6 +15,7 @@ events) and the CPU oracle timed on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import collections
 import json
 import os
 import sys
@@ -428,82 +429,145 @@ def batched_leg(cfx, G, torch, count, seed, steps):
     return out
 
 
-def serve_leg(cfx, G, torch, rate, duration, seed, arena_gb, slots, nmax):
+def serve_leg(cfx, G, torch, rate, duration, seed, arena_gb, slots, nmax, pool=0, lowp_min_n=0,
+              passes=("fp64", "bf16", "bf16_unrouted"), v=128, leaves=2, lookahead=0):
     """The serving loop on a seeded Poisson stream: arrivals at `rate` per
     second for `duration` seconds, n log-uniform in [64, nmax], cond
     log-uniform in [1e2, 1e8] (Householder construction), 1-16 right-hand
     sides, 30 % re-solves of an earlier request's factors (kept resident).
     The inputs are built on the device before the clock starts; requests are
-    submitted at their arrival times from this thread.  Run once with FP64
-    factors and once with BF16 factors + GMRES-IR (target 5e-15; a request
-    whose refinement does not reach it in 3 outer steps refactors in FP64)."""
+    submitted at their arrival times from this thread.  One pass per entry
+    of `passes`: "fp64" (FP64 factors), "bf16" (BF16 factors + GMRES-IR,
+    target 5e-15, a request whose refinement does not reach it in 3 outer
+    steps refactors in FP64; requests below `lowp_min_n` are routed to FP64
+    factors) and "bf16_unrouted" (the same with every request in BF16).
+
+    pool > 0 (long, fast streams whose distinct inputs would not fit in HBM):
+    sizes are rounded to 24 log-spaced orders in [64, nmax] and each request
+    takes one of `pool` matrices built for its order (each with its own
+    condition number) and the first nrhs columns of one right-hand-side
+    block per order; a re-solve uses its source's matrix."""
     dev = torch.device("cuda:0")
     reqs = G.serving_stream(rate, duration, seed, nmax=nmax)
     built = []
-    for i, r in enumerate(reqs):
-        src = r if r.resolve_of < 0 else reqs[r.resolve_of]
-        if r.resolve_of < 0:
-            A = G.householder_matrix(G.householder_spec(r.n, r.cond, r.seed % (2**31)), device="cuda:0")
-        else:
-            A = built[r.resolve_of][0]
-        g = torch.Generator(device=dev)
-        g.manual_seed(r.seed % (2**31))
-        B = torch.randn(r.n, r.nrhs, dtype=torch.float64, device=dev, generator=g)
-        built.append((A, B))
+    if pool > 0:
+        grid = np.unique(np.round(np.exp(np.linspace(np.log(64), np.log(nmax), 24))).astype(int))
+        mats, rhs = {}, {}
+        for gi, nn in enumerate(grid):
+            nn = int(nn)
+            mats[nn] = []
+            for q in range(pool):
+                gq = np.random.default_rng([seed, gi, q])
+                cond = float(np.exp(gq.uniform(np.log(1e2), np.log(1e8))))
+                mats[nn].append(G.householder_matrix(G.householder_spec(nn, cond, int(gq.integers(0, 2**31))),
+                                                     device="cuda:0"))
+            g = torch.Generator(device=dev)
+            g.manual_seed(seed * 1000 + gi)
+            rhs[nn] = torch.randn(nn, 16, dtype=torch.float64, device=dev, generator=g)
+        choice = []
+        for i, r in enumerate(reqs):
+            if r.resolve_of >= 0:
+                nn, q = choice[r.resolve_of]
+            else:
+                nn = int(grid[np.argmin(np.abs(np.log(grid) - np.log(r.n)))])
+                q = r.seed % pool
+            choice.append((nn, q))
+            built.append((mats[nn][q], rhs[nn][:, :r.nrhs]))
+        sizes = [c[0] for c in choice]
+    else:
+        for i, r in enumerate(reqs):
+            if r.resolve_of < 0:
+                A = G.householder_matrix(G.householder_spec(r.n, r.cond, r.seed % (2**31)), device="cuda:0")
+            else:
+                A = built[r.resolve_of][0]
+            g = torch.Generator(device=dev)
+            g.manual_seed(r.seed % (2**31))
+            B = torch.randn(r.n, r.nrhs, dtype=torch.float64, device=dev, generator=g)
+            built.append((A, B))
+        sizes = [r.n for r in reqs]
     torch.cuda.synchronize()
     out = {"rate_per_s": rate, "duration_s": duration, "requests": len(reqs), "n_range": [64, nmax],
-           "arena_gb": arena_gb, "slots": slots}
-    for prec in ("fp64", "bf16"):
-        kw = dict(precision=prec, v=256, leaves=8, tol=5e-15,
+           "arena_gb": arena_gb, "slots": slots, "lowp_min_n": lowp_min_n,
+           "factorisation": {"v": v, "leaves": leaves, "lookahead": lookahead},
+           "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES", "default")}
+    if pool > 0:
+        out["inputs"] = f"pooled: orders rounded to {len(grid)} log-spaced sizes, {pool} matrices per size"
+    nlog = max(50, len(reqs) // 20)
+    for label in passes:
+        prec = "fp64" if label == "fp64" else "bf16"
+        kw = dict(precision=prec, v=v, leaves=leaves, lookahead=lookahead, tol=5e-15,
                   max_outer=4 if prec == "fp64" else 3, gmres_restart=20, gmres_tol=1e-6)
-        srv = cfx.Server(int(arena_gb * (1 << 30)), max_slots=slots, **kw)
+        srv = cfx.Server(int(arena_gb * (1 << 30)), max_slots=slots,
+                         lowp_min_n=lowp_min_n if label == "bf16" else 0, **kw)
         tickets = [None] * len(reqs)
-        xs = [torch.zeros_like(b) for _, b in built]
+        xs = [None] * len(reqs)
         torch.cuda.synchronize()
         fid = {}
         results = [None] * len(reqs)
         t0 = time.perf_counter()
-        pending = []
+        pending = collections.deque()
+        backlog_end = 0
+
+        def collect(limit):
+            # the oldest pending requests first (they finish roughly in order)
+            k = 0
+            while pending and k < limit:
+                j = pending[0]
+                res = srv.poll(tickets[j])
+                if res is None:
+                    break
+                pending.popleft()
+                results[j] = res
+                xs[j] = None
+                if reqs[j].resolve_of < 0:
+                    fid[j] = res["factor_id"]
+                k += 1
+
         for i, r in enumerate(reqs):
             while time.perf_counter() - t0 < r.t_arrival:
                 time.sleep(2e-4)
             A, B = built[i]
+            xs[i] = torch.empty(sizes[i], r.nrhs, dtype=torch.float64, device=dev)
             if r.resolve_of >= 0 and r.resolve_of in fid:
                 tickets[i] = srv.submit(A, B, xs[i], kind=cfx.RESOLVE, factor_id=fid[r.resolve_of])
             else:
                 tickets[i] = srv.submit(A, B, xs[i], keep_resident=r.resolve_of < 0)
             pending.append(i)
-            if (i + 1) % 50 == 0:
-                log(f"serve {prec}: submitted {i + 1}/{len(reqs)}, {len(pending)} pending")
-            still = []
-            for j in pending:      # collect finished results without blocking
-                res = srv.poll(tickets[j])
-                if res is None:
-                    still.append(j)
-                    continue
-                results[j] = res
-                if reqs[j].resolve_of < 0:
-                    fid[j] = res["factor_id"]
-            pending = still
-        for c, j in enumerate(pending):
+            if (i + 1) % nlog == 0:
+                log(f"serve {label}: submitted {i + 1}/{len(reqs)}, {len(pending)} pending")
+            collect(64)
+        backlog_end = len(pending)
+        t_arrivals = time.perf_counter() - t0
+        c = 0
+        while pending:
+            j = pending.popleft()
             results[j] = srv.wait(tickets[j], timeout=600)
-            if (c + 1) % 20 == 0:
-                log(f"serve {prec}: draining, {c + 1}/{len(pending)} done")
+            xs[j] = None
+            if reqs[j].resolve_of < 0:
+                fid[j] = results[j]["factor_id"]
+            c += 1
+            if c % nlog == 0:
+                log(f"serve {label}: draining, {c}/{backlog_end} done")
         wall = time.perf_counter() - t0
         st = srv.stats()
         srv.close()
+        del srv, xs                   # the arena goes before the next pass allocates its own
+        torch.cuda.empty_cache()
         lat = np.array([r["t_done"] - r["t_submit"] for r in results])
         ok = [r for r in results if r["status"] == 0]
-        new_flops = sum(2.0 * reqs[i].n ** 3 / 3 for i, r in enumerate(results)
+        new_flops = sum(2.0 * sizes[i] ** 3 / 3 for i, r in enumerate(results)
                         if r["status"] == 0 and not r["resident_hit"])
-        solve_flops = sum(2.0 * reqs[i].n ** 2 * reqs[i].nrhs for i, r in enumerate(results) if r["status"] == 0)
+        solve_flops = sum(2.0 * sizes[i] ** 2 * reqs[i].nrhs for i, r in enumerate(results) if r["status"] == 0)
         etas = np.array([r["eta"] for r in ok])
         resolves = [i for i, q in enumerate(reqs) if q.resolve_of >= 0]
         hits = sum(1 for i in resolves if results[i]["resident_hit"])
-        out[prec] = {"p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
+        out[label] = {"p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
                      "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
                      "max_ms": round(1e3 * float(lat.max()), 3),
                      "wall_s": round(wall, 3),
+                     "backlog_at_last_arrival": backlog_end,
+                     "drain_s": round(wall - t_arrivals, 3),
+                     "completed_per_s": round(len(ok) / wall, 1),
                      "lu_tflops": round(new_flops / wall / 1e12, 3),
                      "lu_plus_solve_tflops": round((new_flops + solve_flops) / wall / 1e12, 3),
                      "failed": len(results) - len(ok),
@@ -513,7 +577,7 @@ def serve_leg(cfx, G, torch, rate, duration, seed, arena_gb, slots, nmax):
                      "fp64_fallbacks": sum(1 for r in ok if r.get("fallback", 0)),
                      "batched_requests": st["batched_requests"], "evictions": st["evictions"],
                      "bytes_peak_gb": round(st["bytes_peak"] / 2**30, 2)}
-        log(f"serve {prec}: {out[prec]}")
+        log(f"serve {label}: {out[label]}")
     del built
     torch.cuda.empty_cache()
     return out
@@ -553,6 +617,19 @@ def main():
     ap.add_argument("--serve-nmax", type=int, default=8192)
     ap.add_argument("--serve-arena-gb", type=float, default=64.0)
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-pool", type=int, default=0,
+                    help="pooled inputs: matrices per rounded order (0: one matrix per request)")
+    ap.add_argument("--serve-lowp-min-n", type=int, default=32768,
+                    help="the bf16 pass factors smaller requests in FP64 (measured crossover of BF16 + "
+                         "GMRES-IR against the FP64 solve on this device)")
+    ap.add_argument("--serve-passes", default="fp64,bf16,bf16_unrouted")
+    ap.add_argument("--serve-only", action="store_true", help="run the serving leg alone")
+    ap.add_argument("--serve-v", type=int, default=128, help="panel width of the served factorisations")
+    ap.add_argument("--serve-leaves", type=int, default=2, help="tournament leaves of the served factorisations")
+    ap.add_argument("--serve-lookahead", type=int, default=0)
+    ap.add_argument("--hw-queues", type=int, default=None,
+                    help="hardware queues of the process (GPU_MAX_HW_QUEUES, set before the runtime starts; "
+                         "the serving workers' streams share them)")
     ap.add_argument("--device-gen", action="store_true",
                     help="draw A and b on the device (seeded torch generator) instead of on the host; "
                          "used for the counter runs (no CPU baseline then)")
@@ -577,6 +654,10 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.hw_queues is not None:
+        if not 1 <= args.hw_queues <= 16:
+            raise SystemExit("--hw-queues takes 1..16")
+        os.environ["GPU_MAX_HW_QUEUES"] = str(int(args.hw_queues))
     import torch
     import cfx_inputs as G
     from paper_2010_05975_amd import cfx
@@ -585,6 +666,13 @@ def main():
     dev = torch.device("cuda:0")
     if args.tslu_bench:
         print(json.dumps({"tslu_bench": tslu_bench(cfx, torch, n, v, L, args.seed)}), flush=True)
+        return
+    if args.serve_only:
+        print(json.dumps({"serve": serve_leg(cfx, G, torch, args.serve_rate, args.serve_duration, args.seed + 13,
+                                             args.serve_arena_gb, args.serve_slots, args.serve_nmax,
+                                             args.serve_pool, args.serve_lowp_min_n,
+                                             tuple(args.serve_passes.split(",")), args.serve_v,
+                                             args.serve_leaves, args.serve_lookahead)}), flush=True)
         return
     if args.schur_replay:
         chunk = args.chunk or cfx.overlap_tuning()[1] or n     # 0: the whole rest in one launch
@@ -752,7 +840,9 @@ def main():
         out["batched"] = batched_leg(cfx, G, torch, args.batched_count, args.seed + 11, max(args.steps, 1))
     if not args.no_serve:
         out["serve"] = serve_leg(cfx, G, torch, args.serve_rate, args.serve_duration, args.seed + 13,
-                                 args.serve_arena_gb, args.serve_slots, args.serve_nmax)
+                                 args.serve_arena_gb, args.serve_slots, args.serve_nmax, args.serve_pool,
+                                 args.serve_lowp_min_n, tuple(args.serve_passes.split(",")), args.serve_v,
+                                 args.serve_leaves, args.serve_lookahead)
     if args.calibration_copy:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)

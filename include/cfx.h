@@ -422,6 +422,12 @@ typedef struct {
                                 ir.lu.precision FP64, ir.max_outer = 0 gives
                                 the plain solve                            */
     int32_t batch_max;       /* max systems per batched launch (0: 256)     */
+    int64_t lowp_min_n;      /* with a low-precision ir.lu.precision: the
+                                smallest order factored in that precision;
+                                smaller requests are factored in FP64 (the
+                                low-precision route only pays off for large
+                                systems).  0: every request in ir.lu's
+                                precision                                  */
 } cfx_serve_cfg;
 
 enum { CFX_SOLVE = 0, CFX_RESOLVE = 1 };

@@ -42,7 +42,7 @@ class IrReport(C.Structure):
 
 class ServeCfg(C.Structure):
     _fields_ = [("arena", C.c_void_p), ("arena_bytes", C.c_size_t), ("max_slots", C.c_int32),
-                ("ir", IrOpts), ("batch_max", C.c_int32)]
+                ("ir", IrOpts), ("batch_max", C.c_int32), ("lowp_min_n", C.c_int64)]
 
 
 class Request(C.Structure):
@@ -521,10 +521,10 @@ class Server:
     uint8 CUDA tensor owned here; A, B, X of a request are held until its
     result is polled (the library reads and writes them meanwhile)."""
 
-    def __init__(self, arena_bytes, max_slots=4, batch_max=0, **ir_kw):
+    def __init__(self, arena_bytes, max_slots=4, batch_max=0, lowp_min_n=0, **ir_kw):
         self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
         cfg = ServeCfg(C.c_void_p(self.arena.data_ptr()), arena_bytes, max_slots, ir_opts(**ir_kw),
-                       batch_max)
+                       batch_max, int(lowp_min_n))
         s = C.c_void_p()
         _check("cfx_serve_create", lib().cfx_serve_create(C.byref(cfg), C.byref(s)))
         self.s = s
@@ -578,6 +578,7 @@ class Server:
             lib().cfx_serve_destroy(self.s)
             self.s = None
             self.held.clear()
+            self.arena = None      # the server no longer touches it
 
     def __del__(self):
         try:

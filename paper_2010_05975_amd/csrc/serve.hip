@@ -362,7 +362,10 @@ int run_single(cfx_server *S, cfx_handle *h, hipStream_t st, Job *j)
         f->prec = o.precision;
         return CFX_OK;
     };
-    if (!j->hit) SRV_CHECK(factor(S->cfg.ir.lu));
+    // the request's precision: FP64 below the low-precision threshold
+    cfx_lu_opts o_req = S->cfg.ir.lu;
+    if (o_req.precision != CFX_PREC_FP64 && n < S->cfg.lowp_min_n) o_req.precision = CFX_PREC_FP64;
+    if (!j->hit) SRV_CHECK(factor(o_req));
     SRV_CHECK(launch_set_int(v.sync + 4, 0, st));   // give-up flag of the solves
     j->res.eta = 0.0;
     for (int64_t c = 0; c < r.nrhs; ++c) {

@@ -213,3 +213,29 @@ def test_serve_evicts_least_recently_used(cfx):
         assert r2["resident_hit"] == 1
     finally:
         srv.close()
+
+
+def test_lowp_routing_small_requests_take_fp64(cfx):
+    """A BF16 server with lowp_min_n routes smaller requests to FP64
+    factors: their results equal those of an FP64 server with the same
+    refinement settings bit for bit, while requests at or above the
+    threshold stay low precision (they need refinement steps)."""
+    say("serve lowp routing")
+    reqs = make_requests([600, 800, 1000], 61, cond=1e4)   # above the batched sizes
+    kw = dict(v=64, leaves=4, tol=5e-15, max_outer=3, gmres_restart=20, gmres_tol=1e-6)
+    srv64 = cfx.Server(256 << 20, max_slots=1, precision="fp64", **kw)
+    srvr = cfx.Server(256 << 20, max_slots=1, precision="bf16", lowp_min_n=900, **kw)
+    try:
+        a = solve_alone(srv64, reqs)
+        b = solve_alone(srvr, reqs)
+    finally:
+        srv64.close()
+        srvr.close()
+    for (xa, ra), (xb, rb), (A, B) in zip(a, b, reqs):
+        assert ra["status"] == rb["status"] == 0
+        assert O.eta(A, xb, B) <= 5e-15
+    for i in (0, 1):                      # n < 900: FP64 factors on both servers
+        assert np.array_equal(a[i][0], b[i][0])
+        assert b[i][1]["fallback"] == 0 and b[i][1]["batched"] == 0
+    assert b[2][1]["outer"] >= 1          # n = 1000: BF16 factors, refined
+    assert a[2][1]["outer"] == 0
