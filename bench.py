@@ -89,6 +89,10 @@ def committed_traffic(n, v, L, field="traffic_bytes_per_launch", launches=None, 
 # Fast memory of one processor at the two levels of the MI355X hierarchy
 # (FP64 elements): an XCD (4 MiB L2 + 32 compute units x (160 KiB LDS +
 # 512 KiB registers)) and a compute unit (LDS + registers).
+# leaves of at least this many rows in every factorisation of the bench
+# (cfx_lu_opts.min_leaf_rows; set from --min-leaf-rows)
+MIN_LEAF = 0
+
 M_XCD = (4 * 2**20 + 32 * (160 + 512) * 2**10) // 8
 M_CU = ((160 + 512) * 2**10) // 8
 
@@ -155,12 +159,15 @@ def tslu_bench(cfx, torch, n, v, L, seed, reps=5):
     panel, no other work on the device) on N(0,1) panels of the heights the
     factorisation meets (rows = n - k), with the factorisation's leaf count,
     plus a single 2v-row node (one leaf of a merge's size): median time per
-    call and per pivot step (HIP events)."""
+    call and per pivot step (HIP events).  Leaf counts follow the bench's
+    minimum leaf height."""
     dev = torch.device("cuda:0")
     g = torch.Generator(device=dev)
     g.manual_seed(seed)
     out = []
-    cases = [(r, L) for r in (n, (3 * n) // 4, n // 2, n // 4, n // 8, 4 * v)] + [(2 * v, 1), (v, 1)]
+    def leaves_of(r):
+        return min(L, max(1, -(-r // MIN_LEAF))) if MIN_LEAF else L
+    cases = [(r, leaves_of(r)) for r in (n, (3 * n) // 4, n // 2, n // 4, n // 8, 4 * v)] + [(2 * v, 1), (v, 1)]
     for rows, leaves in cases:
         W = torch.randn(rows, v, dtype=torch.float64, device=dev, generator=g)
         work = cfx.workspace(rows, v, leaves, "fp64", 0, dev)
@@ -230,6 +237,7 @@ def masked_leg(cfx, torch, pristine, A_swapped, ipiv, n, v, L, lookahead, work, 
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         cfx.getrf_masked(M, v=v, leaves=L, lookahead=lookahead, work=work, ipiv=ipm, rowmap=rowmap, info=info,
+                         min_leaf_rows=MIN_LEAF,
                          stream=stream)
         e1.record(stream)
         torch.cuda.synchronize()
@@ -264,7 +272,7 @@ def delayed_leg(cfx, torch, pristine, A_ref, n, v, L, lookahead, work, stream, d
     info = torch.empty(1, dtype=torch.int32, device=pristine.device)
     for d in delays:
         cfx.set_schur_delay(d)
-        wk = cfx.workspace(n, v, L, "fp64", lookahead, pristine.device)
+        wk = cfx.workspace(n, v, L, "fp64", lookahead, pristine.device, min_leaf_rows=MIN_LEAF)
         times = []
         for it in range(reps + 1):
             M.copy_(pristine)
@@ -273,7 +281,8 @@ def delayed_leg(cfx, torch, pristine, A_ref, n, v, L, lookahead, work, stream, d
                 cfx.profile_begin()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            cfx.getrf(M, v=v, leaves=L, lookahead=lookahead, work=wk, ipiv=ipiv, info=info, stream=stream)
+            cfx.getrf(M, v=v, leaves=L, lookahead=lookahead, work=wk, ipiv=ipiv, info=info, stream=stream,
+                      min_leaf_rows=MIN_LEAF)
             e1.record(stream)
             torch.cuda.synchronize()
             if it:
@@ -307,7 +316,7 @@ def ir_leg(cfx, G, torch, n, v, L, conds, precs, seed, check_oracle):
     stream = torch.cuda.current_stream()
     out = {"n": n, "v": v, "leaves": L, "tol": 5e-15, "gmres_restart": 30, "gmres_tol": 1e-6,
            "max_outer": 20, "cases": []}
-    work_lu = cfx.workspace(n, v, L, "fp64", 1, dev)
+    work_lu = cfx.workspace(n, v, L, "fp64", 1, dev, min_leaf_rows=MIN_LEAF)
     for cond in conds:
         spec = G.householder_spec(n, cond, seed)
         A = G.householder_matrix(spec, device="cuda:0")
@@ -320,7 +329,7 @@ def ir_leg(cfx, G, torch, n, v, L, conds, precs, seed, check_oracle):
         x = b.clone()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ipiv, info = cfx.getrf(F, v=v, leaves=L, lookahead=1, work=work_lu, stream=stream)
+        ipiv, info = cfx.getrf(F, v=v, leaves=L, lookahead=1, work=work_lu, stream=stream, min_leaf_rows=MIN_LEAF)
         cfx.getrs(F, ipiv, x, stream=stream)
         torch.cuda.synchronize()
         t_plain = time.perf_counter() - t0
@@ -331,12 +340,12 @@ def ir_leg(cfx, G, torch, n, v, L, conds, precs, seed, check_oracle):
         del F
         torch.cuda.empty_cache()
         for prec in ["fp64"] + list(precs):
-            nbytes = cfx.gesv_ir_buffer_size(n, 1, precision=prec, v=v, leaves=L, lookahead=1)
+            nbytes = cfx.gesv_ir_buffer_size(n, 1, precision=prec, v=v, leaves=L, lookahead=1, min_leaf_rows=MIN_LEAF)
             work = torch.empty(nbytes, dtype=torch.uint8, device=dev)
             X = torch.empty_like(b)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            X, rep = cfx.gesv_ir(A, b, X=X, work=work, stream=stream, precision=prec, v=v, leaves=L,
+            X, rep = cfx.gesv_ir(A, b, X=X, work=work, stream=stream, precision=prec, v=v, leaves=L, min_leaf_rows=MIN_LEAF,
                                  lookahead=1, tol=5e-15, max_outer=out["max_outer"],
                                  gmres_restart=out["gmres_restart"], gmres_tol=out["gmres_tol"])
             torch.cuda.synchronize()
@@ -591,6 +600,9 @@ def main():
     ap.add_argument("--n", type=int, default=32768)
     ap.add_argument("--v", type=int, default=256)
     ap.add_argument("--leaves", type=int, default=8)
+    ap.add_argument("--min-leaf-rows", type=int, default=4096,
+                    help="leaves of at least this many rows: a panel of r rows has min(L, ceil(r / R)) leaves "
+                         "(0: L leaves for every panel)")
     ap.add_argument("--lookahead", type=int, default=1)
     ap.add_argument("--schur-wgs", type=int, default=None,
                     help="grid bound of the overlapped Schur launches (cfx_set_overlap_tuning; "
@@ -663,6 +675,8 @@ def main():
     from paper_2010_05975_amd import cfx
 
     n, v, L = args.n, args.v, args.leaves
+    global MIN_LEAF
+    MIN_LEAF = args.min_leaf_rows
     dev = torch.device("cuda:0")
     if args.tslu_bench:
         print(json.dumps({"tslu_bench": tslu_bench(cfx, torch, n, v, L, args.seed)}), flush=True)
@@ -707,7 +721,7 @@ def main():
         cfx.set_schur_delay(args.delay)
     if args.reserve_cus is not None:
         cfx.set_reserved_cus(args.reserve_cus)
-    work = cfx.workspace(n, v, L, "fp64", args.lookahead, dev)
+    work = cfx.workspace(n, v, L, "fp64", args.lookahead, dev, min_leaf_rows=MIN_LEAF)
     if args.schur_wgs is not None or args.chunk is not None or args.one_stream:
         w0, c0, _ = cfx.overlap_tuning()
         cfx.set_overlap_tuning(w0 if args.schur_wgs is None else args.schur_wgs,
@@ -722,7 +736,7 @@ def main():
         B.copy_(pb)
         e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
         e0.record(stream)
-        cfx.getrf(A, v=v, leaves=L, lookahead=args.lookahead, work=work, ipiv=ipiv, info=info,
+        cfx.getrf(A, v=v, leaves=L, lookahead=args.lookahead, work=work, ipiv=ipiv, info=info, min_leaf_rows=MIN_LEAF,
                   stream=stream)
         e1.record(stream)
         cfx.getrs(A, ipiv, B, stream=stream)
@@ -804,8 +818,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"FP64 getrf+getrs, N={n}, v={v}, L={L} leaves, A~N(0,1) seed "
-                               f"{args.seed}, 1 RHS, lookahead={args.lookahead}"},
+        "config": {"workload": f"FP64 getrf+getrs, N={n}, v={v}, L={L} leaves"
+                               + (f" of at least {MIN_LEAF} rows" if MIN_LEAF else "")
+                               + f", A~N(0,1) seed {args.seed}, 1 RHS, lookahead={args.lookahead}"},
         "pct_fp64_peak": round(100 * value / FP64_PEAK_TFLOPS, 2),
         "getrf_ms": round(getrf_ms, 3),
         "getrs_ms": round(getrs_ms, 3),

@@ -64,8 +64,12 @@ enum {
 /* Options of the tournament-pivoted LU.
  *   v         : panel width (Alg. 1 blocking parameter v), 1..256.
  *   leaves    : leaf count L of the tournament; a panel with r rows left has
- *               leaves of h = max(v, ceil(r / L)) rows (the last one may be
- *               shorter).  h must not exceed 8192 rows.
+ *               L_r leaves of h = max(v, ceil(r / L_r)) rows (the last one
+ *               may be shorter), L_r = L, or with min_leaf_rows = R > 0
+ *               L_r = min(L, max(1, ceil(r / R))): leaves of at least R rows
+ *               (TP(v, L_r), Sec. 7.3, with the leaf count following the
+ *               panel's height: fewer tree levels for short panels).  h must
+ *               not exceed 8192 rows.
  *   precision : CFX_PREC_*; the pivot search, row interchanges and both
  *               triangular solves are always FP64.  With BF16/FP16/FP8 each
  *               Schur update rounds L21 and U12 to that format (to nearest,
@@ -76,12 +80,14 @@ enum {
  *               sum (FP8: scaled back exactly) from the FP64 trailing
  *               matrix.
  *   lookahead : 0 or 1; 1 overlaps the next panel's tournament with the
- *               rest of the current Schur update on a second stream. */
+ *               rest of the current Schur update on a second stream.
+ *   min_leaf_rows : R above; 0 (fixed L) or 1..8192. */
 typedef struct {
     int32_t v;
     int32_t leaves;
     int32_t precision;
     int32_t lookahead;
+    int32_t min_leaf_rows;
 } cfx_lu_opts;
 
 typedef struct cfx_handle cfx_handle;

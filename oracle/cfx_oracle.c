@@ -168,7 +168,7 @@ int oracle_tslu(int64_t rows, int64_t vb, const double *W, int64_t ldw,
 }
 
 int oracle_getrf(int64_t n, double *A, int64_t lda, int64_t v, int64_t L,
-                 int32_t *ipiv, int32_t *info, double *margins,
+                 int64_t min_leaf, int32_t *ipiv, int32_t *info, double *margins,
                  int64_t npanels, oracle_counters *cnt)
 {
     if (n < 0) return -1;
@@ -176,8 +176,9 @@ int oracle_getrf(int64_t n, double *A, int64_t lda, int64_t v, int64_t L,
     if (lda < (n > 1 ? n : 1)) return -3;
     if (v < 1) return -4;
     if (L < 1) return -5;
-    if (!ipiv && n > 0) return -6;
-    if (!info) return -7;
+    if (min_leaf < 0) return -6;
+    if (!ipiv && n > 0) return -7;
+    if (!info) return -8;
 
     *info = 0;
     int64_t ndiv = 0, nms = 0;
@@ -193,9 +194,17 @@ int oracle_getrf(int64_t n, double *A, int64_t lda, int64_t v, int64_t L,
         int64_t vb = (n - k < v) ? n - k : v;
         int64_t m = n - k - vb;  /* trailing size */
 
-        /* TournPivot on the current panel A[k:n, k:k+vb]. */
+        /* TournPivot on the current panel A[k:n, k:k+vb], over L leaves,
+         * or with a minimum leaf height over ceil(rows / min_leaf) of them
+         * (at most L, at least 1). */
+        int64_t Lk = L;
+        if (min_leaf > 0) {
+            Lk = (n - k + min_leaf - 1) / min_leaf;
+            if (Lk > L) Lk = L;
+            if (Lk < 1) Lk = 1;
+        }
         double mm = 1.0;
-        oracle_tslu(n - k, vb, A + k * lda + k, lda, k, L, piv, &mm);
+        oracle_tslu(n - k, vb, A + k * lda + k, lda, k, Lk, piv, &mm);
         if (margins) margins[panel] = mm;
 
         /* Row interchanges over all n columns, LAPACK-style, in order. */

@@ -39,6 +39,9 @@ int oracle_tslu(int64_t rows, int64_t vb, const double *W, int64_t ldw,
 /* Blocked right-looking LU, A = P L U, with tournament pivoting TP(v, L)
  * (Alg. 1 compute steps: TournPivot, FactorizeA10, FactorizeA01,
  * FactorizeA11), with explicit row interchanges.
+ *   min_leaf : 0, or R > 0: a panel with r rows has min(L, max(1,
+ *              ceil(r / R))) leaves (leaves of at least R rows; the leaf
+ *              count follows the panel's height).
  *   A        : n x n, overwritten by L (strict lower, unit diagonal
  *              implicit) and U (upper).
  *   ipiv     : out int32[n]; row i was interchanged with row ipiv[i] >= i,
@@ -50,7 +53,7 @@ int oracle_tslu(int64_t rows, int64_t vb, const double *W, int64_t ldw,
  *   cnt      : out counters (may be NULL).
  * Returns 0, or a negative argument index. */
 int oracle_getrf(int64_t n, double *A, int64_t lda, int64_t v, int64_t L,
-                 int32_t *ipiv, int32_t *info, double *margins,
+                 int64_t min_leaf, int32_t *ipiv, int32_t *info, double *margins,
                  int64_t npanels, oracle_counters *cnt);
 
 /* Solve A X = B with the factors of oracle_getrf: apply ipiv to B in order,

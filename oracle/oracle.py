@@ -33,7 +33,7 @@ def lib():
         L.oracle_tslu.argtypes = [C.c_int64, C.c_int64, dp, C.c_int64, C.c_int64,
                                   C.c_int64, i64p, dp]
         L.oracle_tslu.restype = C.c_int
-        L.oracle_getrf.argtypes = [C.c_int64, dp, C.c_int64, C.c_int64, C.c_int64,
+        L.oracle_getrf.argtypes = [C.c_int64, dp, C.c_int64, C.c_int64, C.c_int64, C.c_int64,
                                    i32p, i32p, dp, C.c_int64, C.POINTER(_Counters)]
         L.oracle_getrf.restype = C.c_int
         L.oracle_getrs.argtypes = [C.c_int64, C.c_int64, dp, C.c_int64, i32p, dp, C.c_int64]
@@ -75,8 +75,10 @@ class Factorization:
         self.counters = counters
 
 
-def getrf(A: np.ndarray, v: int, L: int, npanels: int = 0, overwrite: bool = False):
-    """TP(v, L) LU of a square row-major matrix.  Returns a Factorization."""
+def getrf(A: np.ndarray, v: int, L: int, npanels: int = 0, overwrite: bool = False, min_leaf_rows: int = 0):
+    """TP(v, L) LU of a square row-major matrix.  Returns a Factorization.
+    min_leaf_rows = R > 0: a panel with r rows has min(L, max(1, ceil(r/R)))
+    leaves."""
     A = np.ascontiguousarray(A, dtype=np.float64)
     if not overwrite:
         A = A.copy()
@@ -87,7 +89,7 @@ def getrf(A: np.ndarray, v: int, L: int, npanels: int = 0, overwrite: bool = Fal
     npan = (n + v - 1) // v if (n > 0 and v > 0) else 0
     margins = np.ones(max(npan, 1), dtype=np.float64)
     cnt = _Counters()
-    rc = lib().oracle_getrf(n, _dp(A), max(n, 1), v, L,
+    rc = lib().oracle_getrf(n, _dp(A), max(n, 1), v, L, min_leaf_rows,
                             ipiv.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(info),
                             _dp(margins), npanels, C.byref(cnt))
     if rc != 0:

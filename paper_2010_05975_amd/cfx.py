@@ -24,7 +24,7 @@ _lib = None
 
 class LuOpts(C.Structure):
     _fields_ = [("v", C.c_int32), ("leaves", C.c_int32), ("precision", C.c_int32),
-                ("lookahead", C.c_int32)]
+                ("lookahead", C.c_int32), ("min_leaf_rows", C.c_int32)]
 
 
 class IrOpts(C.Structure):
@@ -210,21 +210,21 @@ def version() -> str:
     return lib().cfx_version().decode()
 
 
-def getrf_buffer_size(n, v=256, leaves=64, precision="fp64", lookahead=0, handle=None):
+def getrf_buffer_size(n, v=256, leaves=64, precision="fp64", lookahead=0, handle=None, min_leaf_rows=0):
     h = handle or default_handle()
-    o = LuOpts(v, leaves, PREC[precision], lookahead)
+    o = LuOpts(v, leaves, PREC[precision], lookahead, min_leaf_rows)
     b = C.c_size_t()
     _check("cfx_getrf_buffer_size", lib().cfx_getrf_buffer_size(h.h, n, C.byref(o), C.byref(b)))
     return b.value
 
 
-def workspace(n, v=256, leaves=64, precision="fp64", lookahead=0, device=None, handle=None):
-    nbytes = getrf_buffer_size(n, v, leaves, precision, lookahead, handle)
+def workspace(n, v=256, leaves=64, precision="fp64", lookahead=0, device=None, handle=None, min_leaf_rows=0):
+    nbytes = getrf_buffer_size(n, v, leaves, precision, lookahead, handle, min_leaf_rows)
     return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device or "cuda")
 
 
 def getrf(A, v=256, leaves=64, precision="fp64", lookahead=0, work=None, ipiv=None, info=None,
-          stream=None, handle=None):
+          stream=None, handle=None, min_leaf_rows=0):
     """cfx_getrf: factor A in place; returns (ipiv int32[n], info int32[1])."""
     h = handle or default_handle()
     lda = _mat(A, "A")
@@ -236,15 +236,15 @@ def getrf(A, v=256, leaves=64, precision="fp64", lookahead=0, work=None, ipiv=No
     if info is None:
         info = torch.empty(1, dtype=torch.int32, device=A.device)
     if work is None:
-        work = workspace(n, v, leaves, precision, lookahead, A.device, h)
-    o = LuOpts(v, leaves, PREC[precision], lookahead)
+        work = workspace(n, v, leaves, precision, lookahead, A.device, h, min_leaf_rows)
+    o = LuOpts(v, leaves, PREC[precision], lookahead, min_leaf_rows)
     _check("cfx_getrf", lib().cfx_getrf(h.h, n, _ptr(A), lda, _ptr(ipiv), _ptr(info), C.byref(o),
                                         _ptr(work), work.numel(), _stream(stream)))
     return ipiv[:n], info
 
 
 def getrf_masked(A, v=256, leaves=64, precision="fp64", lookahead=0, work=None, ipiv=None, rowmap=None,
-                 info=None, stream=None, handle=None):
+                 info=None, stream=None, handle=None, min_leaf_rows=0):
     """cfx_getrf_masked: factor A in place without moving rows; returns
     (ipiv, rowmap, info) (int32 device tensors)."""
     h = handle or default_handle()
@@ -259,8 +259,8 @@ def getrf_masked(A, v=256, leaves=64, precision="fp64", lookahead=0, work=None, 
     if info is None:
         info = torch.empty(1, dtype=torch.int32, device=A.device)
     if work is None:
-        work = workspace(n, v, leaves, precision, lookahead, A.device, h)
-    o = LuOpts(v, leaves, PREC[precision], lookahead)
+        work = workspace(n, v, leaves, precision, lookahead, A.device, h, min_leaf_rows)
+    o = LuOpts(v, leaves, PREC[precision], lookahead, min_leaf_rows)
     _check("cfx_getrf_masked", lib().cfx_getrf_masked(h.h, n, _ptr(A), lda, _ptr(ipiv), _ptr(rowmap), _ptr(info),
                                                       C.byref(o), _ptr(work), work.numel(), _stream(stream)))
     return ipiv, rowmap, info
@@ -351,8 +351,8 @@ def set_solve_spin_limit(polls, handle=None):
 
 
 def ir_opts(precision="bf16", v=256, leaves=64, lookahead=0, tol=5e-15, max_outer=20,
-            gmres_restart=30, gmres_tol=1e-6):
-    return IrOpts(LuOpts(v, leaves, PREC[precision], lookahead), tol, max_outer, gmres_restart,
+            gmres_restart=30, gmres_tol=1e-6, min_leaf_rows=0):
+    return IrOpts(LuOpts(v, leaves, PREC[precision], lookahead, min_leaf_rows), tol, max_outer, gmres_restart,
                   gmres_tol)
 
 

@@ -111,11 +111,14 @@ struct Layout {
         off_utg, off_rtg, off_mp, total;
 };
 
-static Layout layout(int64_t n, int v, int leaves, int precision, int delay)
+static Layout layout(int64_t n, int v, int leaves, int precision, int delay, int min_leaf)
 {
     Layout L{};
     int64_t h0 = (n + leaves - 1) / leaves;
     if (h0 < v) h0 = v;
+    // with a minimum leaf height R, panels shorter than L R rows have
+    // fewer leaves of up to R rows
+    if (min_leaf > 0 && (n < min_leaf ? n : min_leaf) > h0) h0 = n < min_leaf ? n : min_leaf;
     // A panel with r rows has ceil(r / max(vb, ceil(r / leaves))) <= leaves
     // nodes; that count is not monotone in r, so bound it by leaves (and n).
     L.max_nodes = leaves < n ? leaves : n;
@@ -140,15 +143,15 @@ static Layout layout(int64_t n, int v, int leaves, int precision, int delay)
     return L;
 }
 
-size_t workspace_bytes(int64_t n, int v, int leaves, int precision, int delay)
+size_t workspace_bytes(int64_t n, int v, int leaves, int precision, int delay, int min_leaf)
 {
-    return layout(n, v, leaves, precision, delay).total;
+    return layout(n, v, leaves, precision, delay, min_leaf).total;
 }
 
 int carve_workspace(void *work, size_t bytes, int64_t n, int v, int leaves, int precision,
-                    Workspace *ws, int delay)
+                    Workspace *ws, int delay, int min_leaf)
 {
-    Layout L = layout(n, v, leaves, precision, delay);
+    Layout L = layout(n, v, leaves, precision, delay, min_leaf);
     if (bytes < L.total) return CFX_ENOMEM;
     char *b = static_cast<char *>(work);
     ws->S = reinterpret_cast<double *>(b + L.off_S);
@@ -179,6 +182,7 @@ static int check_opts(const cfx_lu_opts *o)
         o->precision != CFX_PREC_FP8)
         return 2;
     if (o->lookahead < 0 || o->lookahead > 1) return 1;
+    if (o->min_leaf_rows < 0 || o->min_leaf_rows > kMaxLeafRows) return 1;
     return 0;
 }
 
@@ -220,7 +224,7 @@ static IrLayout ir_layout(int64_t n, const cfx_ir_opts *o, int delay)
     L.off_perm = p;  p = align_up(p + (size_t)n * sizeof(int32_t));
     L.off_info = p;  p = align_up(p + sizeof(int32_t));
     L.off_getrf = p;
-    L.getrf_bytes = workspace_bytes(n, o->lu.v, o->lu.leaves, o->lu.precision, delay);
+    L.getrf_bytes = workspace_bytes(n, o->lu.v, o->lu.leaves, o->lu.precision, delay, o->lu.min_leaf_rows);
     p = align_up(p + L.getrf_bytes);
     L.off_vec = p;   p = align_up(p + ir_vec_bytes(n, o->gmres_restart));
     L.total = p;
@@ -341,7 +345,7 @@ int cfx_getrf_buffer_size(cfx_handle *h, int64_t n, const cfx_lu_opts *opts, siz
     if (n < 0) return -2;
     if (check_opts(opts)) return check_opts(opts) == 2 ? CFX_ENOTSUP : -3;
     if (!bytes) return -4;
-    *bytes = workspace_bytes(n, opts->v, opts->leaves, opts->precision, h->delay);
+    *bytes = workspace_bytes(n, opts->v, opts->leaves, opts->precision, h->delay, opts->min_leaf_rows);
     return CFX_OK;
 }
 
@@ -387,8 +391,8 @@ static int getrf_run_delayed(cfx_handle *h, int64_t n, double *A, int64_t lda, i
     auto tslu = [&](int64_t k, hipStream_t s) -> int {
         const int vb = (int)((n - k) < v ? (n - k) : v);
         hipEvent_t e = pf.begin(s);
-        const int rc =
-            launch_tslu(at(k, k), lda, k, n - k, vb, Lv, ws, nullptr, ipiv, info, s, nullptr, h->fuse_rows);
+        const int rc = launch_tslu(at(k, k), lda, k, n - k, vb, panel_leaves(Lv, opts->min_leaf_rows, n - k), ws,
+                                   nullptr, ipiv, info, s, nullptr, h->fuse_rows);
         pf.end(PH_TSLU, e, s);
         return rc;
     };
@@ -479,14 +483,15 @@ static int getrf_run(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *
     int rc = launch_set_int(info, 0, st);
     if (rc || n == 0) return rc;
 
-    const int v = opts->v, L = opts->leaves;
+    const int v = opts->v, L = opts->leaves, ml = opts->min_leaf_rows;
     {
         int64_t h0 = (n + L - 1) / L;
         if (h0 < v) h0 = v;
         if (h0 > kMaxLeafRows) return CFX_ENOTSUP;
     }
     Workspace ws;
-    if ((rc = carve_workspace(work, work_bytes, n, v, L, opts->precision, &ws, h->delay))) return rc;
+    if ((rc = carve_workspace(work, work_bytes, n, v, L, opts->precision, &ws, h->delay, opts->min_leaf_rows)))
+        return rc;
     if (rm && (rc = launch_rowmap_init(rm, n, st))) return rc;
     if (h->delay > 1) {
         if (rm) return CFX_ENOTSUP;
@@ -530,7 +535,8 @@ static int getrf_run(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *
             const int vb = (int)((n - k) < v ? (n - k) : v);
             const int64_t m = n - k - vb;
             hipEvent_t e = pf.begin(st);
-            if ((rc = launch_tslu(panel_w(k), lda, k, n - k, vb, L, ws, nullptr, ipiv, info, st, rm,
+            if ((rc = launch_tslu(panel_w(k), lda, k, n - k, vb, panel_leaves(L, ml, n - k), ws, nullptr, ipiv,
+                                  info, st, rm,
                                   h->fuse_rows)))
                 return rc;
             pf.end(PH_TSLU, e, st);
@@ -561,7 +567,8 @@ static int getrf_run(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *
     {
         const int vb0 = (int)(n < v ? n : v);
         hipEvent_t e = pf.begin(st);
-        if ((rc = launch_tslu(panel_w(0), lda, 0, n, vb0, L, ws, nullptr, ipiv, info, st, rm, h->fuse_rows)))
+        if ((rc = launch_tslu(panel_w(0), lda, 0, n, vb0, panel_leaves(L, ml, n), ws, nullptr, ipiv, info, st, rm,
+                              h->fuse_rows)))
             return rc;
         pf.end(PH_TSLU, e, st);
     }
@@ -597,7 +604,8 @@ static int getrf_run(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *
             if (us != st) CFX_HIP(hipStreamWaitEvent(us, h->ev_panel, 0));
             const int64_t kn = k + vb;
             e = pf.begin(ts);
-            if ((rc = launch_tslu(panel_w(kn), lda, kn, n - kn, vbn, L, ws, nullptr, ipiv, info, ts, rm,
+            if ((rc = launch_tslu(panel_w(kn), lda, kn, n - kn, vbn, panel_leaves(L, ml, n - kn), ws, nullptr,
+                                  ipiv, info, ts, rm,
                                   h->fuse_rows)))
                 return rc;
             pf.end(PH_TSLU, e, ts);

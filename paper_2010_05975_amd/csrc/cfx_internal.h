@@ -41,9 +41,17 @@ struct Workspace {
 // Bytes of workspace for order n and options; and the carve-up.
 // delay: panels per trailing update of the tile-stationary schedule (the
 // low-precision packed operands then hold K = delay v).
-size_t workspace_bytes(int64_t n, int v, int leaves, int precision, int delay = 1);
+size_t workspace_bytes(int64_t n, int v, int leaves, int precision, int delay = 1, int min_leaf = 0);
+// Leaves of the tournament of a panel with `rows` rows: L, or with a
+// minimum leaf height R > 0, min(L, max(1, ceil(rows / R))).
+inline int panel_leaves(int leaves, int min_leaf, int64_t rows)
+{
+    if (min_leaf <= 0) return leaves;
+    const int64_t k = (rows + min_leaf - 1) / min_leaf;
+    return (int)(k < 1 ? 1 : (k < leaves ? k : leaves));
+}
 int carve_workspace(void *work, size_t bytes, int64_t n, int v, int leaves,
-                    int precision, Workspace *ws, int delay = 1);
+                    int precision, Workspace *ws, int delay = 1, int min_leaf = 0);
 
 // Tournament pivoting of the rows x vb panel at W (stride ldw); panel row i
 // is global row row0 + i.  When `ipiv` is set the root also turns the

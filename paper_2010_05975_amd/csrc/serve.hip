@@ -146,7 +146,8 @@ namespace {
 size_t single_scratch(const cfx_server *S, int64_t n)
 {
     const int restart = S->cfg.ir.gmres_restart;
-    return al(256) + al(workspace_bytes(n, S->cfg.ir.lu.v, S->cfg.ir.lu.leaves, S->cfg.ir.lu.precision)) +
+    return al(256) + al(workspace_bytes(n, S->cfg.ir.lu.v, S->cfg.ir.lu.leaves, S->cfg.ir.lu.precision, 1,
+                                                 S->cfg.ir.lu.min_leaf_rows)) +
            al(ir_vec_bytes(n, restart));
 }
 
@@ -340,7 +341,8 @@ int run_single(cfx_server *S, cfx_handle *h, hipStream_t st, Job *j)
     char *sp = S->base() + j->soff;
     int32_t *dinfo = reinterpret_cast<int32_t *>(sp);
     char *wk = sp + al(256);
-    const size_t wbytes = workspace_bytes(n, S->cfg.ir.lu.v, S->cfg.ir.lu.leaves, S->cfg.ir.lu.precision);
+    const size_t wbytes = workspace_bytes(n, S->cfg.ir.lu.v, S->cfg.ir.lu.leaves, S->cfg.ir.lu.precision, 1,
+                                                 S->cfg.ir.lu.min_leaf_rows);
     IrVectors v = carve_ir(wk + al(wbytes), n, S->cfg.ir.gmres_restart);
     IrParams p{S->cfg.ir.tol, S->cfg.ir.max_outer, S->cfg.ir.gmres_tol};
     p.spin_limit = solve_spin_limit(h);
@@ -557,9 +559,11 @@ int cfx_serve_create(const cfx_serve_cfg *cfg, cfx_server **out)
     if (!cfg->arena || (reinterpret_cast<uintptr_t>(cfg->arena) & 255) || cfg->arena_bytes < 4096) return -1;
     if (cfg->max_slots < 1 || cfg->max_slots > 64) return -1;
     if (cfg->batch_max < 0) return -1;
+    if (cfg->lowp_min_n < 0) return -1;
     {
         const cfx_ir_opts &o = cfg->ir;
-        if (o.lu.v < 1 || o.lu.v > kMaxV || o.lu.leaves < 1 || o.lu.lookahead < 0 || o.lu.lookahead > 1)
+        if (o.lu.v < 1 || o.lu.v > kMaxV || o.lu.leaves < 1 || o.lu.lookahead < 0 || o.lu.lookahead > 1 ||
+            o.lu.min_leaf_rows < 0 || o.lu.min_leaf_rows > kMaxLeafRows)
             return -1;
         if (o.lu.precision != CFX_PREC_FP64 && o.lu.precision != CFX_PREC_BF16 && o.lu.precision != CFX_PREC_FP16 &&
             o.lu.precision != CFX_PREC_FP8)

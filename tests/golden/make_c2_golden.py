@@ -2,7 +2,8 @@
 
 For A ~ N(0, 1) (seed 0, the generator in cfx_inputs) of order N in
 {16384, 32768}, the CPU oracle runs the whole TP(v = 256, L = 8)
-factorisation (Alg. 1 with tournament pivoting, Sec. 7.3 / Sec. 7.4 Step 1)
+factorisation with leaves of at least 4096 rows (min(8, ceil(r / 4096))
+leaves for a panel of r rows) (Alg. 1 with tournament pivoting, Sec. 7.3 / Sec. 7.4 Step 1)
 and this script stores, per N, in c2_n<N>_seed0.npz:
   ipiv      int32[N]   the oracle's LAPACK-style interchanges
   margins   float64[N/256]  minimum pivot margin of every panel
@@ -37,6 +38,7 @@ import cfx_inputs as G  # noqa: E402
 from oracle import oracle as O  # noqa: E402
 
 V, LEAVES, SEED = 256, 8, 0
+MIN_LEAF_ROWS = 4096      # leaves of at least 4096 rows: min(8, ceil(r / 4096)) per panel
 
 
 def path(n: int) -> str:
@@ -72,7 +74,7 @@ def make(n: int) -> None:
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     print(f"N={n}: oracle getrf (v={V}, L={LEAVES}, {threads} threads) ...", flush=True)
     t0 = time.time()
-    f = O.getrf(A, V, LEAVES)
+    f = O.getrf(A, V, LEAVES, min_leaf_rows=MIN_LEAF_ROWS)
     t1 = time.time()
     print(f"  {t1 - t0:.0f} s; min margin {f.margins.min():.3e}; info {f.info}", flush=True)
     res = frob_residual(A, f.LU, f.ipiv)
@@ -80,6 +82,7 @@ def make(n: int) -> None:
     np.savez_compressed(path(n), ipiv=f.ipiv.astype(np.int32), margins=f.margins.astype(np.float64),
                         info=np.int32(f.info), residual=np.float64(res), digest=np.str_(dg),
                         v=np.int32(V), leaves=np.int32(LEAVES), seed=np.int32(SEED),
+                        min_leaf_rows=np.int32(MIN_LEAF_ROWS),
                         numpy_version=np.str_(np.__version__), seconds=np.float64(t1 - t0),
                         threads=np.int32(threads))
 

@@ -350,7 +350,8 @@ def gpu_frob_residual(A0, LU, perm, block=2048):
 @pytest.mark.parametrize("n", [16384, 32768])
 def test_getrf_full_size_against_stored_oracle(cfx, n):
     """The plain FP64 workload at full size (A ~ N(0,1) seed 0, v = 256,
-    L = 8, lookahead as the bench runs it): every panel's pivots bit for bit
+    L = 8 with leaves of at least 4096 rows, lookahead, as the bench runs
+    it): every panel's pivots bit for bit
     against the oracle's whole factorisation (stored by
     tests/golden/make_c2_golden.py) up to the first panel whose oracle margin
     is <= 1e-10, and ||P A - L U||_F / ||A||_F <= 1e-12 computed on the GPU
@@ -363,7 +364,8 @@ def test_getrf_full_size_against_stored_oracle(cfx, n):
     A0 = to_dev(A)
     del A
     dA = A0.clone()
-    ipiv, info = cfx.getrf(dA, v=v, leaves=L, lookahead=1)
+    R = int(gold["min_leaf_rows"]) if "min_leaf_rows" in gold else 0
+    ipiv, info = cfx.getrf(dA, v=v, leaves=L, lookahead=1, min_leaf_rows=R)
     torch.cuda.synchronize()
     piv = ipiv.cpu().numpy()
     assert int(info.cpu()[0]) == int(gold["info"]) == 0
@@ -402,3 +404,30 @@ def test_fused_tournament_nodes_bitwise_equal(cfx, n, v, L, la):
     assert np.array_equal(out[0][0], out[1][0])
     ref = O.getrf(A, v, L)
     assert compare_panels(out[0][1][:n], ref.ipiv, ref.margins, v) == len(ref.margins)
+
+
+@pytest.mark.parametrize("n,v,L,R,la", [(2048, 128, 8, 512, 1), (1500, 100, 5, 300, 0), (3000, 256, 8, 1024, 1),
+                                        (777, 64, 4, 200, 1)])
+def test_min_leaf_rows_matches_oracle(cfx, n, v, L, R, la):
+    """Leaves of at least R rows (min(L, max(1, ceil(r / R))) leaves for a
+    panel of r rows): pivots bit for bit against the oracle with the same
+    rule panel by panel (margin rule), factors within rounding, residual
+    <= 1e-12; the masked factorisation gives the same factors through its
+    row map."""
+    say(f"min leaf rows n={n} v={v} L={L} R={R} la={la}")
+    A = G.normal_matrix(n, 1300 + n)
+    ref = O.getrf(A, v, L, min_leaf_rows=R)
+    dA = to_dev(A)
+    ipiv, info = cfx.getrf(dA, v=v, leaves=L, lookahead=la, min_leaf_rows=R)
+    torch.cuda.synchronize()
+    LU, piv = dA.cpu().numpy(), ipiv.cpu().numpy()[:n]
+    assert int(info.cpu()[0]) == ref.info == 0
+    npan = compare_panels(piv, ref.ipiv, ref.margins, v)
+    assert npan == len(ref.margins)
+    np.testing.assert_allclose(LU, ref.LU, rtol=0, atol=lu_tolerance(ref.LU, n))
+    assert O.lu_residual(A, LU, piv) <= 1e-12
+    dM = to_dev(A)
+    ipm, rowmap, infom = cfx.getrf_masked(dM, v=v, leaves=L, lookahead=la, min_leaf_rows=R)
+    torch.cuda.synchronize()
+    assert np.array_equal(ipm.cpu().numpy()[:n], piv)
+    assert np.array_equal(dM.cpu().numpy()[rowmap.cpu().numpy()[:n]], LU)

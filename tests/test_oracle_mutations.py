@@ -30,6 +30,8 @@ MUTATIONS = {
     "ipiv_relative_index": ("ipiv[k + j] = (int32_t)(k + r);", "ipiv[k + j] = (int32_t)(r);"),
     "gepp_no_elimination": ("blk[i * vb + c] -= l * blk[j * vb + c];", "(void)l;"),
     "eta_no_compensation": ("c += te + pe;", "(void)te; (void)pe;"),
+    "min_leaf_count_floor": ("Lk = (n - k + min_leaf - 1) / min_leaf;", "Lk = (n - k) / min_leaf;"),
+    "min_leaf_ignored": ("if (min_leaf > 0) {", "if (min_leaf < 0) {"),
     "eta_ignores_non_finite": ("if (bad) return NAN;", "(void)bad;"),
     "merge_uses_partial_values": ("gather_rows(W, ldw, row0, gid, cl + cr, vb, blk);",
                                   "gather_rows(W, ldw, row0, gid, cl + cr, vb, blk); "

@@ -503,3 +503,45 @@ def test_householder_generator_condition(cond):
     sign, logdet = np.linalg.slogdet(A)
     assert sign == 1.0
     assert logdet == pytest.approx(np.log(spec.s).sum(), rel=1e-8, abs=1e-8)
+
+
+# ---------------------------------------------------------------------------
+# Minimum leaf height: the leaf count follows the panel's height
+# ---------------------------------------------------------------------------
+
+def test_min_leaf_rows_extremes():
+    """R >= n gives one leaf per panel: TP(v, 1), i.e. the same factors as
+    L = 1; R = 1 gives min(L, rows) = L leaves: the fixed-L factors."""
+    A = G.normal_matrix(200, 71)
+    one = O.getrf(A, 16, 1)
+    r_big = O.getrf(A, 16, 8, min_leaf_rows=500)
+    assert np.array_equal(r_big.ipiv, one.ipiv) and np.array_equal(r_big.LU, one.LU)
+    fixed = O.getrf(A, 16, 8)
+    r_one = O.getrf(A, 16, 8, min_leaf_rows=1)
+    assert np.array_equal(r_one.ipiv, fixed.ipiv) and np.array_equal(r_one.LU, fixed.LU)
+    with pytest.raises(ValueError):
+        O.getrf(A, 16, 8, min_leaf_rows=-1)
+
+
+def test_min_leaf_rows_per_panel_leaf_count():
+    """n = 480, v = 32, L = 4, R = 128: panel j (r = 480 - 32 j rows) has
+    min(4, ceil(r / 128)) leaves -- 4, 4, 4, 3, 3, 3, 3, 2, 2, 2, 2, 1, ...
+    Each panel step of the full factorisation equals one panel of a
+    fixed-leaf factorisation of the trailing matrix left by the previous
+    panels, with that leaf count (pivots and values bit for bit)."""
+    n, v, L, R = 480, 32, 4, 128
+    expect = [4, 4, 4, 3, 3, 3, 3, 2, 2, 2, 2, 1, 1, 1, 1]
+    A = G.normal_matrix(n, 72)
+    for j, lj in enumerate(expect):
+        k = j * v
+        before = O.getrf(A, v, L, npanels=j, min_leaf_rows=R) if j else None
+        T = (before.LU if j else A)[k:, k:].copy()
+        step = O.getrf(T, v, lj, npanels=1)
+        full = O.getrf(A, v, L, npanels=j + 1, min_leaf_rows=R)
+        assert np.array_equal(full.ipiv[k:k + v] - k, step.ipiv[:v]), j
+        assert np.array_equal(full.LU[k:, k:], step.LU), j
+        # a different leaf count gives different pivots on this matrix for
+        # the panels where the rule decides (the pin would catch a wrong count)
+        if lj > 1:
+            other = O.getrf(T, v, lj - 1, npanels=1)
+            assert not np.array_equal(other.ipiv[:v], step.ipiv[:v]) or not np.array_equal(other.LU, step.LU)
