@@ -13,17 +13,22 @@
 // about 460 registers per lane, so one workgroup is resident per compute
 // unit and the persistent grid is one workgroup per compute unit.
 //   panel    thread t owns rows t and t + 256; the panel's vb columns of
-//            those rows live in registers.  Each pivot step is a wavefront
-//            argmax (ties to the smaller row) combined across the 4
+//            those rows live in registers (a window rotating by one column
+//            per step).  Each pivot step is a wavefront argmax on integer
+//            keys (DPP; ties to the smaller row) combined across the 4
 //            wavefronts in LDS; rows move between owners through LDS.
 //   swaps    the panel's interchanges, composed into (destination, source)
-//            pairs, applied to the columns outside the panel.
+//            pairs, applied to the columns outside the panel (8 loads in
+//            flight per thread before the values are staged in LDS).
 //   U12      L11^{-1} A12, one column per thread, L11 in LDS.
 //   Schur    A22 -= L21 U12 on the FP64 matrix cores (16x16x4 blocks,
-//            32x32 per wavefront per pass), operands from L2.
+//            32x32 per wavefront per pass): U12 staged once in LDS, each
+//            wavefront walks tile rows with the row's L21 block in
+//            registers and the next C block requested ahead.
 //   solve    B gathered by the row permutation into LDS, forward and back
 //            substitution in 32-row blocks (off-diagonal parts as dot
-//            products, diagonal blocks by lane broadcast), written back.
+//            products with 16 factor values requested at once, diagonal
+//            blocks by lane broadcast), written back.
 // The panel width v per size class comes from the handle's tuning table.
 #include <climits>
 #include <utility>
@@ -60,10 +65,12 @@ __device__ __forceinline__ double bcast(double x, int l)
 }
 
 struct Smem {
-    double X[kMaxN * kMaxRhs];        // solve: permuted right-hand sides
+    // solve: permuted right-hand sides (stride kMaxRhs); factorisation:
+    // staging of the interchanged rows, then of the panel's U12 rows
+    double X[kMaxN * kMaxVB];
     double L11[kMaxVB * (kMaxVB + 1)];
     double rowP[kMaxVB], rowC[kMaxVB];
-    double redv[4];
+    unsigned long long redk[4];
     int redr[4];
     int perm[kMaxN];                  // position -> original row
     int iperm[kMaxN];                 // original row -> position before the panel
@@ -74,55 +81,106 @@ struct Smem {
     int ticket;
 };
 
-// The workgroup-wide pivot of column j of the panel: the largest |value|
-// among rows >= col, ties to the smaller row; rows whose values are all
-// NaN leave p = col.
-__device__ __forceinline__ int wg_argmax(double bv, int br, Smem &s)
+// The pivot order as an unsigned key: |a|'s bits + 1 (non-negative
+// doubles order as their bit patterns), 0 for NaN and for rows that are not
+// candidates, so a NaN never wins.
+__device__ __forceinline__ unsigned long long piv_key(double a)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(a) & 0x7FFFFFFFFFFFFFFFull;
+    return b > 0x7FF0000000000000ull ? 0ull : b + 1ull;
+}
+
+// Largest / smallest 32-bit value over the wavefront, uniform across lanes:
+// a DPP butterfly inside each row of 16 lanes (xor 1, xor 2, half-mirror,
+// mirror), then row broadcasts (lane 15 into rows 1 and 3, lane 31 into
+// rows 2 and 3) leave the result in lane 63.
+__device__ __forceinline__ unsigned wave_max_u32(unsigned a)
+{
+    a = max(a, (unsigned)__builtin_amdgcn_update_dpp(0, (int)a, 0xB1, 0xF, 0xF, false));
+    a = max(a, (unsigned)__builtin_amdgcn_update_dpp(0, (int)a, 0x4E, 0xF, 0xF, false));
+    a = max(a, (unsigned)__builtin_amdgcn_update_dpp(0, (int)a, 0x141, 0xF, 0xF, false));
+    a = max(a, (unsigned)__builtin_amdgcn_update_dpp(0, (int)a, 0x140, 0xF, 0xF, false));
+    a = max(a, (unsigned)__builtin_amdgcn_update_dpp(0, (int)a, 0x142, 0xA, 0xF, false));
+    a = max(a, (unsigned)__builtin_amdgcn_update_dpp(0, (int)a, 0x143, 0xC, 0xF, false));
+    return (unsigned)__builtin_amdgcn_readlane((int)a, 63);
+}
+__device__ __forceinline__ int wave_min_i32(int a)
+{
+    const int big = INT_MAX;
+    a = min(a, __builtin_amdgcn_update_dpp(big, a, 0xB1, 0xF, 0xF, false));
+    a = min(a, __builtin_amdgcn_update_dpp(big, a, 0x4E, 0xF, 0xF, false));
+    a = min(a, __builtin_amdgcn_update_dpp(big, a, 0x141, 0xF, 0xF, false));
+    a = min(a, __builtin_amdgcn_update_dpp(big, a, 0x140, 0xF, 0xF, false));
+    a = min(a, __builtin_amdgcn_update_dpp(big, a, 0x142, 0xA, 0xF, false));
+    a = min(a, __builtin_amdgcn_update_dpp(big, a, 0x143, 0xC, 0xF, false));
+    return __builtin_amdgcn_readlane(a, 63);
+}
+
+// The workgroup-wide pivot of column j of the panel: the largest key (the
+// largest |value|), ties to the smaller row; INT_MAX when no row is a
+// candidate or every candidate is NaN.  The wave's largest key (high
+// words first, the low words only among lanes holding the largest high
+// word), the lane holding it found by a ballot (a minimum over rows only
+// when several lanes tie), then the 4 wavefronts' winners through LDS.
+__device__ __forceinline__ int wg_argmax(unsigned long long key, int row, Smem &s)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int off = 32; off >= 1; off >>= 1) {
-        const double ov = __shfl_xor(bv, off);
-        const int orow = __shfl_xor(br, off);
-        if (ov > bv || (ov == bv && orow < br)) {
-            bv = ov;
-            br = orow;
-        }
-    }
+    const unsigned hi = (unsigned)(key >> 32), lo = (unsigned)key;
+    const unsigned mh = wave_max_u32(hi);
+    const unsigned ml = wave_max_u32(hi == mh ? lo : 0u);
+    const unsigned long long km = ((unsigned long long)mh << 32) | ml;
+    const int cand = (key == km && km != 0ull) ? row : INT_MAX;
+    const unsigned long long hits = __ballot(cand != INT_MAX);
+    const int wr = hits == 0ull ? INT_MAX
+                   : __popcll(hits) == 1 ? __builtin_amdgcn_readlane(cand, __ffsll((long long)hits) - 1)
+                                         : wave_min_i32(cand);
     if (lane == 0) {
-        s.redv[wave] = bv;
-        s.redr[wave] = br;
+        s.redk[wave] = km;
+        s.redr[wave] = wr;
     }
     __syncthreads();
-    bv = s.redv[0];
-    br = s.redr[0];
+    unsigned long long bk = s.redk[0];
+    int br = s.redr[0];
 #pragma unroll
     for (int w = 1; w < 4; ++w) {
-        const double ov = s.redv[w];
+        const unsigned long long ok = s.redk[w];
         const int orow = s.redr[w];
-        if (ov > bv || (ov == bv && orow < br)) {
-            bv = ov;
+        if (ok > bk || (ok == bk && orow < br)) {
+            bk = ok;
             br = orow;
         }
     }
-    return br;
+    return bk == 0ull ? INT_MAX : br;
 }
 
 // One 32x32 block of A22 -= L21 U12 per wavefront pass, K = vb (zero
 // padded to a multiple of 4).  f64 16x16x4 MFMA: A lane l = (row l%16,
 // k l/16), B lane l = (k l/16, col l%16), D lane l element q = (row
 // l/16 + 4q, col l%16).
-__device__ __forceinline__ void schur_tiles(double *A, int64_t lda, int n, int k, int vb)
+template <int VB>
+__device__ __forceinline__ void schur_tiles(double *A, int64_t lda, int n, int k, Smem &s)
 {
-    const int m = n - k - vb;
+    constexpr int KS = (VB + 3) / 4;     // k steps of 4
+    const int m = n - k - VB;
     if (m <= 0) return;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6;
     const int lr = lane & 15, lk = lane >> 4;
     const int tiles = (m + 31) / 32;
-    const int r0 = k + vb;
-    for (int tix = wave; tix < tiles * tiles; tix += 4) {
-        const int ti = tix / tiles, tj = tix - ti * tiles;
-        const int i0 = r0 + ti * 32, j0 = r0 + tj * 32;
-        d4 acc[2][2];
+    const int r0 = k + VB;
+    // the panel's U12 rows (VB x m) staged once in LDS, zero beyond m and
+    // VB; every tile then reads its U operand from there
+    const int ldu = tiles * 32 + 4;
+    double *Us = s.X;
+    for (int e = t; e < 4 * KS * ldu; e += NT) {
+        const int kk = e / ldu, j = e - kk * ldu;
+        Us[e] = (kk < VB && j < m) ? A[(int64_t)(k + kk) * lda + r0 + j] : 0.0;
+    }
+    __syncthreads();
+    // each wavefront walks whole tile rows: the tile row's L21 block is
+    // loaded once into registers; the next tile's C block is requested
+    // while the current one is on the matrix cores
+    auto load_c = [&](int i0, int j0, d4 (&acc)[2][2]) {
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -132,34 +190,52 @@ __device__ __forceinline__ void schur_tiles(double *A, int64_t lda, int n, int k
                     const int gi = i0 + a * 16 + lk + 4 * q, gj = j0 + b * 16 + lr;
                     acc[a][b][q] = (gi < n && gj < n) ? A[(int64_t)gi * lda + gj] : 0.0;
                 }
-        for (int kk = 0; kk < vb; kk += 4) {
-            const int kc = kk + lk;
-            double af[2], bf[2];
+    };
+    for (int ti = wave; ti < tiles; ti += 4) {
+        const int i0 = r0 + ti * 32;
+        double af[KS][2];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const int kc = 4 * ks + lk;
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
                 const int gi = i0 + a * 16 + lr;
-                af[a] = (gi < n && kc < vb) ? -A[(int64_t)gi * lda + k + kc] : 0.0;
+                af[ks][a] = (gi < n && kc < VB) ? -A[(int64_t)gi * lda + k + kc] : 0.0;
             }
+        }
+        d4 acc[2][2];
+        load_c(i0, r0, acc);
+        for (int tj = 0; tj < tiles; ++tj) {
+            const int j0 = r0 + tj * 32;
+            d4 nxt[2][2];
+            const bool more = tj + 1 < tiles;
+            if (more) load_c(i0, j0 + 32, nxt);
 #pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                const int gj = j0 + b * 16 + lr;
-                bf[b] = (gj < n && kc < vb) ? A[(int64_t)(k + kc) * lda + gj] : 0.0;
+            for (int ks = 0; ks < KS; ++ks) {
+                double bf[2];
+#pragma unroll
+                for (int b = 0; b < 2; ++b) bf[b] = Us[(4 * ks + lk) * ldu + tj * 32 + b * 16 + lr];
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[ks][a], bf[b], acc[a][b], 0, 0, 0);
             }
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
                 for (int b = 0; b < 2; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int gi = i0 + a * 16 + lk + 4 * q, gj = j0 + b * 16 + lr;
+                        if (gi < n && gj < n) A[(int64_t)gi * lda + gj] = acc[a][b][q];
+                    }
+            if (!more) break;
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) acc[a][b] = nxt[a][b];
         }
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int gi = i0 + a * 16 + lk + 4 * q, gj = j0 + b * 16 + lr;
-                    if (gi < n && gj < n) A[(int64_t)gi * lda + gj] = acc[a][b][q];
-                }
     }
 }
 
@@ -183,25 +259,29 @@ __device__ __forceinline__ void panel(double *A, int64_t lda, int n, int k, int3
             P[q][c] = row[c];
         });
     }
-    static_for<W>([&](auto J) {
-        constexpr int j = decltype(J)::value;
+    // The pivot steps run as a loop (one copy of its body: the kernel's code
+    // must stay small enough for the instruction cache), on a register
+    // window that rotates left by one column per step: at step j, P[q][0]
+    // holds column j, P[q][c] column j + c for c < W - j, and the finished
+    // columns sit at the end; after W steps the window is back in order.
+#pragma unroll 1
+    for (int j = 0; j < W; ++j) {
         const int col = k + j;
-        double bv = -1.0;
+        unsigned long long bk = 0ull;
         int br = INT_MAX;
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int r = t + NT * q;
-            if (r >= col && r < n) {
-                const double a = fabs(P[q][j]);
-                if (a > bv || (a == bv && r < br)) {
-                    bv = a;
-                    br = r;
-                }
+            const unsigned long long kq = (r >= col && r < n) ? piv_key(P[q][0]) : 0ull;
+            if (kq > bk) {          // rows in increasing order: a tie keeps the smaller row
+                bk = kq;
+                br = r;
             }
         }
-        int p = wg_argmax(bv, br, s);
+        int p = wg_argmax(bk, br, s);
         if (p == INT_MAX) p = col;
-        // exchange rows col and p between their owners
+        // exchange rows col and p between their owners (whole rows, in the
+        // window's order, which every thread shares)
         if (t == (p & (NT - 1))) {
             const int q = p >> 8;
             static_for<W>([&](auto C) {
@@ -236,25 +316,35 @@ __device__ __forceinline__ void panel(double *A, int64_t lda, int n, int k, int3
             s.perm[col] = s.perm[p];
             s.perm[p] = a;
         }
-        const double piv = s.rowP[j];
+        const double piv = s.rowP[0];
         if (piv != 0.0) {
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
                 const int r = t + NT * q;
                 if (r > col && r < n) {
-                    const double l = P[q][j] / piv;
-                    P[q][j] = l;
+                    const double l = P[q][0] / piv;
+                    P[q][0] = l;
                     static_for<W>([&](auto C) {
                         constexpr int c = decltype(C)::value;
-                        if constexpr (c > j) P[q][c] -= l * s.rowP[c];
+                        if constexpr (c > 0)
+                            if (c < W - j) P[q][c] -= l * s.rowP[c];
                     });
                 }
             }
         } else if (t == 0 && s.info == 0) {
             s.info = col + 1;
         }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const double f = P[q][0];
+            static_for<W - 1>([&](auto C) {
+                constexpr int c = decltype(C)::value;
+                P[q][c] = P[q][c + 1];
+            });
+            P[q][W - 1] = f;
+        }
         __syncthreads();
-    });
+    }
     // ---- write the panel back
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
@@ -296,12 +386,26 @@ __device__ __forceinline__ void panel(double *A, int64_t lda, int n, int k, int3
         // all sources of a column are read (staged in LDS) before any
         // destination is written; columns in chunks that fit the stage
         const int nt = s.ntouch;
-        const int cw = (kMaxN * kMaxRhs) / nt;
+        const int cw = (kMaxN * kMaxVB) / nt;
         for (int c0 = 0; c0 < n; c0 += cw) {
             const int cn = n - c0 < cw ? n - c0 : cw;
-            for (int e = t; e < nt * cn; e += NT) {
-                const int i = e / cn, cc = e - i * cn;
-                s.X[e] = A[(int64_t)s.tsrc[i] * lda + c0 + cc];
+            const int tot = nt * cn;
+            // 8 loads in flight per thread before their values are staged
+            for (int e0 = t; e0 < tot; e0 += 8 * NT) {
+                double val[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int e = e0 + u * NT;
+                    if (e < tot) {
+                        const int i = e / cn, cc = e - i * cn;
+                        val[u] = A[(int64_t)s.tsrc[i] * lda + c0 + cc];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int e = e0 + u * NT;
+                    if (e < tot) s.X[e] = val[u];
+                }
             }
             __syncthreads();
             for (int e = t; e < nt * cn; e += NT) {
@@ -342,7 +446,7 @@ __device__ __forceinline__ void panel(double *A, int64_t lda, int n, int k, int3
         });
     }
     __syncthreads();
-    schur_tiles(A, lda, n, k, W);
+    schur_tiles<W>(A, lda, n, k, s);
     __syncthreads();
 }
 
@@ -356,6 +460,29 @@ __device__ __forceinline__ void factor(double *A, int64_t lda, int n, int32_t *i
     if constexpr (VB > 8)
         for (; k + 8 <= n; k += 8) panel<8>(A, lda, n, k, ipiv, s);
     for (; k < n; ++k) panel<1>(A, lda, n, k, ipiv, s);
+}
+
+// sum_{j0 <= j < j1} row[j] X[j][c]: 16 factor values requested at once
+// (each round one memory latency instead of one per element), four
+// partial sums.
+__device__ __forceinline__ double dot_rows(const double *row, int j0, int j1, const double *X, int c)
+{
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int j = j0;
+    for (; j + 16 <= j1; j += 16) {
+        double r[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) r[u] = row[j + u];
+#pragma unroll
+        for (int u = 0; u < 16; u += 4) {
+            s0 += r[u] * X[(j + u) * kMaxRhs + c];
+            s1 += r[u + 1] * X[(j + u + 1) * kMaxRhs + c];
+            s2 += r[u + 2] * X[(j + u + 2) * kMaxRhs + c];
+            s3 += r[u + 3] * X[(j + u + 3) * kMaxRhs + c];
+        }
+    }
+    for (; j < j1; ++j) s0 += row[j] * X[j * kMaxRhs + c];
+    return (s0 + s1) + (s2 + s3);
 }
 
 // X (LDS, stride kMaxRhs) <- U^{-1} L^{-1} X with the factors in A.  The
@@ -372,14 +499,7 @@ __device__ __forceinline__ void solve(const double *A, int64_t lda, int n, int n
         for (int e = t; e < bs * nrhs; e += NT) {
             const int i = I0 + e / nrhs, c = e % nrhs;
             const double *row = A + (int64_t)i * lda;
-            double s0 = 0.0, s1 = 0.0;
-            int j = 0;
-            for (; j + 1 < I0; j += 2) {
-                s0 += row[j] * s.X[j * kMaxRhs + c];
-                s1 += row[j + 1] * s.X[(j + 1) * kMaxRhs + c];
-            }
-            if (j < I0) s0 += row[j] * s.X[j * kMaxRhs + c];
-            s.X[i * kMaxRhs + c] -= s0 + s1;
+            s.X[i * kMaxRhs + c] -= dot_rows(row, 0, I0, s.X, c);
         }
         // strictly lower part of the diagonal block, zero elsewhere
         for (int e = t; e < SBK * SBK; e += NT) {
@@ -408,14 +528,7 @@ __device__ __forceinline__ void solve(const double *A, int64_t lda, int n, int n
         for (int e = t; e < bs * nrhs; e += NT) {
             const int i = I0 + e / nrhs, c = e % nrhs;
             const double *row = A + (int64_t)i * lda;
-            double s0 = 0.0, s1 = 0.0;
-            int j = j1;
-            for (; j + 1 < n; j += 2) {
-                s0 += row[j] * s.X[j * kMaxRhs + c];
-                s1 += row[j + 1] * s.X[(j + 1) * kMaxRhs + c];
-            }
-            if (j < n) s0 += row[j] * s.X[j * kMaxRhs + c];
-            s.X[i * kMaxRhs + c] -= s0 + s1;
+            s.X[i * kMaxRhs + c] -= dot_rows(row, j1, n, s.X, c);
         }
         // strictly upper part (zero elsewhere) and the diagonal (1 outside)
         for (int e = t; e < SBK * SBK; e += NT) {
