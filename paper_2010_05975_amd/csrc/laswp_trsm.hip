@@ -225,16 +225,28 @@ __device__ __forceinline__ void trsm_body(double *A, int64_t lda, const int32_t 
 #pragma unroll
                 for (int j = 0; j < TSB; ++j) x[j] = Sb[wave][lane][j] - Sg[wave][lane][j];
                 // substitution against the diagonal triangle, column by
-                // column (x_c -= x_j U[j][c] in increasing j for every c)
+                // column (x_c -= x_j U[j][c] in increasing j for every c);
+                // row j + 1 of the triangle is requested from LDS while row
+                // j is applied, so the updates do not wait on LDS one by one
+                double u[TSB];
+#pragma unroll
+                for (int c = 0; c < TSB; ++c) u[c] = Us[c0 * ULD + c];
 #pragma unroll
                 for (int j = 0; j < TSB; ++j) {
                     if (j < bc) {
+                        double un[TSB];
+                        if (j + 1 < bc) {
+#pragma unroll
+                            for (int c = j + 1; c < TSB; ++c) un[c] = Us[(c0 + j + 1) * ULD + c];
+                        }
                         if constexpr (MODE == 0) {
-                            const double d = Us[(c0 + j) * ULD + j];
+                            const double d = u[j];
                             x[j] = d != 0.0 ? x[j] / d : x[j];
                         }
 #pragma unroll
-                        for (int c = j + 1; c < TSB; ++c) x[c] -= x[j] * Us[(c0 + j) * ULD + c];
+                        for (int c = j + 1; c < TSB; ++c) x[c] -= x[j] * u[c];
+#pragma unroll
+                        for (int c = j + 1; c < TSB; ++c) u[c] = un[c];
                     }
                 }
 #pragma unroll
