@@ -252,7 +252,7 @@ int cfx_create(cfx_handle **h)
         hipEventCreateWithFlags(&p->ev_panel, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&p->ev_tslu, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&p->ev_upd, hipEventDisableTiming) != hipSuccess) {
-        delete p;
+        cfx_destroy(p);
         return CFX_EHIP;
     }
     if (hipEventCreateWithFlags(&p->ev_getrs, hipEventDisableTiming) != hipSuccess ||
@@ -585,8 +585,11 @@ static int getrf_run(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *
         if (m > 0) {
             const int vbn = (int)(m < v ? m : v);          // next panel width
             // FP64: L21 and the next panel's columns of U12 first (one
-            // launch), the rest of U12 after the next tournament has been
-            // started; the low-precision pack needs all of U12 at once
+            // launch), the rest of U12 with the rest of the update; the
+            // low-precision pack needs all of U12 at once.  (The rest of U12
+            // needs only the interchanges, but launched beside the first
+            // solve it holds that solve back: neither grid fits the device
+            // at once, and the first waits for the second to drain.)
             const int64_t n1 = prec == CFX_PREC_FP64 ? vbn : m;
             e = pf.begin(st);
             if ((rc = launch_trsm_first(A, lda, k, vb, m, n1, st, rm))) return rc;
@@ -596,31 +599,42 @@ static int getrf_run(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *
             if ((rc = pack(b, m, vb, st))) return rc;
             if ((rc = schur(b, m, 0, vbn, vb, 0, st))) return rc;
             pf.end(PH_SCHUR, e, st, 2.0 * (double)m * vbn * vb);
-            // next panel's tournament on the side stream, the rest of the
-            // update on the CU-masked stream when there is one
+            // the rest of the update on the CU-masked stream when there is
+            // one, then the next panel's tournament on the side stream.  The
+            // rest is queued first: the tournament is a long run of small
+            // launches, and a host that is held back by the depth of the
+            // side stream's queue would otherwise reach the update only
+            // after most of the tournament had been dispatched
             hipStream_t ts = side, us = (h->upd && !h->one_stream) ? h->upd : st;
             CFX_HIP(hipEventRecord(h->ev_panel, st));
-            CFX_HIP(hipStreamWaitEvent(ts, h->ev_panel, 0));
+            if (ts != st) CFX_HIP(hipStreamWaitEvent(ts, h->ev_panel, 0));
             if (us != st) CFX_HIP(hipStreamWaitEvent(us, h->ev_panel, 0));
             const int64_t kn = k + vb;
-            e = pf.begin(ts);
-            if ((rc = launch_tslu(panel_w(kn), lda, kn, n - kn, vbn, panel_leaves(L, ml, n - kn), ws, nullptr,
-                                  ipiv, info, ts, rm,
-                                  h->fuse_rows)))
-                return rc;
-            pf.end(PH_TSLU, e, ts);
-            CFX_HIP(hipEventRecord(h->ev_tslu, ts));
-            tslu_on_side = true;
+            auto tournament = [&]() -> int {
+                hipEvent_t et = pf.begin(ts);
+                const int r = launch_tslu(panel_w(kn), lda, kn, n - kn, vbn, panel_leaves(L, ml, n - kn), ws,
+                                          nullptr, ipiv, info, ts, rm, h->fuse_rows);
+                if (r) return r;
+                pf.end(PH_TSLU, et, ts);
+                CFX_HIP(hipEventRecord(h->ev_tslu, ts));
+                tslu_on_side = true;
+                return CFX_OK;
+            };
+            // on one stream the tournament goes first: it is the next
+            // panel's critical path and the rest only has to end before the
+            // next interchanges
+            if (us == ts && (rc = tournament())) return rc;
             if (n1 < m) {
                 e = pf.begin(us);
                 if ((rc = launch_trsm_rest(A, lda, k, vb, m, n1, us, rm))) return rc;
                 pf.end(PH_TRSM, e, us);
             }
-            // the rest of the update, in column chunks: between two chunks
-            // the dispatcher can start the tournament's launches queued on
-            // the side stream instead of leaving them behind one huge grid
-            // (one event pair around all chunks: events between the
-            // launches would cost the step about 2 %)
+            // the rest of the update, in column chunks when the update shares
+            // the device with the tournament without reserved compute units:
+            // between two chunks the dispatcher can start the tournament's
+            // launches instead of leaving them behind one huge grid (one
+            // event pair around all chunks: events between the launches
+            // would cost the step about 2 %)
             const int64_t chunk = h->la_chunk > 0 ? h->la_chunk : (us != st ? m : kLaChunk);
             const int wgs = h->schur_wgs >= 0 ? h->schur_wgs : (prec == CFX_PREC_FP64 ? 0 : cfx::kLpSchurWgs);
             if (vbn < m) {
@@ -636,6 +650,7 @@ static int getrf_run(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *
                 CFX_HIP(hipEventRecord(h->ev_upd, us));
                 upd_pending = true;
             }
+            if (us != ts && (rc = tournament())) return rc;
         }
         if (pf.on) ++pf.panels;
     }
