@@ -21,9 +21,10 @@
 // kept in registers in the matrix cores' operand layout, and sweeps
 // 32-column blocks left to right.  Per block the workgroup stages the U
 // columns of the block once in LDS; each wavefront applies its finished
-// blocks on the FP64 matrix cores (X_b -= X_{<b} U_{<b,b}), then 16 lanes
-// solve their rows against the 32 x 32 diagonal triangle by substitution
-// with true division (a zero diagonal leaves that column unscaled).
+// blocks on the FP64 matrix cores (X_b -= X_{<b} U_{<b,b}), then solves its
+// 16 rows against the 32 x 32 diagonal triangle by substitution, four lanes
+// per row, with true division (a zero diagonal leaves that column
+// unscaled).
 #include <utility>
 
 #include "cfx_internal.h"
@@ -120,6 +121,16 @@ template <int N, typename F>
 __device__ __forceinline__ void sfor(F &&f)
 {
     sfor_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// Lane q of every group of four lanes (DPP quad permutation), 64 bits.
+template <int Q>
+__device__ __forceinline__ double quad_bcast(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, Q * 0x55, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), Q * 0x55, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
 // U(r, c) of the solve: U00 for L21 (mode 0), L00^T for U12 (mode 1), from
@@ -220,37 +231,48 @@ __device__ __forceinline__ void trsm_body(double *A, int64_t lda, const int32_t 
                 Sg[wave][lk + 4 * q][16 + lr] = g1[q];
             }
             __syncthreads();
-            if (lane < TSW) {
-                double x[TSB];
+            {
+                // substitution against the diagonal triangle by all 64 lanes:
+                // lanes 4r .. 4r+3 hold row r of the wave's 16, eight columns
+                // each (lane group sg: columns 8 sg .. 8 sg + 7).  Step j: the
+                // lane holding column j finishes x_j (mode 0: divides it by
+                // U[j][j]), a quad broadcast hands x_j to the row's other
+                // lanes, and each lane applies x_c -= x_j U[j][c] to its
+                // columns c > j; row j + 1 of the triangle is requested from
+                // LDS meanwhile.  Per element: the same operations in the
+                // same order (increasing j) as a row-by-row substitution.
+                const int sr = lane >> 2, sg = lane & 3;
+                double x[8], u[8];
 #pragma unroll
-                for (int j = 0; j < TSB; ++j) x[j] = Sb[wave][lane][j] - Sg[wave][lane][j];
-                // substitution against the diagonal triangle, column by
-                // column (x_c -= x_j U[j][c] in increasing j for every c);
-                // row j + 1 of the triangle is requested from LDS while row
-                // j is applied, so the updates do not wait on LDS one by one
-                double u[TSB];
-#pragma unroll
-                for (int c = 0; c < TSB; ++c) u[c] = Us[c0 * ULD + c];
-#pragma unroll
-                for (int j = 0; j < TSB; ++j) {
+                for (int c = 0; c < 8; ++c) {
+                    x[c] = Sb[wave][sr][8 * sg + c] - Sg[wave][sr][8 * sg + c];
+                    u[c] = Us[c0 * ULD + 8 * sg + c];
+                }
+                sfor<TSB>([&](auto JC) {
+                    constexpr int j = decltype(JC)::value;
+                    constexpr int gj = j / 8, cj = j % 8;
                     if (j < bc) {
-                        double un[TSB];
+                        double un[8];
                         if (j + 1 < bc) {
 #pragma unroll
-                            for (int c = j + 1; c < TSB; ++c) un[c] = Us[(c0 + j + 1) * ULD + c];
+                            for (int c = 0; c < 8; ++c) un[c] = Us[(c0 + j + 1) * ULD + 8 * sg + c];
                         }
                         if constexpr (MODE == 0) {
-                            const double d = u[j];
-                            x[j] = d != 0.0 ? x[j] / d : x[j];
+                            if (sg == gj) {
+                                const double d = u[cj];
+                                x[cj] = d != 0.0 ? x[cj] / d : x[cj];
+                            }
                         }
+                        const double xj = quad_bcast<gj>(x[cj]);
 #pragma unroll
-                        for (int c = j + 1; c < TSB; ++c) x[c] -= x[j] * u[c];
+                        for (int c = 0; c < 8; ++c)
+                            if (8 * sg + c > j) x[c] -= xj * u[c];
 #pragma unroll
-                        for (int c = j + 1; c < TSB; ++c) u[c] = un[c];
+                        for (int c = 0; c < 8; ++c) u[c] = un[c];
                     }
-                }
+                });
 #pragma unroll
-                for (int j = 0; j < TSB; ++j) Sb[wave][lane][j] = x[j];
+                for (int c = 0; c < 8; ++c) Sb[wave][sr][8 * sg + c] = x[c];
             }
             __syncthreads();
             sfor<TSB / 4>([&](auto SC) {
