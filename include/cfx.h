@@ -122,6 +122,18 @@ int cfx_overlap_tuning(cfx_handle *h, int32_t *schur_workgroups, int32_t *chunk_
 int cfx_set_overlap_tuning(cfx_handle *h, int32_t schur_workgroups, int32_t chunk_cols,
                            int32_t one_stream);
 
+/* Triangular solves of cfx_getrf with lookahead = 1 (scheduling only: the
+ * same bits).  L21 and the next panel's columns of U12 are solved in one
+ * launch ahead of the next tournament; the rest of U12 is solved with the
+ * rest of the update.  While the trailing matrix has at least `rows` rows
+ * the update, not the next tournament, bounds each step, and all of U12 is
+ * solved in the first launch instead (one launch less before the update).
+ * The low-precision factorisations always solve all of U12 first.
+ *   rows : >= 0; default 16384; 0 = always all of U12 first.
+ * Get: host int32 pointer.  Set returns -2 for a negative value. */
+int cfx_full_trsm_rows(cfx_handle *h, int32_t *rows);
+int cfx_set_full_trsm_rows(cfx_handle *h, int32_t rows);
+
 /* Launch shape of the tournament (scheduling only: the same selection and
  * values bit for bit).  Nodes of at most node_rows rows (every merge node
  * at v <= 256, and the short leaves of late panels, when node_rows = 512)

@@ -126,6 +126,8 @@ def lib():
         L.cfx_getrs_check.argtypes = [vp, vp]
         L.cfx_schur_delay.argtypes = [vp, vp]
         L.cfx_tournament_fusion.argtypes = [vp, vp]
+        L.cfx_full_trsm_rows.argtypes = [vp, vp]
+        L.cfx_set_full_trsm_rows.argtypes = [vp, i32]
         L.cfx_set_tournament_fusion.argtypes = [vp, i32]
         L.cfx_set_schur_delay.argtypes = [vp, i32]
         L.cfx_reserved_cus.argtypes = [vp, vp]
@@ -141,6 +143,7 @@ def lib():
                   "cfx_getrf_masked", "cfx_getrs_masked", "cfx_schur_delay", "cfx_set_schur_delay",
                   "cfx_reserved_cus", "cfx_set_reserved_cus",
                   "cfx_tournament_fusion", "cfx_set_tournament_fusion",
+                  "cfx_full_trsm_rows", "cfx_set_full_trsm_rows",
                   "cfx_getrs_noalloc",
                   "cfx_schur_update_buffer_size", "cfx_schur_update",
                   "cfx_gesv_ir_buffer_size", "cfx_gesv_ir",
@@ -456,6 +459,19 @@ def batched_set_tuning(vb, handle=None):
     h = handle or default_handle()
     t = (C.c_int32 * 5)(*vb)
     _check("cfx_batched_set_tuning", lib().cfx_batched_set_tuning(h.h, t))
+
+
+def full_trsm_rows(handle=None):
+    """cfx_full_trsm_rows: trailing size from which all of U12 is solved first."""
+    h = handle or default_handle()
+    r = C.c_int32()
+    _check("cfx_full_trsm_rows", lib().cfx_full_trsm_rows(h.h, C.byref(r)))
+    return r.value
+
+
+def set_full_trsm_rows(rows, handle=None):
+    h = handle or default_handle()
+    _check("cfx_set_full_trsm_rows", lib().cfx_set_full_trsm_rows(h.h, int(rows)))
 
 
 def tournament_fusion(handle=None):

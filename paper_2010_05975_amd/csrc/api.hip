@@ -51,6 +51,7 @@ namespace cfx {
 constexpr int kLpSchurWgs = 384;
 constexpr int64_t kLaChunk = 512;    // columns per overlapped launch without reserved compute units
 constexpr int kReserveCus = 32;      // compute units kept free for the tournament by default
+constexpr int64_t kFullTrsmRows = 16384;   // trailing size from which all of U12 is solved up front
 }  // namespace cfx
 
 struct cfx_handle {
@@ -64,6 +65,7 @@ struct cfx_handle {
     // workgroups to drain (null: the caller's stream)
     hipStream_t upd = nullptr;
     hipEvent_t ev_upd = nullptr;    // the rest of the last update done
+    int64_t full_trsm_rows = cfx::kFullTrsmRows;   // all of U12 up front from this trailing size
     int reserve_cus = 0;
 
     void *scratch = nullptr;        // getrs permutation + gather buffer
@@ -589,8 +591,12 @@ static int getrf_run(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *
             // low-precision pack needs all of U12 at once.  (The rest of U12
             // needs only the interchanges, but launched beside the first
             // solve it holds that solve back: neither grid fits the device
-            // at once, and the first waits for the second to drain.)
-            const int64_t n1 = prec == CFX_PREC_FP64 ? vbn : m;
+            // at once, and the first waits for the second to drain.)  While
+            // the trailing matrix is large the update, not the next
+            // tournament, bounds the step: then all of U12 is solved in the
+            // first launch, which starts the update about one solve earlier
+            // and the tournament a fraction of one later.
+            const int64_t n1 = (prec == CFX_PREC_FP64 && m < h->full_trsm_rows) ? vbn : m;
             e = pf.begin(st);
             if ((rc = launch_trsm_first(A, lda, k, vb, m, n1, st, rm))) return rc;
             pf.end(PH_TRSM, e, st);
@@ -962,6 +968,22 @@ int cfx_set_overlap_tuning(cfx_handle *h, int32_t schur_workgroups, int32_t chun
     h->schur_wgs = schur_workgroups;
     h->la_chunk = chunk_cols;
     h->one_stream = one_stream != 0;
+    return CFX_OK;
+}
+
+int cfx_full_trsm_rows(cfx_handle *h, int32_t *rows)
+{
+    if (!h) return -1;
+    if (!rows) return -2;
+    *rows = (int32_t)h->full_trsm_rows;
+    return CFX_OK;
+}
+
+int cfx_set_full_trsm_rows(cfx_handle *h, int32_t rows)
+{
+    if (!h) return -1;
+    if (rows < 0) return -2;
+    h->full_trsm_rows = rows;
     return CFX_OK;
 }
 

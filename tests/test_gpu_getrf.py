@@ -267,6 +267,40 @@ def test_reserved_cus_bitwise_equal(cfx, prec):
         assert np.array_equal(LU, ref[0]), (cus, chunk, masked)
 
 
+@pytest.mark.parametrize("masked", [False, True])
+def test_full_trsm_rows_bitwise_equal(cfx, masked):
+    """All of U12 solved in the first launch (threshold 0) or split between
+    the first launch and the rest of the update (threshold above the matrix)
+    is scheduling only: the same pivots and factors bit for bit."""
+    n, v, L = 2304, 128, 4
+    say(f"full-U12 threshold bitwise masked={masked}")
+    A = G.normal_matrix(n, 23)
+    got = []
+    for rows in (1 << 30, 0, 1000):
+        h = cfx.Handle()
+        try:
+            cfx.set_full_trsm_rows(rows, handle=h)
+            assert cfx.full_trsm_rows(handle=h) == rows
+            dA = to_dev(A)
+            if masked:
+                ipiv, rowmap, info = cfx.getrf_masked(dA, v=v, leaves=L, lookahead=1, handle=h)
+            else:
+                ipiv, info = cfx.getrf(dA, v=v, leaves=L, lookahead=1, handle=h)
+            torch.cuda.synchronize()
+        finally:
+            h.close()
+        LU = dA.cpu().numpy()
+        if masked:
+            LU = LU[rowmap.cpu().numpy()[:n]]
+        got.append((LU, ipiv.cpu().numpy()[:n], int(info.cpu()[0])))
+    for LU, ipiv, info in got[1:]:
+        assert info == got[0][2]
+        assert np.array_equal(ipiv, got[0][1])
+        assert np.array_equal(LU, got[0][0])
+    ref = O.getrf(A, v, L)
+    compare_panels(got[0][1], ref.ipiv, ref.margins, v)
+
+
 @pytest.mark.parametrize("n,wgs,chunk", [(2100, 8, 64), (2100, 12, 300), (2100, 40, 4096), (2048, 8, 256),
                                          (2048, 24, 4096)])
 def test_getrf_bounded_schur_grid_bitwise_equal(cfx, n, wgs, chunk):

@@ -60,7 +60,7 @@ def check(cfx, prec, m, n, K, seed, wgs=0, wide=False):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "bf16", "fp16", "fp8"])
-@pytest.mark.parametrize("m,n,K", [(256, 384, 256), (512, 256, 128), (384, 128, 64)])
+@pytest.mark.parametrize("m,n,K", [(256, 384, 256), (512, 256, 128), (384, 128, 64), (256, 256, 80)])
 def test_whole_tiles(cfx, prec, m, n, K):
     say(f"schur whole tiles {prec} {m}x{n} K={K}")
     check(cfx, prec, m, n, K, 11 + m + n + K)
