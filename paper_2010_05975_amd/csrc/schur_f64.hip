@@ -48,16 +48,18 @@ __device__ __forceinline__ void tile_at(int pos, int tm, int tn, int &ti, int &t
     tj = r / gsz;
 }
 
+// One 128 x 128 tile (ti, tj) of C -= L U.
 // EDGE: the tile may cross the matrix edge or K is not a multiple of BK
 // (every access is guarded).  VEC: operands are 16-byte aligned with even
 // strides, so a thread fetches its 8 contiguous doubles as 4 x 16 bytes.
+// The arithmetic is the same in every variant (the guards only substitute
+// zeros and skip stores), so a tile's values do not depend on the variant.
 template <bool EDGE, bool VEC, bool MAPPED>
-__global__ __launch_bounds__(256, 2) void schur_f64_kernel(const double *__restrict__ L, int64_t ldl,
-                                                           const double *__restrict__ U, int64_t ldu,
-                                                           double *__restrict__ C, int64_t ldc,
-                                                           int64_t mr, int64_t nc, int K, int tm, int tn,
-                                                           const int32_t *__restrict__ rmap,
-                                                           const int32_t *__restrict__ umap)
+__device__ __forceinline__ void schur_tile(const double *__restrict__ L, int64_t ldl, const double *__restrict__ U,
+                                           int64_t ldu, double *__restrict__ C, int64_t ldc, int64_t mr, int64_t nc,
+                                           int K, int ti, int tj, const int32_t *__restrict__ rmap,
+                                           const int32_t *__restrict__ umap, double (*As)[BK * LDA_S],
+                                           double (*Bs)[BK * LDB_S])
 {
     // physical row of tile row i of L / C, and of row l of U
     auto crow = [&](int64_t i) -> int64_t {
@@ -68,24 +70,6 @@ __global__ __launch_bounds__(256, 2) void schur_f64_kernel(const double *__restr
         if constexpr (MAPPED) return (int64_t)umap[(!EDGE || l < K) ? l : 0];
         return l;
     };
-    __shared__ double As[2][BK * LDA_S];
-    __shared__ double Bs[2][BK * LDB_S];
-
-    // XCD-aware persistent schedule: the hardware sends workgroup b to XCD
-    // b % 8.  XCD x owns the contiguous positions [x*per, (x+1)*per) (plus
-    // position 8*per + x of the ragged end), and its workgroups walk them
-    // with a stride of their count, so the tiles that share operand strips
-    // stay in one L2.  With one workgroup per tile every workgroup takes
-    // exactly one position.
-    const int nb = tm * tn;
-    const int xcd = blockIdx.x % NXCD, slot = blockIdx.x / NXCD;
-    const int nsl = ((int)gridDim.x - xcd + NXCD - 1) / NXCD;   // workgroups on this XCD
-    const int per = nb / NXCD;
-    const int cnt = per + (xcd < nb - per * NXCD ? 1 : 0);
-#pragma unroll 1
-    for (int it = slot; it < cnt; it += nsl) {
-    int ti, tj;
-    tile_at(it < per ? xcd * per + it : NXCD * per + xcd, tm, tn, ti, tj);
     const int64_t i0 = (int64_t)ti * BM, j0 = (int64_t)tj * BN;
 
     const int tid = threadIdx.x;
@@ -205,8 +189,48 @@ __global__ __launch_bounds__(256, 2) void schur_f64_kernel(const double *__restr
                 if (!EDGE || (gi < mr && gj < nc)) __builtin_nontemporal_store(acc[a][b][q], &C[crow(gi) * ldc + gj]);
             }
         }
-    }   // tiles of this workgroup (the last K chunk ended with a barrier, so
-        // the next tile may refill the LDS buffers)
+}
+
+// Tiles are walked XCD-aware (below).  A ragged launch (EDGE) runs its
+// interior tiles, which lie wholly inside the matrix, through the unguarded
+// body and only the tiles on the edge through the guarded one.
+template <bool EDGE, bool VEC, bool MAPPED>
+__global__ __launch_bounds__(256, 2) void schur_f64_kernel(const double *__restrict__ L, int64_t ldl,
+                                                           const double *__restrict__ U, int64_t ldu,
+                                                           double *__restrict__ C, int64_t ldc,
+                                                           int64_t mr, int64_t nc, int K, int tm, int tn,
+                                                           const int32_t *__restrict__ rmap,
+                                                           const int32_t *__restrict__ umap)
+{
+    __shared__ double As[2][BK * LDA_S];
+    __shared__ double Bs[2][BK * LDB_S];
+
+    // XCD-aware persistent schedule: the hardware sends workgroup b to XCD
+    // b % 8.  XCD x owns the contiguous positions [x*per, (x+1)*per) (plus
+    // position 8*per + x of the ragged end), and its workgroups walk them
+    // with a stride of their count, so the tiles that share operand strips
+    // stay in one L2.  With one workgroup per tile every workgroup takes
+    // exactly one position.  Each tile ends with a barrier after its last K
+    // chunk, so the next tile may refill the LDS buffers.
+    const int nb = tm * tn;
+    const int xcd = blockIdx.x % NXCD, slot = blockIdx.x / NXCD;
+    const int nsl = ((int)gridDim.x - xcd + NXCD - 1) / NXCD;   // workgroups on this XCD
+    const int per = nb / NXCD;
+    const int cnt = per + (xcd < nb - per * NXCD ? 1 : 0);
+    const bool kfull = K % BK == 0;
+#pragma unroll 1
+    for (int it = slot; it < cnt; it += nsl) {
+        int ti, tj;
+        tile_at(it < per ? xcd * per + it : NXCD * per + xcd, tm, tn, ti, tj);
+        if constexpr (EDGE) {
+            if (kfull && (int64_t)(ti + 1) * BM <= mr && (int64_t)(tj + 1) * BN <= nc)
+                schur_tile<false, VEC, MAPPED>(L, ldl, U, ldu, C, ldc, mr, nc, K, ti, tj, rmap, umap, As, Bs);
+            else
+                schur_tile<true, VEC, MAPPED>(L, ldl, U, ldu, C, ldc, mr, nc, K, ti, tj, rmap, umap, As, Bs);
+        } else {
+            schur_tile<false, VEC, MAPPED>(L, ldl, U, ldu, C, ldc, mr, nc, K, ti, tj, rmap, umap, As, Bs);
+        }
+    }
 }
 
 }  // namespace
@@ -226,22 +250,26 @@ int launch_schur_f64(const double *L, int64_t ldl, const double *U, int64_t ldu,
     const bool vec = ((reinterpret_cast<uintptr_t>(L) | reinterpret_cast<uintptr_t>(U)) & 15) == 0 &&
                      (ldl % 2 == 0) && (ldu % 2 == 0);
     if ((rmap == nullptr) != (umap == nullptr)) return CFX_ENOTSUP;   // both maps or none
+    const dim3 grid((unsigned)nb), block(256);
+#define CFX_SCHUR_LAUNCH(E, V, M)                                                                          \
+    hipLaunchKernelGGL((schur_f64_kernel<E, V, M>), grid, block, 0, st, L, ldl, U, ldu, C, ldc, mr, nc, K, tm, tn, \
+                       rmap, umap)
     if (rmap) {
-        if (full && vec)
-            hipLaunchKernelGGL((schur_f64_kernel<false, true, true>), dim3((unsigned)nb), dim3(256), 0, st, L,
-                               ldl, U, ldu, C, ldc, mr, nc, K, tm, tn, rmap, umap);
-        else
-            hipLaunchKernelGGL((schur_f64_kernel<true, false, true>), dim3((unsigned)nb), dim3(256), 0, st, L,
-                               ldl, U, ldu, C, ldc, mr, nc, K, tm, tn, rmap, umap);
-    } else if (full && vec)
-        hipLaunchKernelGGL((schur_f64_kernel<false, true, false>), dim3((unsigned)nb), dim3(256), 0, st, L, ldl,
-                           U, ldu, C, ldc, mr, nc, K, tm, tn, rmap, umap);
-    else if (full)
-        hipLaunchKernelGGL((schur_f64_kernel<false, false, false>), dim3((unsigned)nb), dim3(256), 0, st, L,
-                           ldl, U, ldu, C, ldc, mr, nc, K, tm, tn, rmap, umap);
-    else
-        hipLaunchKernelGGL((schur_f64_kernel<true, false, false>), dim3((unsigned)nb), dim3(256), 0, st, L, ldl,
-                           U, ldu, C, ldc, mr, nc, K, tm, tn, rmap, umap);
+        if (full) {
+            if (vec) CFX_SCHUR_LAUNCH(false, true, true);
+            else CFX_SCHUR_LAUNCH(false, false, true);
+        } else {
+            if (vec) CFX_SCHUR_LAUNCH(true, true, true);
+            else CFX_SCHUR_LAUNCH(true, false, true);
+        }
+    } else if (full) {
+        if (vec) CFX_SCHUR_LAUNCH(false, true, false);
+        else CFX_SCHUR_LAUNCH(false, false, false);
+    } else {
+        if (vec) CFX_SCHUR_LAUNCH(true, true, false);
+        else CFX_SCHUR_LAUNCH(true, false, false);
+    }
+#undef CFX_SCHUR_LAUNCH
     CFX_HIP(hipGetLastError());
     return CFX_OK;
 }
