@@ -109,7 +109,7 @@ static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
     int64_t max_nodes, node_rows;
-    size_t off_S, off_cand0, off_cand1, off_cnt0, off_cnt1, off_plan, off_lu00, off_selg, off_rsel,
+    size_t off_S, off_cand0, off_cand1, off_cnt0, off_cnt1, off_plan, off_plan2, off_lu00, off_selg, off_rsel,
         off_utg, off_rtg, off_mp, total;
 };
 
@@ -133,6 +133,7 @@ static Layout layout(int64_t n, int v, int leaves, int precision, int delay, int
     L.off_cnt0 = o;  o = align_up(o + (size_t)L.max_nodes * sizeof(int32_t));
     L.off_cnt1 = o;  o = align_up(o + (size_t)L.max_nodes * sizeof(int32_t));
     L.off_plan = o;  o = align_up(o + (size_t)(1 + 4 * kMaxV) * sizeof(int32_t));
+    L.off_plan2 = o; o = align_up(o + (size_t)(1 + 4 * kMaxV) * sizeof(int32_t));
     L.off_lu00 = o;  o = align_up(o + (size_t)v * v * sizeof(double));
     L.off_selg = o;  o = align_up(o + (size_t)L.max_nodes * 2 * kMaxV * sizeof(int32_t));
     L.off_rsel = o;  o = align_up(o + (size_t)L.max_nodes * L.node_rows);
@@ -163,6 +164,7 @@ int carve_workspace(void *work, size_t bytes, int64_t n, int v, int leaves, int 
     ws->ccnt[0] = reinterpret_cast<int32_t *>(b + L.off_cnt0);
     ws->ccnt[1] = reinterpret_cast<int32_t *>(b + L.off_cnt1);
     ws->plan = reinterpret_cast<int32_t *>(b + L.off_plan);
+    ws->plan_alt = reinterpret_cast<int32_t *>(b + L.off_plan2);
     ws->lu00 = reinterpret_cast<double *>(b + L.off_lu00);
     ws->selg = reinterpret_cast<int32_t *>(b + L.off_selg);
     ws->rsel = reinterpret_cast<unsigned char *>(b + L.off_rsel);
@@ -506,8 +508,16 @@ static int getrf_run(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *
     // k..k+vb; with a row map the blocks point at row 0 of their columns and
     // their rows go through the map.
     auto panel_w = [&](int64_t k) -> double * { return rm ? A + k : A + k * lda + k; };
+    // The row-move plan of panel k: panels alternate between two buffers,
+    // so a panel's interchanges that are still being applied beside the
+    // next panel's tournament never read the plan that tournament writes.
+    auto wsk = [&](int64_t k) -> Workspace {
+        Workspace w = ws;
+        if ((k / v) & 1) w.plan = ws.plan_alt;
+        return w;
+    };
     auto swap = [&](int64_t k, int vb, hipStream_t s) -> int {
-        return rm ? launch_rowmap_apply(A, lda, rm, k, vb, ws, s) : launch_laswp(A, lda, n, k, vb, ws, s);
+        return rm ? launch_rowmap_apply(A, lda, rm, k, vb, wsk(k), s) : launch_laswp(A, lda, n, k, vb, wsk(k), s);
     };
     struct Blocks {
         double *L21, *U12, *C;
@@ -537,7 +547,7 @@ static int getrf_run(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *
             const int vb = (int)((n - k) < v ? (n - k) : v);
             const int64_t m = n - k - vb;
             hipEvent_t e = pf.begin(st);
-            if ((rc = launch_tslu(panel_w(k), lda, k, n - k, vb, panel_leaves(L, ml, n - k), ws, nullptr, ipiv,
+            if ((rc = launch_tslu(panel_w(k), lda, k, n - k, vb, panel_leaves(L, ml, n - k), wsk(k), nullptr, ipiv,
                                   info, st, rm,
                                   h->fuse_rows)))
                 return rc;
@@ -569,7 +579,7 @@ static int getrf_run(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *
     {
         const int vb0 = (int)(n < v ? n : v);
         hipEvent_t e = pf.begin(st);
-        if ((rc = launch_tslu(panel_w(0), lda, 0, n, vb0, panel_leaves(L, ml, n), ws, nullptr, ipiv, info, st, rm,
+        if ((rc = launch_tslu(panel_w(0), lda, 0, n, vb0, panel_leaves(L, ml, n), wsk(0), nullptr, ipiv, info, st, rm,
                               h->fuse_rows)))
             return rc;
         pf.end(PH_TSLU, e, st);
@@ -581,11 +591,19 @@ static int getrf_run(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *
         if (tslu_on_side) CFX_HIP(hipStreamWaitEvent(st, h->ev_tslu, 0));
         if (upd_pending) CFX_HIP(hipStreamWaitEvent(st, h->ev_upd, 0));
         tslu_on_side = upd_pending = false;
+        // While the next tournament bounds the step (U12 split between the
+        // first solve and the rest of the update), only the columns of this
+        // panel and the next one are interchanged ahead of it; the others go
+        // with the rest of the update, before the rest of U12.
+        const int vbn0 = (int)(m < v ? m : v);
+        const bool split_swap = !rm && m > 0 && prec == CFX_PREC_FP64 && m < h->full_trsm_rows;
         hipEvent_t e = pf.begin(st);
-        if ((rc = swap(k, vb, st))) return rc;
+        if (split_swap) rc = launch_laswp(A, lda, n, k, vb, wsk(k), st, k, k + vb + vbn0, true);
+        else rc = swap(k, vb, st);
+        if (rc) return rc;
         pf.end(PH_LASWP, e, st);
         if (m > 0) {
-            const int vbn = (int)(m < v ? m : v);          // next panel width
+            const int vbn = vbn0;                          // next panel width
             // FP64: L21 and the next panel's columns of U12 first (one
             // launch), the rest of U12 with the rest of the update; the
             // low-precision pack needs all of U12 at once.  (The rest of U12
@@ -618,7 +636,7 @@ static int getrf_run(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *
             const int64_t kn = k + vb;
             auto tournament = [&]() -> int {
                 hipEvent_t et = pf.begin(ts);
-                const int r = launch_tslu(panel_w(kn), lda, kn, n - kn, vbn, panel_leaves(L, ml, n - kn), ws,
+                const int r = launch_tslu(panel_w(kn), lda, kn, n - kn, vbn, panel_leaves(L, ml, n - kn), wsk(kn),
                                           nullptr, ipiv, info, ts, rm, h->fuse_rows);
                 if (r) return r;
                 pf.end(PH_TSLU, et, ts);
@@ -630,6 +648,11 @@ static int getrf_run(cfx_handle *h, int64_t n, double *A, int64_t lda, int32_t *
             // panel's critical path and the rest only has to end before the
             // next interchanges
             if (us == ts && (rc = tournament())) return rc;
+            if (split_swap) {
+                e = pf.begin(us);
+                if ((rc = launch_laswp(A, lda, n, k, vb, wsk(k), us, k, k + vb + vbn, false))) return rc;
+                pf.end(PH_LASWP, e, us);
+            }
             if (n1 < m) {
                 e = pf.begin(us);
                 if ((rc = launch_trsm_rest(A, lda, k, vb, m, n1, us, rm))) return rc;

@@ -27,6 +27,7 @@ struct Workspace {
     int32_t *cand[2];   // candidate lists, ping-pong: nodes x v
     int32_t *ccnt[2];   // candidate counts: nodes
     int32_t *plan;      // row-move plan: [0] = count, then dst[2v], src[2v]
+    int32_t *plan_alt;  // a second plan buffer (panels of the lookahead schedule alternate)
     double *lu00;       // factored diagonal block, v x v
     int32_t *selg;      // tournament node state: selection [nodes x 2 x kMaxV]
     unsigned char *rsel; // tournament node state: selected-row mask [nodes x rs_node]
@@ -113,10 +114,12 @@ int launch_trsv(int64_t n, int64_t nrhs, const double *LU, int64_t lda, double *
 // Host-blocking: *gave_up = sync[4] after `st` drains; sync[4] is cleared.
 int read_solve_flag(int32_t *sync, hipStream_t st, bool *gave_up);
 
-// Apply the row-move plan to all n columns of A; the diagonal block of the
-// panel (rows k..k+vb, columns k..k+vb) is written from ws.lu00.
+// Apply the row-move plan to the n columns of A (w1 <= w0), to the columns
+// [w0, w1) only (window), or to all columns but those; the diagonal block of
+// the panel (rows k..k+vb, columns k..k+vb) is written from ws.lu00 where
+// its columns are covered.
 int launch_laswp(double *A, int64_t lda, int64_t n, int64_t k, int vb,
-                 const Workspace &ws, hipStream_t st);
+                 const Workspace &ws, hipStream_t st, int64_t w0 = 0, int64_t w1 = 0, bool window = false);
 
 // Row masking: the root's row-move plan applied to the row map rm (logical
 // row -> physical row) instead of the rows, and L00\U00 written into the

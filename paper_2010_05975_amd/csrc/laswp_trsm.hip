@@ -38,13 +38,18 @@ namespace {
 constexpr int SW_COLS = 16;
 constexpr int SW_SLOTS = 2 * kMaxV / (256 / SW_COLS);   // 32 pairs per thread
 
+// Columns c0 + s for stripe positions s < split, c0 + skip + s after them,
+// below n: the interchanges of one column range, or of all columns outside a
+// window.
 __global__ __launch_bounds__(256) void laswp_kernel(double *A, int64_t lda, int64_t n, int64_t k,
-                                                    int vb, const int32_t *plan, const double *lu00)
+                                                    int vb, const int32_t *plan, const double *lu00,
+                                                    int64_t c0, int64_t split, int64_t skip)
 {
     const int np = plan[0];
     const int32_t *dst = plan + 1;
     const int32_t *src = plan + 1 + 2 * kMaxV;
-    const int64_t c = (int64_t)blockIdx.x * SW_COLS + (threadIdx.x & (SW_COLS - 1));
+    const int64_t sp = (int64_t)blockIdx.x * SW_COLS + (threadIdx.x & (SW_COLS - 1));
+    const int64_t c = c0 + sp + (sp >= split ? skip : 0);
     const int q0 = threadIdx.x / SW_COLS;
     const bool in_panel = c >= k && c < k + vb;
     double vals[SW_SLOTS];
@@ -318,11 +323,27 @@ __global__ void set_int_kernel(int32_t *p, int32_t v) { *p = v; }
 }  // namespace
 
 int launch_laswp(double *A, int64_t lda, int64_t n, int64_t k, int vb, const Workspace &ws,
-                 hipStream_t st)
+                 hipStream_t st, int64_t w0, int64_t w1, bool window)
 {
-    const int64_t grid = (n + SW_COLS - 1) / SW_COLS;
-    hipLaunchKernelGGL(laswp_kernel, dim3((unsigned)grid), dim3(256), 0, st, A, lda, n, k, vb,
-                       (const int32_t *)ws.plan, (const double *)ws.lu00);
+    // all n columns (w1 <= w0); the columns [w0, w1) (window); or all
+    // columns but those
+    int64_t c0 = 0, cols = n, split = n, skip = 0, end = n;
+    if (w1 > w0) {
+        if (window) {
+            c0 = w0;
+            cols = w1 - w0;
+            split = cols;
+            end = w1;
+        } else {
+            cols = n - (w1 - w0);
+            split = w0;
+            skip = w1 - w0;
+        }
+    }
+    if (cols <= 0) return CFX_OK;
+    const int64_t grid = (cols + SW_COLS - 1) / SW_COLS;
+    hipLaunchKernelGGL(laswp_kernel, dim3((unsigned)grid), dim3(256), 0, st, A, lda, end, k, vb,
+                       (const int32_t *)ws.plan, (const double *)ws.lu00, c0, split, skip);
     CFX_HIP(hipGetLastError());
     return CFX_OK;
 }
