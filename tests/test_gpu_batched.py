@@ -88,6 +88,41 @@ def test_batched_workload_sample_matches_oracle(cfx):
                      batch.Bs[i].cpu().numpy(), f"system {i} n={n}")
 
 
+def test_batched_pooled_layout_matches_oracle(cfx):
+    """Systems packed back to back in one buffer each for A and B (lda = n,
+    ldb = nrhs, no padding), as the batched workload lays them out: a
+    kernel that touched memory outside its own system would change a
+    neighbour.  Every system is checked against the oracle, and the pool's
+    bytes outside the systems' matrices are unchanged (there are none inside
+    the pool; guard blocks before and after it are checked instead)."""
+    spec = G.batched_spec(240, 21)
+    say("batched pooled layout (240 systems, lda = n)")
+    systems = [G.batched_system(spec, i) for i in range(240)]
+    n = np.array([A.shape[0] for A, _ in systems], dtype=np.int64)
+    r = np.array([B.shape[1] for _, B in systems], dtype=np.int64)
+    offA = np.concatenate([[0], np.cumsum(n * n)])
+    offB = np.concatenate([[0], np.cumsum(n * r)])
+    guard = 4096
+    poolA = torch.full((int(offA[-1]) + 2 * guard,), 7.25, dtype=torch.float64, device="cuda")
+    poolB = torch.full((int(offB[-1]) + 2 * guard,), 7.25, dtype=torch.float64, device="cuda")
+    hostA = np.concatenate([A.ravel() for A, _ in systems])
+    hostB = np.concatenate([B.ravel() for _, B in systems])
+    poolA[guard:guard + hostA.size] = to_dev(hostA)
+    poolB[guard:guard + hostB.size] = to_dev(hostB)
+    As = [poolA[guard + int(offA[i]):guard + int(offA[i + 1])].view(int(n[i]), int(n[i])) for i in range(240)]
+    Bs = [poolB[guard + int(offB[i]):guard + int(offB[i + 1])].view(int(n[i]), int(r[i])) for i in range(240)]
+    batch = cfx.Batch(As, Bs)
+    info = cfx.gesv_batched(batch, graph=False).cpu().numpy()
+    torch.cuda.synchronize()
+    pa, pb = poolA.cpu().numpy(), poolB.cpu().numpy()
+    for g in (pa[:guard], pa[guard + hostA.size:], pb[:guard], pb[guard + hostB.size:]):
+        assert np.all(g == 7.25)
+    for i, (A, B) in enumerate(systems):
+        k = A.shape[0]
+        check_system(A, B, As[i].cpu().numpy(), batch.ipiv[i][:k].cpu().numpy(), int(info[i]),
+                     Bs[i].cpu().numpy(), f"pooled system {i} n={k}")
+
+
 def test_batched_graph_replays_match_eager(cfx):
     """The first call captures the launches into a graph; later calls with
     the same arguments replay it.  Between replays the inputs are restored
