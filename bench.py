@@ -661,7 +661,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only (no sharding or collectives); "
+        print("bench.py: the factorisation runs on one GPU only (no sharding or collectives); "
               "a single N x N factorisation is one GPU's work. Run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
