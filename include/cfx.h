@@ -299,8 +299,8 @@ int cfx_set_solve_spin_limit(cfx_handle *h, int32_t polls);
  * device array of 32 MiB per GPU (set up by cfx_create; held until the
  * process ends) instead of the handle's growable scratch.  No call on this
  * path allocates or frees memory.
- *   Limit: 256 + 4 n (rounded up to 256) + 8 n nrhs bytes <= 32 MiB (e.g.
- *   n = 32768 with up to 127 right-hand sides); larger problems return
+ *   Limit: 256 + 4 n (rounded up to 256) + 8 n max(nrhs, 2) bytes <= 32 MiB
+ *   (e.g. n = 32768 with up to 127 right-hand sides); larger problems return
  *   CFX_ENOTSUP without doing anything.
  *   Every call on one GPU shares that array: calls that overlap on the
  *   device race (order them on one stream, or through events).  The

@@ -785,7 +785,7 @@ int cfx_gesv_ir(cfx_handle *h, int64_t n, int64_t nrhs, const double *A, int64_t
     for (int64_t c = 0; c < nrhs; ++c) {
         if ((rc = launch_copy_rows(n, 1, B + c, ldb, v.b, 1, st))) return rc;
         if ((rc = launch_gather_rows(n, 1, v.b, 1, perm, v.x, 1, st))) return rc;
-        if ((rc = launch_trsv(n, 1, F, n, v.x, 1, v.sync, st, p.spin_limit))) return rc;
+        if ((rc = launch_trsv(n, 1, F, n, v.x, 1, v.sync, v.ys, st, p.spin_limit))) return rc;
         IrResult res{};
         rc = ir_refine(A, lda, F, n, perm, v, p, &res, st);
         if (rc == CFX_ESOLVE) {         // X is NaN: report it, go on with the others
@@ -1115,7 +1115,7 @@ int cfx_getrs(cfx_handle *h, int64_t n, int64_t nrhs, const double *LU, int64_t 
     if (ldb < (nrhs > 1 ? nrhs : 1)) return -8;
     if (n == 0 || nrhs == 0) return CFX_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const size_t need = align_up((size_t)n * sizeof(int32_t)) + (size_t)n * nrhs * sizeof(double);
+    const size_t need = align_up((size_t)n * sizeof(int32_t)) + (size_t)n * (nrhs > 1 ? nrhs : 2) * sizeof(double);
     int rc = ensure_scratch(h, need);
     if (rc) return rc;
     // calls on one handle share its scratch and counters: each one waits for
@@ -1188,7 +1188,8 @@ int cfx_getrs_noalloc(cfx_handle *h, int64_t n, int64_t nrhs, const double *LU, 
     // device's fixed scratch (no allocation on this path)
     const size_t off_perm = kTrsvSyncBytes;
     const size_t off_tmp = off_perm + align_up((size_t)n * sizeof(int32_t));
-    if ((size_t)nrhs > (kNoAllocScratchBytes - off_tmp) / sizeof(double) / (size_t)n) return CFX_ENOTSUP;
+    const size_t cols = nrhs > 1 ? (size_t)nrhs : 2;   // one right-hand side: its solve's intermediate vector
+    if (cols > (kNoAllocScratchBytes - off_tmp) / sizeof(double) / (size_t)n) return CFX_ENOTSUP;
     if (!h->na_scratch) return CFX_EHIP;
     hipStream_t st = static_cast<hipStream_t>(stream);
     char *base = static_cast<char *>(h->na_scratch);
@@ -1214,7 +1215,7 @@ int cfx_getrs_masked(cfx_handle *h, int64_t n, int64_t nrhs, const double *LU, i
     if (ldb < (nrhs > 1 ? nrhs : 1)) return -8;
     if (n == 0 || nrhs == 0) return CFX_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const size_t need = (size_t)n * nrhs * sizeof(double);
+    const size_t need = (size_t)n * (nrhs > 1 ? nrhs : 2) * sizeof(double);
     int rc = ensure_scratch(h, need);
     if (rc) return rc;
     if (h->getrs_issued) CFX_HIP(hipStreamWaitEvent(st, h->ev_getrs, 0));

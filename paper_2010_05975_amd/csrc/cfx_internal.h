@@ -90,7 +90,8 @@ constexpr int kSolveSpinLimit = 1 << 22;
 
 // getrs pieces: permutation of ipiv, and the blocked triangular solves.
 // rm (row masking): factor row i is physical row rm[i], and rm is also the
-// permutation of P B (ipiv is then not read).
+// permutation of P B (ipiv is then not read).  tmp holds n x max(nrhs, 2)
+// doubles.
 int launch_getrs(int64_t n, int64_t nrhs, const double *LU, int64_t lda,
                  const int32_t *ipiv, double *B, int64_t ldb, int32_t *perm,
                  double *tmp, int32_t *sync, hipStream_t st,
@@ -103,13 +104,15 @@ int launch_gather_rows(int64_t n, int64_t nrhs, const double *B, int64_t ldb,
 int launch_copy_rows(int64_t n, int64_t nrhs, const double *T, int64_t ldt,
                      double *B, int64_t ldb, hipStream_t st);
 // X <- U^{-1} L^{-1} X in place (X n x nrhs, stride ldx).  `sync` (device,
-// kTrsvSyncBytes, may be null) lets one contiguous right-hand side take the
-// one-launch-per-triangle solve; calls sharing a sync buffer must be
-// stream-ordered.  sync[4] is set (and stays set until the host clears it)
-// when a wait of that solve gave up after spin_limit polls.
+// kTrsvSyncBytes) and Y (device, n doubles, the intermediate vector; its
+// contents are overwritten) let one contiguous right-hand side take the
+// one-launch-per-triangle solve; with either null it takes the blocked
+// launches.  Calls sharing a sync buffer or Y must be stream-ordered.
+// sync[4] is set (and stays set until the host clears it) when a wait of
+// that solve gave up after spin_limit polls.
 constexpr size_t kTrsvSyncBytes = 256;
 int launch_trsv(int64_t n, int64_t nrhs, const double *LU, int64_t lda, double *X,
-                int64_t ldx, int32_t *sync, hipStream_t st,
+                int64_t ldx, int32_t *sync, double *Y, hipStream_t st,
                 int spin_limit = kSolveSpinLimit, const int32_t *rm = nullptr);
 // Host-blocking: *gave_up = sync[4] after `st` drains; sync[4] is cleared.
 int read_solve_flag(int32_t *sync, hipStream_t st, bool *gave_up);
@@ -198,6 +201,7 @@ struct IrVectors {
     int64_t n;
     int restart;
     double *x, *r, *b, *w, *z, *rowabs, *tmp;
+    double *ys;         // intermediate vector of the one-launch triangular solves
     double *V;          // restart + 1 Krylov vectors at stride ldv
     int64_t ldv;
     double *partial;    // block partial sums

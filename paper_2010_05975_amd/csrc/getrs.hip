@@ -385,22 +385,31 @@ __global__ __launch_bounds__(256) void bwd_step_kernel(const double *__restrict_
 
 // ---------------------------------------------------------------------------
 // One right-hand side: one launch per triangle.  Blocks of TB rows take
-// tickets in solve order (top down for L, bottom up for U); a block applies
-// the solved blocks as they appear (a release counter of solved blocks,
-// bumped in order), then solves its diagonal block in one wavefront and
-// publishes it.  A block only waits for blocks with smaller tickets, which
-// were taken by running workgroups, so every wait ends; each factor element
-// is still read once.  Per row the sum runs over the blocks in solve order,
-// 16 columns per lane, then a fixed quad reduction: the result does not
-// depend on timing.
+// tickets in solve order (top down for L, bottom up for U).  Each triangle
+// reads its right-hand side from one vector and writes its solution to the
+// other, whose entries hold a mark (a signalling-NaN bit pattern that no
+// arithmetic result carries) until they are solved: a block applies the
+// solved blocks as their values appear, each wavefront polling the values
+// themselves (one relaxed device-scope load per lane; a value is final once
+// it is not the mark), so no counter and no fence lies between a block's
+// result and the blocks that use it.  Then the block solves its diagonal
+// block in one wavefront and stores its values.  A block only waits for
+// blocks with smaller tickets, which were taken by running workgroups, so
+// every wait ends; each factor element is still read once.  Per row the sum
+// runs over the blocks in solve order, 16 columns per lane, then a fixed
+// quad reduction: the result does not depend on timing.
 // ---------------------------------------------------------------------------
 constexpr int TB = 64;
+constexpr unsigned long long kUnsolved = 0xFFF05EB71E5E17A1ull;   // exponent all ones, quiet bit clear
+constexpr unsigned long long kQuietNaN = 0x7FF8000000000000ull;
 
-// Clears the tickets and solved counts; sync[4] (a wait gave up) is sticky
-// until the host reads and clears it.
-__global__ void trsv_sync_reset_kernel(int32_t *sync)
+// Clears the tickets and marks every entry of `out` unsolved; sync[4] (a
+// wait gave up) is sticky until the host reads and clears it.
+__global__ void trsv_reset_kernel(int32_t *sync, double *out, int64_t n)
 {
-    if (threadIdx.x < 4) sync[threadIdx.x] = 0;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 4) sync[i] = 0;
+    if (i < n) out[i] = __longlong_as_double((long long)kUnsolved);
 }
 
 template <int CTRL>
@@ -411,23 +420,39 @@ __device__ __forceinline__ double dpp_d(double a)
     return __hiloint2double(hi, lo);
 }
 
-// LOWER: L y = x with unit L (forward); else U x = y (backward).
-// sync[0..1] forward ticket / solved count, sync[2..3] backward, sync[4]
-// set when a wait gave up after spin_limit polls (never, when the tickets
-// order the blocks and the device runs every resident workgroup; the bound
-// only guarantees that every workgroup exits).  A block that gave up writes
-// NaN for its rows, so an invalid solution is never mistaken for a result.
+__device__ __forceinline__ double poll_value(const double *p)
+{
+    const unsigned long long u = __hip_atomic_load(reinterpret_cast<const unsigned long long *>(p),
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __longlong_as_double((long long)u);
+}
+
+__device__ __forceinline__ bool is_unsolved(double v)
+{
+    return (unsigned long long)__double_as_longlong(v) == kUnsolved;
+}
+
+// LOWER: L y = x with unit L (forward, in = x, out = y); else U x = y
+// (backward, in = y, out = x).  `out` holds the mark in every entry on
+// entry.  The forward solve also marks `in` once its block has read its
+// right-hand side, so `in` is ready to be the backward solve's `out`.
+// sync[0] / sync[2] are the forward / backward tickets, sync[4] is set when
+// a wait gave up after spin_limit polls (never, when the tickets order the
+// blocks and the device runs every resident workgroup; the bound only
+// guarantees that every workgroup exits).  A block that gave up writes NaN
+// for its rows, so an invalid solution is never mistaken for a result, and
+// waits no more.
 template <bool LOWER>
 __global__ __launch_bounds__(256) void trsv_sf_kernel(const double *__restrict__ LU, int64_t lda,
-                                                      const int32_t *rm, double *x, int64_t n, int nb,
-                                                      int32_t *sync, int spin_limit)
+                                                      const int32_t *rm, double *in, double *out, int64_t n,
+                                                      int nb, int32_t *sync, int spin_limit)
 {
     __shared__ double part[TB];
-    __shared__ double Ts[TB][TB + 1];   // the diagonal block (padded rows)
-    __shared__ int sh_t, sh_avail, sh_gaveup;
+    __shared__ double Ts[TB][TB + 1];   // the diagonal block (padded rows), zero on and off its triangle
+    __shared__ double Dg[TB];           // U: its diagonal
+    __shared__ int sh_t, sh_gaveup;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int32_t *ticket = sync + (LOWER ? 0 : 2);
-    int32_t *solved = sync + (LOWER ? 1 : 3);
     if (tid == 0) {
         sh_t = atomicAdd(ticket, 1);
         sh_gaveup = 0;
@@ -443,143 +468,188 @@ __global__ __launch_bounds__(256) void trsv_sf_kernel(const double *__restrict__
     const double *lrow = LU + fr(rm, r0 + (rok ? rr : 0)) * lda;
     const int nk = t;                            // blocks to apply, in solve order
     auto kcol = [&](int i) -> int64_t { return (int64_t)(LOWER ? i : nb - 1 - i) * TB + cq; };
+    // Every load is issued, its address clamped into the matrix (a row past
+    // the block's rows reads the block's first row, whose sums are never
+    // used), and what lies past column n is replaced by zero only where the
+    // values are used: no branch around a load, and no wait until the use.
     auto load_l = [&](int i, double *lv) {
         const int64_t c0 = kcol(i);
 #pragma unroll
-        for (int e = 0; e < 16; ++e) lv[e] = (rok && c0 + e < n) ? lrow[c0 + e] : 0.0;
+        for (int e = 0; e < 16; ++e) lv[e] = lrow[c0 + e < n ? c0 + e : n - 1];
     };
     // one value of block i of the solution per lane (lane l: column l)
+    auto xcol = [&](int i) -> int64_t { return (int64_t)(LOWER ? i : nb - 1 - i) * TB + lane; };
     auto load_x = [&](int i) -> double {
-        const int64_t c = (int64_t)(LOWER ? i : nb - 1 - i) * TB + lane;
-        return c < n ? x[c] : 0.0;
+        const int64_t c = xcol(i);
+        return poll_value(out + (c < n ? c : n - 1));
     };
-    // the diagonal block (L: strictly lower; U: upper with the diagonal) is
-    // staged in LDS before any wait; wave 0 takes it into registers only for
-    // the solve, so the registers stay free for the prefetch ring below
+    // the diagonal block (L: strictly lower; U: strictly upper, its
+    // diagonal apart) is staged in LDS before any wait (every load in
+    // bounds, so they are all in flight at once); wave 0 takes it into
+    // registers only for the solve, so the registers stay free for the
+    // prefetch ring below.  For U the coefficients above the diagonal are
+    // divided by the diagonal element of their column (the unit triangle
+    // U D^-1), so that no division waits on the previous row in the
+    // substitution.
+    double tv[TB * TB / 256];
 #pragma unroll
     for (int rep = 0; rep < TB * TB / 256; ++rep) {
         const int e = tid + 256 * rep;
         const int i = e / TB, j = e - i * TB;
-        const bool in = i < rows && j < rows && (LOWER ? j < i : j >= i);
-        Ts[i][j] = in ? LU[fr(rm, r0 + i) * lda + r0 + j] : 0.0;
+        const int ic = i < rows ? i : rows - 1, jc = j < rows ? j : rows - 1;
+        tv[rep] = LU[fr(rm, r0 + ic) * lda + r0 + jc];
     }
+#pragma unroll
+    for (int rep = 0; rep < TB * TB / 256; ++rep) {
+        const int e = tid + 256 * rep;
+        const int i = e / TB, j = e - i * TB;
+        const bool in_tri = i < rows && j < rows && (LOWER ? j < i : j > i);
+        Ts[i][j] = in_tri ? tv[rep] : 0.0;
+        if (!LOWER && i == j) Dg[i] = i < rows ? tv[rep] : 1.0;
+    }
+    if constexpr (!LOWER) {
+        __syncthreads();
+#pragma unroll
+        for (int rep = 0; rep < TB * TB / 256; ++rep) {
+            const int e = tid + 256 * rep;
+            const int i = e / TB, j = e - i * TB;
+            if (j > i && j < rows) Ts[i][j] = Ts[i][j] / Dg[j];
+        }
+    }
+    __syncthreads();                              // the staged block is visible to wave 0
     const bool ok = wave == 0 && lane < rows;
     const int64_t gi = r0 + (ok ? lane : 0);
-    const double rhs = ok ? x[gi] : 0.0;
+    const double rhs = ok ? in[gi] : 0.0;
 
     // per row: block sums (16 products each, one lane) accumulated over the
-    // blocks with Neumaier's compensation.  The factor tiles of the next
-    // blocks are requested D ahead, and the solution values of every block
-    // already known to be solved as soon as that is known (one value per
-    // lane, spread to the lanes that need it by cross-lane moves), so a
-    // block row that runs behind the solved blocks does not pay one memory
-    // round trip per block.
+    // blocks with Neumaier's compensation.  The factor tiles and the
+    // solution values of the next D blocks are requested ahead, so a block
+    // row that runs behind the solved blocks does not pay one memory round
+    // trip per block; a value still marked is loaded again when its block
+    // is reached, until it is not.
+    // The ring of D slots is unrolled by D, so that every slot keeps its
+    // registers and the wait before a slot's use covers only that slot's
+    // loads, not those issued after it.
     constexpr int D = 3;
     double acc = 0.0, cmp = 0.0;
     double lq[D][16];
     double xq[D];
-    bool xv[D];
-    static_for<D>([&](auto S) {
-        constexpr int q = decltype(S)::value;
-        if (q < nk) load_l(q, lq[q]);
-        xq[q] = 0.0;
-        xv[q] = false;
-    });
-    int i = 0;
-    while (i < nk) {
-        if (tid == 0) {
-            int sv = __hip_atomic_load(solved, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            for (int spins = 0; sv <= i && spins < spin_limit; ++spins) {
-                __builtin_amdgcn_s_sleep(2);
-                sv = __hip_atomic_load(solved, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            // the solved blocks' values become visible to this workgroup
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            if (sv <= i) {
-                atomicOr(sync + 4, 1);
-                sh_gaveup = 1;
-                sv = nk;
-            }
-            sh_avail = sv < nk ? sv : nk;
+    bool gave = false;
+    auto refill = [&](int q, int i) {
+        load_l(i, lq[q]);
+        xq[q] = load_x(i);
+    };
+    auto apply = [&](int q, int i) {
+        double xi = xq[q];
+        if (!gave && __ballot(is_unsolved(xi))) {
+            int spins = 0;
+            do {
+                if (spins++ >= spin_limit) {
+                    gave = true;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+                xi = load_x(i);
+            } while (__ballot(is_unsolved(xi)));
         }
-        __syncthreads();
-        const int avail = sh_avail;
-        for (; i < avail; ++i) {
+        if (xcol(i) >= n) xi = 0.0;
+        if (kcol(i) - cq + TB > n) {              // the block reaches past column n
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+                if (kcol(i) + e >= n) lq[q][e] = 0.0;
+        }
+        double bsum = 0.0;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) bsum += lq[q][e] * __shfl(xi, cq + e);
+        const double tsum = acc + bsum;
+        cmp += fabs(acc) >= fabs(bsum) ? (acc - tsum) + bsum : (bsum - tsum) + acc;
+        acc = tsum;
+    };
+    if (nk > 0) {
+        static_for<D>([&](auto S) {
+            if (decltype(S)::value < nk) refill(decltype(S)::value, decltype(S)::value);
+        });
+        for (int i = 0; i < nk; i += D) {
             static_for<D>([&](auto S) {
                 constexpr int q = decltype(S)::value;
-                if (!xv[q] && i + q < avail) {
-                    xq[q] = load_x(i + q);
-                    xv[q] = true;
+                if (i + q < nk) {
+                    apply(q, i + q);
+                    if (i + q + D < nk) refill(q, i + q + D);
                 }
             });
-            double ln[16];
-            if (i + D < nk) load_l(i + D, ln);
-            double bsum = 0.0;
-#pragma unroll
-            for (int e = 0; e < 16; ++e) bsum += lq[0][e] * __shfl(xq[0], cq + e);
-            const double tsum = acc + bsum;
-            cmp += fabs(acc) >= fabs(bsum) ? (acc - tsum) + bsum : (bsum - tsum) + acc;
-            acc = tsum;
-            static_for<D - 1>([&](auto S) {
-                constexpr int q = decltype(S)::value;
-#pragma unroll
-                for (int e = 0; e < 16; ++e) lq[q][e] = lq[q + 1][e];
-                xq[q] = xq[q + 1];
-                xv[q] = xv[q + 1];
-            });
-            if (i + D < nk) {
-#pragma unroll
-                for (int e = 0; e < 16; ++e) lq[D - 1][e] = ln[e];
-            }
-            xv[D - 1] = false;
         }
-        __syncthreads();                          // sh_avail is written again
+    }
+    // wave 0 requests its rows of the diagonal block now, so that the reads
+    // are in flight during the reduction and the barrier
+    double Tr[TB];
+    if (wave == 0) {
+#pragma unroll
+        for (int j = 0; j < TB; ++j) Tr[j] = Ts[lane][j];
     }
     acc += cmp;
     acc += dpp_d<0xB1>(acc);                      // quad_perm [1,0,3,2]
     acc += dpp_d<0x4E>(acc);                      // quad_perm [2,3,0,1]
     if ((lane & 3) == 0) part[rr] = acc;
+    if (gave && lane == 0) {
+        sh_gaveup = 1;
+        atomicOr(sync + 4, 1);
+    }
     __syncthreads();
     if (wave != 0) return;
-    double Tr[TB];      // L: columns j < lane; U: columns j > lane
+    // Lane l holds row l; at step j (solve order) the value of row j is
+    // final, is broadcast, and every lane subtracts its coefficient of
+    // column j times it.  The coefficients of a lane's own and later columns
+    // are zero, so the step is one broadcast and one fused multiply-add over
+    // the whole wavefront: a row already final takes v - 0 * x_j, which is v
+    // unless x_j is not finite or v is a zero of the other sign than the
+    // product.  The wavefront is issue-bound here, so this form (no per-step
+    // selection of the final values) is the fast one; when any result is
+    // zero or not finite, the block is solved again keeping each row's value
+    // at its own step, which is exact in every case.  U is solved as U D^-1
+    // (unit diagonal) for D x; x follows by one division per row.
+    const double dg = LOWER ? 1.0 : Dg[lane];
+    const double v0 = ok ? rhs - part[lane] : 0.0;
+    double v = v0;
 #pragma unroll
-    for (int j = 0; j < TB; ++j) Tr[j] = (LOWER || j > lane) ? Ts[lane][j] : 0.0;
-    const double dg = (!LOWER && ok) ? Ts[lane][lane] : 1.0;
-    double v = ok ? rhs - part[lane] : 0.0;
-    if constexpr (LOWER) {
-#pragma unroll
-        for (int j = 0; j < TB; ++j) {
-            if (j < rows) {
-                const double xj = bcast(v, j);
-                v = lane > j ? v - Tr[j] * xj : v;
-            }
-        }
-    } else {
-#pragma unroll
-        for (int j = TB - 1; j >= 0; --j) {
-            if (j < rows) {
-                if (lane == j) v = v / dg;
-                const double xj = bcast(v, j);
-                v = lane < j ? v - Tr[j] * xj : v;
-            }
+    for (int s = 0; s < TB; ++s) {
+        const int j = LOWER ? s : TB - 1 - s;
+        if (j < rows) v = v - Tr[j] * bcast(v, j);
+    }
+    double fin = v;
+    if (__ballot(ok && (v == 0.0 || !__builtin_isfinite(v)))) {
+        v = v0;
+#pragma unroll 1
+        for (int s = 0; s < rows; ++s) {
+            const int j = LOWER ? s : rows - 1 - s;
+            const double xj = bcast(v, j);
+            fin = lane == j ? v : fin;
+            v = v - Ts[lane][j] * xj;
         }
     }
-    if (ok) x[gi] = sh_gaveup ? __builtin_nan("") : v;
-    // the wavefront's stores complete before the count moves on
-    if (lane == 0) __hip_atomic_store(solved, t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if constexpr (!LOWER) fin = fin / dg;
+    v = fin;
+    if (ok) {
+        unsigned long long u = sh_gaveup ? kQuietNaN : (unsigned long long)__double_as_longlong(v);
+        if (u == kUnsolved) u = kQuietNaN;
+        __hip_atomic_store(reinterpret_cast<unsigned long long *>(out + gi), u, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        if (LOWER) in[gi] = __longlong_as_double((long long)kUnsolved);
+    }
 }
 
-int trsv_one(int64_t n, const double *LU, int64_t lda, const int32_t *rm, double *x, int32_t *sync,
+// x (n doubles, contiguous) holds P b on entry and the solution on return;
+// y (n doubles) is the intermediate vector.
+int trsv_one(int64_t n, const double *LU, int64_t lda, const int32_t *rm, double *x, double *y, int32_t *sync,
              int spin_limit, hipStream_t st)
 {
     const int64_t nb = (n + TB - 1) / TB;
     if (nb > INT32_MAX) return CFX_ENOTSUP;
-    hipLaunchKernelGGL(trsv_sync_reset_kernel, dim3(1), dim3(64), 0, st, sync);
+    hipLaunchKernelGGL(trsv_reset_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, sync, y, n);
     CFX_HIP(hipGetLastError());
-    hipLaunchKernelGGL(trsv_sf_kernel<true>, dim3((unsigned)nb), dim3(256), 0, st, LU, lda, rm, x, n, (int)nb,
+    hipLaunchKernelGGL(trsv_sf_kernel<true>, dim3((unsigned)nb), dim3(256), 0, st, LU, lda, rm, x, y, n, (int)nb,
                        sync, spin_limit);
     CFX_HIP(hipGetLastError());
-    hipLaunchKernelGGL(trsv_sf_kernel<false>, dim3((unsigned)nb), dim3(256), 0, st, LU, lda, rm, x, n, (int)nb,
+    hipLaunchKernelGGL(trsv_sf_kernel<false>, dim3((unsigned)nb), dim3(256), 0, st, LU, lda, rm, y, x, n, (int)nb,
                        sync, spin_limit);
     CFX_HIP(hipGetLastError());
     return CFX_OK;
@@ -669,10 +739,10 @@ int launch_copy_rows(int64_t n, int64_t nrhs, const double *T, int64_t ldt, doub
 }
 
 int launch_trsv(int64_t n, int64_t nrhs, const double *LU, int64_t lda, double *X, int64_t ldx, int32_t *sync,
-                hipStream_t st, int spin_limit, const int32_t *rm)
+                double *Y, hipStream_t st, int spin_limit, const int32_t *rm)
 {
     if (n <= 0 || nrhs <= 0) return CFX_OK;
-    if (nrhs == 1 && sync && (ldx == 1 || n == 1)) return trsv_one(n, LU, lda, rm, X, sync, spin_limit, st);
+    if (nrhs == 1 && sync && Y && (ldx == 1 || n == 1)) return trsv_one(n, LU, lda, rm, X, Y, sync, spin_limit, st);
     if (nrhs == 1) return trsv_impl<1>(n, 1, LU, lda, rm, X, ldx, st);
     return trsv_impl<16>(n, (int)nrhs, LU, lda, rm, X, ldx, st);
 }
@@ -690,7 +760,10 @@ int launch_getrs(int64_t n, int64_t nrhs, const double *LU, int64_t lda, const i
         pb = perm;
     }
     if ((rc = launch_gather_rows(n, nrhs, B, ldb, pb, tmp, nrhs, st))) return rc;
-    if ((rc = launch_trsv(n, nrhs, LU, lda, tmp, nrhs, sync, st, spin_limit, rm))) return rc;
+    // one right-hand side: the second n doubles of tmp are the solve's
+    // intermediate vector
+    if ((rc = launch_trsv(n, nrhs, LU, lda, tmp, nrhs, sync, nrhs == 1 ? tmp + n : nullptr, st, spin_limit, rm)))
+        return rc;
     return launch_copy_rows(n, nrhs, tmp, nrhs, B, ldb, st);
 }
 

@@ -220,7 +220,7 @@ size_t ir_vec_bytes(int64_t n, int restart)
     const size_t vec = ((size_t)n * sizeof(double) + 255) & ~(size_t)255;
     const size_t small = (((size_t)kDotBlocks * (restart + 3) + 8 * (restart + 3)) * sizeof(double) + 255) &
                          ~(size_t)255;
-    return vec * (7 + (size_t)restart + 1) + small + kTrsvSyncBytes;
+    return vec * (8 + (size_t)restart + 1) + small + kTrsvSyncBytes;
 }
 
 IrVectors carve_ir(void *base, int64_t n, int restart)
@@ -237,6 +237,7 @@ IrVectors carve_ir(void *base, int64_t n, int restart)
     v.z = reinterpret_cast<double *>(p); p += vec;
     v.rowabs = reinterpret_cast<double *>(p); p += vec;
     v.tmp = reinterpret_cast<double *>(p); p += vec;
+    v.ys = reinterpret_cast<double *>(p); p += vec;
     v.V = reinterpret_cast<double *>(p); p += vec * ((size_t)restart + 1);
     v.ldv = (int64_t)(vec / sizeof(double));
     v.partial = reinterpret_cast<double *>(p);
@@ -265,7 +266,7 @@ int apply_m(const Ctx &c, const double *src, double *dst)
 {
     int rc = launch_gather_rows(c.v.n, 1, src, 1, c.perm, dst, 1, c.st);
     if (rc) return rc;
-    return launch_trsv(c.v.n, 1, c.F, c.ldf, dst, 1, c.v.sync, c.st, c.spin_limit);
+    return launch_trsv(c.v.n, 1, c.F, c.ldf, dst, 1, c.v.sync, c.v.ys, c.st, c.spin_limit);
 }
 
 // out[0..nv) = V_k . w, k < nv (device result at `out`)

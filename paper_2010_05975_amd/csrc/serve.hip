@@ -375,7 +375,7 @@ int run_single(cfx_server *S, cfx_handle *h, hipStream_t st, Job *j)
         for (;;) {
             SRV_CHECK(launch_copy_rows(n, 1, r.B + c, r.ldb, v.b, 1, st));
             SRV_CHECK(launch_gather_rows(n, 1, v.b, 1, f->perm, v.x, 1, st));
-            SRV_CHECK(launch_trsv(n, 1, f->F, n, v.x, 1, v.sync, st, p.spin_limit));
+            SRV_CHECK(launch_trsv(n, 1, f->F, n, v.x, 1, v.sync, v.ys, st, p.spin_limit));
             ir = IrResult{};
             SRV_CHECK(ir_refine(r.A, r.lda, f->F, n, f->perm, v, p, &ir, st));
             if (ir.converged || f->prec == CFX_PREC_FP64) break;

@@ -352,6 +352,42 @@ def test_getrs_one_rhs_repeat_is_deterministic(cfx):
     assert O.eta(A, outs[0], B[:, :1]) <= 1e-14
 
 
+@pytest.mark.parametrize("kind", ["zeros", "zero_pivot"])
+def test_getrs_one_rhs_degenerate_values(cfx, kind):
+    """The one-right-hand-side solve's fast substitution lets a row that is
+    already final take v - 0 * x; when a result of a block is zero or not
+    finite the block is solved again keeping each row's value at its own
+    step.  Exact zeros in the solution, and a zero on U's diagonal (the rows
+    solved before it must stay finite and correct), take that path; both
+    are compared with the oracle.  Factors: unit L = I, U upper triangular,
+    no interchanges."""
+    n = 300
+    say(f"getrs degenerate values {kind} n={n}")
+    rng = np.random.default_rng(91)
+    LU = np.triu(rng.standard_normal((n, n))) + np.diag(np.full(n, 4.0))
+    ipiv = np.arange(n, dtype=np.int32)
+    if kind == "zeros":
+        x = rng.standard_normal(n)
+        x[n // 2:] = 0.0
+        b = np.triu(LU) @ x            # rows n/2.. of b are exactly zero
+    else:
+        LU[n // 2, n // 2] = 0.0
+        b = rng.standard_normal(n)
+    B = b.reshape(n, 1)
+    Xref = O.getrs(LU, ipiv, B)
+    dB = to_dev(B)
+    cfx.getrs(to_dev(LU), torch.from_numpy(ipiv).cuda(), dB)
+    assert cfx.getrs_check() == 0
+    X = dB.cpu().numpy()
+    fin = np.isfinite(Xref)
+    assert np.array_equal(fin, np.isfinite(X))
+    if kind == "zero_pivot":
+        assert fin[n // 2 + 1:].all() and not fin[: n // 2 + 1].any()
+    np.testing.assert_allclose(X[fin], Xref[fin], rtol=1e-10, atol=1e-12 * np.abs(Xref[fin]).max())
+    if kind == "zeros":
+        assert np.all(X[n // 2:] == 0.0)
+
+
 def _golden(n):
     import os
     import sys
