@@ -667,8 +667,8 @@ def main():
         sys.exit(2)
 
     if args.hw_queues is not None:
-        if not 1 <= args.hw_queues <= 16:
-            raise SystemExit("--hw-queues takes 1..16")
+        if not 1 <= args.hw_queues <= 32:
+            raise SystemExit("--hw-queues takes 1..32")
         os.environ["GPU_MAX_HW_QUEUES"] = str(int(args.hw_queues))
     import torch
     import cfx_inputs as G
