@@ -486,11 +486,10 @@ __global__ __launch_bounds__(256) void trsv_sf_kernel(const double *__restrict__
     // the diagonal block (L: strictly lower; U: strictly upper, its
     // diagonal apart) is staged in LDS before any wait (every load in
     // bounds, so they are all in flight at once); wave 0 takes it into
-    // registers only for the solve, so the registers stay free for the
-    // prefetch ring below.  For U the coefficients above the diagonal are
-    // divided by the diagonal element of their column (the unit triangle
-    // U D^-1), so that no division waits on the previous row in the
-    // substitution.
+    // registers only for the solve.  For U the coefficients above the
+    // diagonal are divided by the diagonal element of their column (the
+    // unit triangle U D^-1), so that no division waits on the previous row
+    // in the substitution.
     double tv[TB * TB / 256];
 #pragma unroll
     for (int rep = 0; rep < TB * TB / 256; ++rep) {
@@ -522,15 +521,17 @@ __global__ __launch_bounds__(256) void trsv_sf_kernel(const double *__restrict__
     const double rhs = ok ? in[gi] : 0.0;
 
     // per row: block sums (16 products each, one lane) accumulated over the
-    // blocks with Neumaier's compensation.  The factor tiles and the
-    // solution values of the next D blocks are requested ahead, so a block
-    // row that runs behind the solved blocks does not pay one memory round
-    // trip per block; a value still marked is loaded again when its block
-    // is reached, until it is not.
-    // The ring of D slots is unrolled by D, so that every slot keeps its
+    // blocks with Neumaier's compensation.  The factor tile and the
+    // solution values of block i + D are requested when block i has been
+    // applied (a ring of D slots, unrolled by D so that every slot keeps its
     // registers and the wait before a slot's use covers only that slot's
-    // loads, not those issued after it.
-    constexpr int D = 3;
+    // loads); a value still marked is loaded again when its block is
+    // reached, until it is not.  D = 1 measured fastest (deeper rings, 2, 3
+    // and 4 slots: 5.0, 5.4 and 5.6 ms against 4.9 ms for the solve at
+    // N = 32768; they keep more streaming loads in flight beside the polls
+    // and stores of the chain), and a row behind the head still catches up
+    // faster than the chain moves.
+    constexpr int D = 1;
     double acc = 0.0, cmp = 0.0;
     double lq[D][16];
     double xq[D];
