@@ -274,7 +274,9 @@ int cfx_getrs_masked(cfx_handle *h, int64_t n, int64_t nrhs, const double *LU,
                      void *stream);
 
 /* Scratch and ordering of cfx_getrs: the permutation and the gathered
- * right-hand sides live in a device buffer owned by the handle, grown with
+ * right-hand sides (with one right-hand side, also the solve's intermediate
+ * vector: n x max(nrhs, 2) doubles) live in a device buffer owned by the
+ * handle, grown with
  * hipMalloc when a call needs more (hipFree of the old one waits for the
  * device).  Calls on one handle are ordered on the device through an event
  * of the handle, whatever streams they are issued on.
@@ -347,7 +349,8 @@ typedef struct {
 } cfx_ir_report;
 
 /* Workspace bytes of cfx_gesv_ir (host pointer `bytes`): an n x n factor
- * copy, pivots, the getrf workspace and (gmres_restart + 8) n-vectors. */
+ * copy, pivots, the getrf workspace and (gmres_restart + 9) n-vectors (one
+ * of them the intermediate vector of the one-launch triangular solves). */
 int cfx_gesv_ir_buffer_size(cfx_handle *h, int64_t n, int64_t nrhs,
                             const cfx_ir_opts *opts, size_t *bytes);
 
