@@ -101,6 +101,41 @@ __global__ __launch_bounds__(256) void gemv_kernel(const double *__restrict__ A,
     }
 }
 
+// out_i = A_i x in plain FP64, one wavefront per row, for rows and x
+// aligned to 16 bytes: each lane loads two consecutive elements at a time
+// and keeps four loads of the row in flight (four partial sums), so that
+// more of the row is requested at once than with one 8-byte load per lane.
+__global__ __launch_bounds__(256) void gemv_plain_kernel(const double *__restrict__ A, int64_t lda, int64_t n,
+                                                         const double *__restrict__ x, double *__restrict__ out)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= n) return;
+    const double2 *row = reinterpret_cast<const double2 *>(A + i * lda);
+    const double2 *x2 = reinterpret_cast<const double2 *>(x);
+    const int64_t n2 = n / 2;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    int64_t j = lane;
+    for (; j + 192 < n2; j += 256) {
+        double2 a[4], b[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            a[q] = row[j + 64 * q];
+            b[q] = x2[j + 64 * q];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s[q] += a[q].x * b[q].x + a[q].y * b[q].y;
+    }
+    for (; j < n2; j += 64) {
+        const double2 a = row[j], b = x2[j];
+        s[0] += a.x * b.x + a.y * b.y;
+    }
+    if ((n & 1) && lane == 0) s[1] += A[i * lda + n - 1] * x[n - 1];
+    double t = (s[0] + s[1]) + (s[2] + s[3]);
+    for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off);
+    if (lane == 0) out[i] = t;
+}
+
 // partial[k * nblk + blk] = sum over this block's slice of V_k . w
 // (V_k = V + k * ldv), k < nv; fixed reduction order.
 __global__ __launch_bounds__(256) void dots_kernel(const double *__restrict__ V, int64_t ldv, int nv,
@@ -197,8 +232,11 @@ unsigned blocks_of(int64_t n, int per) { return (unsigned)((n + per - 1) / per);
 int launch_gemv(const double *A, int64_t lda, int64_t n, const double *x, double *y, hipStream_t st)
 {
     if (n <= 0) return CFX_OK;
-    hipLaunchKernelGGL(gemv_kernel<false>, dim3(blocks_of(n, 4)), dim3(256), 0, st, A, lda, n, x,
-                       (const double *)nullptr, y, (double *)nullptr);
+    if ((((uintptr_t)A | (uintptr_t)x) & 15) == 0 && lda % 2 == 0)
+        hipLaunchKernelGGL(gemv_plain_kernel, dim3(blocks_of(n, 4)), dim3(256), 0, st, A, lda, n, x, y);
+    else
+        hipLaunchKernelGGL(gemv_kernel<false>, dim3(blocks_of(n, 4)), dim3(256), 0, st, A, lda, n, x,
+                           (const double *)nullptr, y, (double *)nullptr);
     CFX_HIP(hipGetLastError());
     return CFX_OK;
 }
