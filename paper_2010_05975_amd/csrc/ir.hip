@@ -52,6 +52,25 @@ __global__ __launch_bounds__(256) void gemv_kernel(const double *__restrict__ A,
     if constexpr (RES) {
         double s0 = 0.0, c0 = 0.0, s1 = 0.0, c1 = 0.0, ab = 0.0;
         int64_t j = lane;
+        if (((((uintptr_t)row) | (uintptr_t)x) & 15) == 0) {
+            // 16-byte loads: the two elements of a pair go to the two sums
+            const double2 *row2 = reinterpret_cast<const double2 *>(row);
+            const double2 *x2 = reinterpret_cast<const double2 *>(x);
+            int64_t j2 = lane;
+#pragma unroll 4
+            for (; j2 < n / 2; j2 += 64) {
+                const double2 a = row2[j2], xv = x2[j2];
+                const double p0 = a.x * xv.x, p1 = a.y * xv.y;
+                const double e0 = fma(a.x, xv.x, -p0), e1 = fma(a.y, xv.y, -p1);
+                double t0, t1;
+                two_sum(s0, p0, s0, t0);
+                two_sum(s1, p1, s1, t1);
+                c0 += t0 + e0;
+                c1 += t1 + e1;
+                ab += fabs(a.x) + fabs(a.y);
+            }
+            j = (n & 1) && lane == 0 ? n - 1 : n;   // the odd last element
+        }
         for (; j + 64 < n; j += 128) {
             const double a0 = row[j], a1 = row[j + 64];
             const double p0 = a0 * x[j], p1 = a1 * x[j + 64];
