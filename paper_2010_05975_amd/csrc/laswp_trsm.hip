@@ -45,9 +45,15 @@ __global__ __launch_bounds__(256) void laswp_kernel(double *A, int64_t lda, int6
                                                     int vb, const int32_t *plan, const double *lu00,
                                                     int64_t c0, int64_t split, int64_t skip)
 {
+    // the plan's row indices are staged in LDS first, so that the row loads
+    // below are all in flight together instead of each waiting for its index
+    __shared__ int32_t s_src[2 * kMaxV], s_dst[2 * kMaxV];
     const int np = plan[0];
-    const int32_t *dst = plan + 1;
-    const int32_t *src = plan + 1 + 2 * kMaxV;
+    for (int q = threadIdx.x; q < np; q += 256) {
+        s_dst[q] = plan[1 + q];
+        s_src[q] = plan[1 + 2 * kMaxV + q];
+    }
+    __syncthreads();
     const int64_t sp = (int64_t)blockIdx.x * SW_COLS + (threadIdx.x & (SW_COLS - 1));
     const int64_t c = c0 + sp + (sp >= split ? skip : 0);
     const int q0 = threadIdx.x / SW_COLS;
@@ -56,14 +62,18 @@ __global__ __launch_bounds__(256) void laswp_kernel(double *A, int64_t lda, int6
 #pragma unroll
     for (int s = 0; s < SW_SLOTS; ++s) {
         const int q = q0 + s * (256 / SW_COLS);
-        if (q < np && c < n) vals[s] = A[(int64_t)src[q] * lda + c];
+        if (q < np && c < n) vals[s] = A[(int64_t)s_src[q] * lda + c];
     }
+    // one wait for every row load, on every path: the stores below then
+    // need no wait of their own (a store's wait would also wait for the
+    // stores before it)
+    __builtin_amdgcn_s_waitcnt(0x0F70);           // vmcnt(0)
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < SW_SLOTS; ++s) {
         const int q = q0 + s * (256 / SW_COLS);
         if (q < np && c < n) {
-            const int64_t d = dst[q];
+            const int64_t d = s_dst[q];
             if (!(in_panel && d < k + vb)) A[d * lda + c] = vals[s];
         }
     }
