@@ -898,6 +898,7 @@ __global__ __launch_bounds__(256) void tslu_gather_kernel(NodeArgs p, int tiles_
 {
     __builtin_amdgcn_s_setprio(3);      // critical path (see tslu_panel_kernel)
     __shared__ double tile[64][65];
+    __shared__ int64_t prow[64];        // physical rows of the tile's 64 rows
     const int per_node = tiles_r * tiles_c;
     const int node = blockIdx.x / per_node;
     const int t = blockIdx.x - node * per_node;
@@ -908,18 +909,23 @@ __global__ __launch_bounds__(256) void tslu_gather_kernel(NodeArgs p, int tiles_
     if (r0 >= r || c0 >= p.vb) return;
     const int tid = threadIdx.x;
     double *Sn = p.S + (size_t)node * p.s_node;
+    // the rows' indices (candidate lists, row map) are looked up once per
+    // row and shared through LDS, so that the value loads below are all in
+    // flight together instead of each waiting for its row's index
+    if (tid < 64 && r0 + tid < r) {
+        const int g = node_gid(p, nr, r0 + tid);
+        prow[tid] = p.rm ? (int64_t)p.rm[g] : (int64_t)(g - p.row0);
+    }
+    __syncthreads();
     constexpr int PER = 64 * 64 / 256;
     double v[PER];
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const int e = tid + k * 256, i = e >> 6, c = e & 63;
-        if (r0 + i < r && c0 + c < p.vb) {
-            const int g = node_gid(p, nr, r0 + i);
-            const int64_t pr = p.rm ? (int64_t)p.rm[g] : (int64_t)(g - p.row0);
-            v[k] = p.W[pr * p.ldw + c0 + c];
-        } else {
+        if (r0 + i < r && c0 + c < p.vb)
+            v[k] = p.W[prow[i] * p.ldw + c0 + c];
+        else
             v[k] = 0.0;
-        }
     }
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
