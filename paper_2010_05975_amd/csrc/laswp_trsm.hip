@@ -151,11 +151,13 @@ __device__ __forceinline__ double quad_bcast(double v)
 // U(r, c) of the solve: U00 for L21 (mode 0), L00^T for U12 (mode 1), from
 // the panel's diagonal block (rows k.. through the row map, columns k..).
 // Only r <= c is ever read.
+// rmk: the panel rows' physical rows (rm[k + i], staged in LDS), or null.
+__device__ __forceinline__ int64_t pk(const int32_t *rmk, int64_t k, int i) { return rmk ? (int64_t)rmk[i] : k + i; }
 template <int MODE>
-__device__ __forceinline__ double uval(const double *A, int64_t lda, const int32_t *rm, int64_t k, int r, int c)
+__device__ __forceinline__ double uval(const double *A, int64_t lda, const int32_t *rmk, int64_t k, int r, int c)
 {
-    if constexpr (MODE == 0) return A[phys(rm, k + r) * lda + k + c];
-    else return r == c ? 1.0 : A[phys(rm, k + c) * lda + k + r];
+    if constexpr (MODE == 0) return A[pk(rmk, k, r) * lda + k + c];
+    else return r == c ? 1.0 : A[pk(rmk, k, c) * lda + k + r];
 }
 
 // One workgroup: rows rbase .. rbase+64 (below rend) of X.  LDS:
@@ -163,9 +165,9 @@ __device__ __forceinline__ double uval(const double *A, int64_t lda, const int32
 //   Sb  per wavefront: the block's rows (inputs, then the solution)
 //   Sg  per wavefront: X_{<b} U_{<b,b} of the block
 template <int MODE>
-__device__ __forceinline__ void trsm_body(double *A, int64_t lda, const int32_t *rm, int64_t k, int vb,
-                                          int64_t rbase, int64_t rend, double *Us, double (*Sb)[TSW][ULD],
-                                          double (*Sg)[TSW][ULD])
+__device__ __forceinline__ void trsm_body(double *A, int64_t lda, const int32_t *rm, const int32_t *rmk, int64_t k,
+                                          int vb, int64_t rbase, int64_t rend, double *Us,
+                                          double (*Sb)[TSW][ULD], double (*Sg)[TSW][ULD])
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lk = lane >> 4;
@@ -176,7 +178,7 @@ __device__ __forceinline__ void trsm_body(double *A, int64_t lda, const int32_t 
     const int64_t xrow = MODE == 0 ? phys(rm, k + vb + (rok ? row : 0)) : 0;
     auto xaddr = [&](int c) -> double * {
         if constexpr (MODE == 0) return A + xrow * lda + k + c;
-        else return A + phys(rm, k + c) * lda + k + vb + row;
+        else return A + pk(rmk, k, c) * lda + k + vb + row;
     };
     // xa[s] = X[row][4s + lk]: the A operand layout of v_mfma_f64_16x16x4f64
     // (lane l holds row l%16, column l/16 of each 16 x 4 slice)
@@ -205,7 +207,7 @@ __device__ __forceinline__ void trsm_body(double *A, int64_t lda, const int32_t 
         for (int i = 0; i < NPRE; ++i) {
             int r, c;
             elem(i, r, c);
-            pre[i] = (r < krf && c < bcf && r <= c0f + c) ? uval<MODE>(A, lda, rm, k, r, c0f + c) : 0.0;
+            pre[i] = (r < krf && c < bcf && r <= c0f + c) ? uval<MODE>(A, lda, rmk, k, r, c0f + c) : 0.0;
         }
     };
     fetch_u(0);
@@ -303,6 +305,16 @@ __device__ __forceinline__ void trsm_body(double *A, int64_t lda, const int32_t 
     });
 }
 
+// With a row map, the panel rows' physical rows (rm[k .. k + vb)) are read
+// once into LDS, so that the solve's loads of the panel rows do not each
+// wait for a row-map lookup.
+__device__ __forceinline__ void stage_panel_rows(const int32_t *rm, int64_t k, int vb, int32_t *rmk)
+{
+    if (!rm) return;
+    for (int i = threadIdx.x; i < vb; i += blockDim.x) rmk[i] = rm[k + i];
+    __syncthreads();
+}
+
 // Rows i0 .. i1 of one solve.
 template <int MODE>
 __global__ __launch_bounds__(256) void trsm_kernel(double *A, int64_t lda, const int32_t *rm, int64_t k, int vb,
@@ -311,7 +323,9 @@ __global__ __launch_bounds__(256) void trsm_kernel(double *A, int64_t lda, const
     __shared__ double Us[kMaxV * ULD];
     __shared__ double Sb[4][TSW][ULD];
     __shared__ double Sg[4][TSW][ULD];
-    trsm_body<MODE>(A, lda, rm, k, vb, i0 + (int64_t)blockIdx.x * TSR, i1, Us, Sb, Sg);
+    __shared__ int32_t rmk[kMaxV];
+    stage_panel_rows(rm, k, vb, rmk);
+    trsm_body<MODE>(A, lda, rm, rm ? rmk : nullptr, k, vb, i0 + (int64_t)blockIdx.x * TSR, i1, Us, Sb, Sg);
 }
 
 // Both solves in one launch: workgroups 0 .. g0 take the m rows of L21,
@@ -322,10 +336,13 @@ __global__ __launch_bounds__(256) void trsm_pair_kernel(double *A, int64_t lda, 
     __shared__ double Us[kMaxV * ULD];
     __shared__ double Sb[4][TSW][ULD];
     __shared__ double Sg[4][TSW][ULD];
+    __shared__ int32_t rmk[kMaxV];
+    stage_panel_rows(rm, k, vb, rmk);
+    const int32_t *rk = rm ? rmk : nullptr;
     if ((int)blockIdx.x < g0)
-        trsm_body<0>(A, lda, rm, k, vb, (int64_t)blockIdx.x * TSR, m, Us, Sb, Sg);
+        trsm_body<0>(A, lda, rm, rk, k, vb, (int64_t)blockIdx.x * TSR, m, Us, Sb, Sg);
     else
-        trsm_body<1>(A, lda, rm, k, vb, (int64_t)(blockIdx.x - g0) * TSR, n1, Us, Sb, Sg);
+        trsm_body<1>(A, lda, rm, rk, k, vb, (int64_t)(blockIdx.x - g0) * TSR, n1, Us, Sb, Sg);
 }
 
 __global__ void set_int_kernel(int32_t *p, int32_t v) { *p = v; }
